@@ -1,0 +1,172 @@
+/*
+ * gbs.h -- C ABI of the MI355X (gfx950) library for batched Gaussian-boson-
+ * sampling probabilities and hafnians.
+ *
+ * What it computes (Wu, Cheng, Zhang, Yung, Sun, arXiv:1908.10070):
+ *
+ *   Haf(V) = sum over perfect matchings sigma of [n] of prod_j V(sigma_{2j-1}, sigma_{2j})
+ *            (Sec. II C, Eq. HafMatch), evaluated with the power-trace formula the paper
+ *            cites for its O(n^3 2^(n/2)) hafnian: with k = n/2, pairs (2i, 2i+1) and X the
+ *            within-pair row swap,
+ *              Haf(A) = sum_{Z subset of [k]} (-1)^(k-|Z|) [lambda^k] det(I - lambda X A_Z)^(-1/2).
+ *
+ *   p(x)   = |Haf(B_x)|^2 / (prod_j s_j! * prod_i cosh r_i),   B = U diag(tanh r_i) U^t,
+ *            B_x(i, j) = B(x_i, x_j)        (Eq. ProOri with W = U U^t, Sec. II C; the
+ *            position-sequence matrix W_x of Sec. III B and App. B). For identical r_i this is
+ *            exactly Eq. ProOri; per-mode r_i are the natural generalisation.
+ *
+ * Conventions
+ *   - gbs_c128 is bit-identical to C99 double _Complex, torch.complex128, hipDoubleComplex.
+ *   - "_dev" pointers are device memory on the context's device; "_host" pointers are host memory.
+ *   - Every entry point returns an int status (GBS_OK on success). Nothing throws or aborts
+ *     across the ABI. On failure no work has been enqueued unless the status is GBS_EHIP.
+ *   - Compute calls enqueue on `stream` (a hipStream_t passed as void*; NULL = legacy default
+ *     stream) and return at once; outputs are valid once the stream reaches the work.
+ *     Host arrays are read before the call returns and may be reused afterwards.
+ *   - Device inputs must stay alive and unmodified until the stream reaches the work.
+ *   - A context is not thread-safe: use one per host thread (and per stream if work on
+ *     several streams must overlap). Calls on one context serialise on its internal staging.
+ *   - n (photon number, matrix size) must satisfy 0 <= n <= GBS_N_MAX. n = 0 gives Haf = 1;
+ *     odd n gives Haf = 0 and p = 0 (P_n = 0 for odd n, Eq. Eqdistribution).
+ *   - Input matrices are assumed complex symmetric; diagonal entries are never used
+ *     (matchings pair distinct indices), so they may hold anything finite.
+ *   - Non-finite inputs propagate as NaN; that is not an error.
+ */
+#ifndef GBS_H_
+#define GBS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GBS_N_MAX 48
+
+typedef struct {
+  double re, im;
+} gbs_c128;
+
+/* Compensated partial sum of subset terms: value = (s_re + c_re) + i (s_im + c_im). */
+typedef struct {
+  double s_re, s_im, c_re, c_im;
+} gbs_partial;
+
+typedef struct gbs_ctx gbs_ctx;
+typedef struct gbs_state gbs_state;
+
+enum {
+  GBS_OK = 0,
+  GBS_EINVAL = 1,        /* null pointer, negative size, malformed offsets */
+  GBS_ERANGE = 2,        /* a mode outside [0, m), n > GBS_N_MAX, subset range outside [0, 2^(n/2)-1] */
+  GBS_ENOMEM = 3,        /* caller workspace too small for the plan, or device allocation failed */
+  GBS_EHIP = 4,          /* a HIP runtime call failed; gbs_last_error() has the text */
+  GBS_EUNSUPPORTED = 5   /* device is not gfx950 */
+};
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on `device`.
+ * workspace_dev/workspace_bytes: optional caller-owned device buffer the library carves its
+ *   scratch (plan, staged patterns, partial sums, counters) from. Pass NULL/0 to let the
+ *   library allocate (and grow) its own device workspace. With a caller buffer, calls whose
+ *   plan does not fit return GBS_ENOMEM and enqueue nothing.
+ * The context also holds pinned host staging buffers, the per-size chain programs, the
+ * launch-shape table (see gbs_ctx_set_tuning) and cached HIP graphs. */
+int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_ctx** out);
+int gbs_ctx_destroy(gbs_ctx* ctx);
+
+/* Static description of a status code. */
+const char* gbs_status_str(int status);
+/* Detail text of the last failure on this context (empty string if none). Valid until the next call. */
+const char* gbs_last_error(const gbs_ctx* ctx);
+
+/* Execution options.
+ *   use_graph:   1 = capture the batch's kernels in a HIP graph and replay it (cached per launch
+ *                shape); 0 = launch eagerly.
+ *   persistent:  1 = persistent work-queue kernels (grid sized to the device, items taken from an
+ *                atomic counter); 0 = one workgroup per work item.
+ * Defaults: use_graph = 1, persistent = 1. */
+int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
+
+/* Launch-shape table (what the autotuner writes): for photon number n, the number of subsets per
+ * work item for the small-subset engine (subsets with 2|Z| <= 16) and for the large-subset engine.
+ * chunk <= 0 restores the built-in default. Results depend only on these values and n, never on
+ * how patterns are batched together. */
+int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chunk_large);
+int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int64_t* chunk_large);
+
+/* Algorithmic FP64 flop count of one hafnian of size n (per-subset matrix products, trace inner
+ * products and the coefficient recursion of the power-trace method as the library schedules it;
+ * a complex multiply-add counts 8). Padding and bookkeeping are not counted. */
+double gbs_haf_flops(int32_t n);
+
+/* ---------------------------------------------------------------- hafnians */
+
+/* Hafnians of `batch` matrices of size n x n, row-major complex128, matrix b starting at
+ * A_dev + b * stride_elems (stride_elems >= n*n). haf_out_dev[b] receives Haf(A_b).
+ * A_dev may be NULL when n = 0 (every result is 1). */
+int haf_batch(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t batch, int64_t stride_elems,
+              gbs_c128* haf_out_dev, void* stream);
+
+/* Hafnians of matrices of mixed sizes: matrix b is n_host[b] x n_host[b], row-major, starting at
+ * A_dev + elem_off_host[b]. */
+int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_off_host,
+                     const int32_t* n_host, int64_t batch, gbs_c128* haf_out_dev, void* stream);
+
+/* ------------------------------------------------------------ GBS state */
+
+/* Build a resident GBS state from an m x m unitary U (device, row-major complex128) and per-mode
+ * squeezing parameters r (host, m doubles). A kernel forms B = U diag(tanh r_i) U^t and the
+ * prefactor 1 / prod_i cosh r_i on the device (Sec. II C: W = U U^t; Eq. ProOri). The state owns
+ * its device copy of B (m*m complex128) and of U; `U_dev` may be freed once the stream is synced.
+ * The state is bound to the context's device and may be used with any context on that device. */
+int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const double* r_host,
+                     void* stream, gbs_state** out);
+int gbs_state_destroy(gbs_state* state);
+/* Device pointer to the state's B (m x m row-major complex128), and m / the prefactor (host copy,
+ * valid after the creating stream has been synced). */
+int gbs_state_info(const gbs_state* state, const gbs_c128** B_dev, int32_t* m, double* prefactor);
+/* Copy the state's B (m*m complex128) into caller device memory dst_dev, enqueued on `stream`. */
+int gbs_state_copy_B(const gbs_state* state, gbs_c128* dst_dev, void* stream);
+
+/* ------------------------------------------------------------ probabilities */
+
+/* Probabilities of `batch` output patterns. Pattern b is the mode list (position sequence x)
+ * modes_host[offsets_host[b] .. offsets_host[b+1]), modes in [0, m), repeats allowed (collisions
+ * give the prod s_j! divisor), order irrelevant (App. B). offsets_host has batch+1 entries,
+ * offsets_host[0] = 0 and non-decreasing.
+ * prob_out_dev[b] = |Haf(B_x)|^2 / (prod_j s_j! prod_i cosh r_i); haf_out_dev (nullable)
+ * receives Haf(B_x). */
+int gbs_prob_batch(gbs_ctx* ctx, const gbs_state* state, const int32_t* modes_host,
+                   const int64_t* offsets_host, int64_t batch, double* prob_out_dev,
+                   gbs_c128* haf_out_dev, void* stream);
+
+/* ------------------------------------------- split evaluation (for schedulers) */
+
+/* The 2^k - 1 non-empty pair subsets Z of a size-n pattern (k = n/2) are ordered by |Z| and, within
+ * one size, by increasing bitmask. gbs_subset_count(n) = 2^(n/2) - 1 for even n (0 for odd n or n=0). */
+int64_t gbs_subset_count(int32_t n);
+
+/* Partial sums of the subset terms over index ranges [lo_host[b], hi_host[b]) of pattern b
+ * (0 <= lo <= hi <= gbs_subset_count(n)). partials_dev[b] receives the compensated partial.
+ * Summing the partials of consecutive ranges covering [0, count) with gbs_finalize gives the
+ * pattern's hafnian. Patterns as in gbs_prob_batch. */
+int gbs_prob_slices(gbs_ctx* ctx, const gbs_state* state, const int32_t* modes_host,
+                    const int64_t* offsets_host, const int64_t* lo_host, const int64_t* hi_host,
+                    int64_t batch, gbs_partial* partials_dev, void* stream);
+
+/* Combine partials: pattern b owns partials_dev[part_off_host[b] .. part_off_host[b+1]), summed in
+ * that order with compensation. n_host[b] is its photon number, sfact_host[b] its prod_j s_j!.
+ * haf_out_dev[b] = sum (1 for n = 0, 0 for odd n); prob_out_dev[b] = prefactor |haf|^2 / sfact
+ * (prefactor taken from `state`; prob_out_dev may be NULL, then state may be NULL). */
+int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partials_dev,
+                 const int64_t* part_off_host, const int32_t* n_host, const double* sfact_host,
+                 int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBS_H_ */

@@ -1,0 +1,71 @@
+"""Build libgbs.so (HIP kernels + host runtime, C ABI) for gfx950 with hipcc, in-tree.
+
+Usage: python -m paper_1908_10070_amd.csrc.build [--force]
+"""
+import os
+import pathlib
+import shutil
+import subprocess
+import sys
+import tempfile
+
+HERE = pathlib.Path(__file__).resolve().parent
+PKG = HERE.parent
+ROOT = PKG.parent
+INCLUDE = ROOT / "include"
+OUT = PKG / "libgbs.so"
+
+SOURCES = ["gbs_kernels.hip", "gbs_runtime.cpp", "gbs_chain.cpp"]
+HEADERS = ["gbs_internal.h"]
+
+ARCH = "gfx950"
+COMMON = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # packed FP32 instructions stay off in device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    f"-I{INCLUDE}", f"-I{HERE}",
+]
+
+
+def hipcc() -> str:
+    p = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    return p
+
+
+def _stale() -> bool:
+    if not OUT.exists():
+        return True
+    t = OUT.stat().st_mtime
+    deps = [HERE / s for s in SOURCES + HEADERS] + [INCLUDE / "gbs.h"]
+    return any(d.stat().st_mtime > t for d in deps)
+
+
+def build(force: bool = True, verbose: bool = False) -> pathlib.Path:
+    """Compile every source and link libgbs.so. Always recompiles when force is true."""
+    if not force and not _stale():
+        return OUT
+    with tempfile.TemporaryDirectory(prefix="gbs_build_") as td:
+        objs = []
+        for src in SOURCES:
+            obj = pathlib.Path(td) / (src + ".o")
+            lang = ["-x", "hip"] if src.endswith(".hip") else []
+            cmd = [hipcc(), *COMMON, *lang, "-c", str(HERE / src), "-o", str(obj)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed on {src}")
+            objs.append(str(obj))
+        tmp = OUT.with_name(OUT.name + f".tmp{os.getpid()}")
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *objs]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("link of libgbs.so failed")
+        os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(force=True, verbose="-v" in sys.argv))

@@ -1,0 +1,96 @@
+// Internal types shared by the HIP kernels and the host runtime of libgbs.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "gbs.h"
+
+namespace gbs {
+
+constexpr int kMaxK = GBS_N_MAX / 2;  // largest pair count k = n/2
+constexpr int kMaxOps = 64;           // ops in one chain program
+constexpr int kMaxSlots = 6;          // LDS matrix slots a chain program may use
+constexpr int kBatchG = 16;           // subsets whose traces are buffered before the coefficient step
+constexpr int kThreads = 256;         // workgroup size of the subset engine (4 waves)
+constexpr int kSmallD = 16;           // subsets with d = 2|Z| <= 16 run one per wave
+
+enum OpType : uint8_t { OP_MUL = 1, OP_TDIAG = 2, OP_TPAIR = 3 };
+
+// One step of the per-subset program. MUL: slot x = slot a * slot b (x may equal a dying operand).
+// TDIAG: t_x = tr(slot a). TPAIR: t_x = tr(slot a * slot b), read as sum_{i,c} a[i][c] b[c][i].
+struct Op {
+  uint8_t type, x, a, b;
+};
+
+// Power-trace schedule for one k: the powers of M_Z to form (an addition chain) and, for every
+// j = 1..k, where t_j = tr(M_Z^j) comes from.
+struct ChainProgram {
+  int32_t nops;
+  int32_t nslots;
+  int32_t nmul;
+  int32_t npair;
+  Op ops[kMaxOps];
+};
+
+struct ConstTables {
+  ChainProgram prog[kMaxK + 1];
+  uint64_t binom[kMaxK + 1][kMaxK + 1];  // C(a, b)
+  double inv[kMaxK + 1];                  // 1/q, correctly rounded
+};
+
+// One pattern (a matrix to take the hafnian of).
+struct PatternDesc {
+  int64_t src;      // haf path: element offset of the row-major n x n matrix; prob path: offset into modes
+  int32_t n;
+  int32_t pad;
+};
+
+// A contiguous range [lo, hi) of the canonical subset order of one pattern, summed into one partial.
+struct WorkItem {
+  int64_t lo, hi;
+  int32_t pattern;
+  int32_t partial;
+};
+
+// Arguments of the subset engine.
+struct EngineArgs {
+  const double2* A;           // haf path: matrices (complex128); prob path: B (m x m)
+  const int32_t* modes;       // prob path: staged mode lists; nullptr on the haf path
+  int32_t m;                  // prob path: row length of B
+  int32_t n_items;
+  const PatternDesc* pats;
+  const WorkItem* items;
+  gbs_partial* partials;
+  int32_t* counter;           // work counter for the persistent launch
+  int32_t persistent;
+  int32_t stage_A;            // copy each pattern matrix into LDS (n <= 32)
+  int32_t nmax;               // largest n among the items (LDS sizing)
+  int32_t slot_stride;        // row stride (complex) of a large-subset slot
+  int32_t slot_elems;         // complex elements per large-subset slot
+  int32_t kmax;               // largest k among the items
+  int32_t nslots;             // largest slot count of the chain programs in use
+};
+
+struct FinalizeArgs {
+  const gbs_partial* partials;
+  const int64_t* part_off;    // batch + 1
+  const int32_t* n;           // photon number per pattern
+  const double* sfact;        // prod_j s_j! per pattern (prob path)
+  const double* prefactor;    // 1 / prod cosh r_i (device scalar), or nullptr
+  int64_t batch;
+  double* prob_out;           // nullable
+  double2* haf_out;           // nullable
+  gbs_partial* partial_out;   // nullable: write the combined compensated partial instead
+};
+
+// Host-side launchers (defined in gbs_kernels.hip).
+size_t engine_lds_bytes(int nmax, int kmax, int slot_elems, int stage_A, int nslots);
+int engine_blocks_per_cu(size_t lds_bytes);
+void launch_reset(int32_t* counter, int n, hipStream_t s);
+void launch_engine(const EngineArgs& a, int grid, size_t lds, hipStream_t s);
+void launch_finalize(const FinalizeArgs& a, hipStream_t s);
+void launch_state(const double2* U, const double* r, int m, double2* B, double* prefactor, hipStream_t s);
+int upload_tables(const ConstTables& t);
+
+}  // namespace gbs

@@ -1,0 +1,790 @@
+// Host runtime of libgbs: contexts, resident GBS states, validation, work planning, staging,
+// HIP-graph capture and the C ABI declared in include/gbs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "gbs.h"
+#include "gbs_internal.h"
+
+namespace gbs {
+bool build_chain_program(int k, int slot_limit, ChainProgram* out);
+}
+
+using namespace gbs;
+
+namespace {
+
+constexpr size_t kLdsBudget = 160 * 1024;
+
+// ------------------------------------------------------------------ tables
+
+struct Tables {
+  bool ok = false;
+  int err = GBS_OK;
+  ConstTables host{};
+};
+
+std::mutex g_tab_mu;
+Tables g_tab;
+
+size_t slot_bytes_large(int n) { return sizeof(double) * 2 * (size_t)n * (n + 1); }
+
+// Chain programs for every k, each the cheapest whose LDS slots fit the engine's budget at d = n.
+const Tables& tables() {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  if (g_tab.ok || g_tab.err != GBS_OK) return g_tab;
+  ConstTables& t = g_tab.host;
+  std::memset(&t, 0, sizeof(t));
+  for (int a = 0; a <= kMaxK; ++a) {
+    t.binom[a][0] = 1;
+    for (int b = 1; b <= kMaxK; ++b) t.binom[a][b] = a == 0 ? 0 : t.binom[a - 1][b - 1] + t.binom[a - 1][b];
+  }
+  for (int q = 1; q <= kMaxK; ++q) t.inv[q] = 1.0 / (double)q;
+  for (int k = 1; k <= kMaxK; ++k) {
+    const int n = 2 * k;
+    const size_t fixed = engine_lds_bytes(n, k, 0, n <= 32, 0);
+    int limit = kMaxSlots;
+    while (limit > 1) {
+      size_t small = sizeof(double) * 2 * 4 * (size_t)limit * kSmallD * (kSmallD + 1);
+      size_t large = k > kSmallD / 2 ? limit * slot_bytes_large(n) : 0;
+      if (fixed + std::max(small, large) + 64 <= kLdsBudget) break;
+      --limit;
+    }
+    if (!build_chain_program(k, limit, &t.prog[k])) {
+      g_tab.err = GBS_EUNSUPPORTED;
+      return g_tab;
+    }
+  }
+  g_tab.ok = true;
+  return g_tab;
+}
+
+// ------------------------------------------------------------------ helpers
+
+int64_t subset_count(int n) {
+  if (n <= 0 || (n & 1)) return 0;
+  return (int64_t(1) << (n / 2)) - 1;
+}
+
+// first canonical index of subsets with |Z| = s (s >= 1)
+int64_t size_start(const ConstTables& t, int k, int s) {
+  int64_t g = 0;
+  for (int q = 1; q < s && q <= k; ++q) g += (int64_t)t.binom[k][q];
+  return g;
+}
+
+double flops_subset(const ChainProgram& p, int k, int s) {
+  const double d = 2.0 * s;
+  return p.nmul * 8.0 * d * d * d + p.npair * 8.0 * d * d + 8.0 * k * (k + 1) / 2.0;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ objects
+
+struct GraphKey {
+  std::vector<int64_t> v;
+  bool operator<(const GraphKey& o) const { return v < o.v; }
+};
+
+struct gbs_ctx {
+  int device = 0;
+  int ncu = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  void* pinned[2] = {nullptr, nullptr};
+  size_t pinned_bytes[2] = {0, 0};
+  hipEvent_t pinned_ev[2] = {nullptr, nullptr};
+  bool pinned_used[2] = {false, false};
+  int pin_idx = 0;
+  hipEvent_t done_ev = nullptr;
+  bool done_recorded = false;
+  hipStream_t cap_stream = nullptr;
+  int use_graph = 1;
+  int persistent = 1;
+  std::map<int, std::pair<int64_t, int64_t>> tuning;
+  std::string last_error;
+  std::list<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
+};
+
+struct gbs_state {
+  int device = 0;
+  int m = 0;
+  double2* U = nullptr;
+  double2* B = nullptr;
+  double* r = nullptr;
+  double* pref = nullptr;
+  double pref_host = 0.0;
+  hipEvent_t ready = nullptr;
+};
+
+namespace {
+
+int fail(gbs_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(ctx, GBS_EHIP, "%s: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+void default_chunks(int n, int64_t* cs, int64_t* cl) {
+  // small-subset items: enough subsets to amortise staging; large-subset items: ~100 us of work
+  *cs = 1024;
+  *cl = n <= 32 ? 32 : (n <= 40 ? 16 : 8);
+}
+
+void chunks_for(const gbs_ctx* ctx, int n, int64_t* cs, int64_t* cl) {
+  default_chunks(n, cs, cl);
+  auto it = ctx->tuning.find(n);
+  if (it != ctx->tuning.end()) {
+    if (it->second.first > 0) *cs = it->second.first;
+    if (it->second.second > 0) *cl = it->second.second;
+  }
+}
+
+// Host-side plan of one call, laid out exactly as it is copied into the device workspace.
+struct Plan {
+  std::vector<PatternDesc> pats;
+  std::vector<WorkItem> items;
+  std::vector<int64_t> part_off;  // batch + 1 (finalize groups)
+  std::vector<int32_t> nvec;
+  std::vector<double> sfact;
+  int64_t n_partials = 0;
+  int nmax = 0, kmax = 0, dmax_large = 0, nslots = 1;
+};
+
+// Split [lo, hi) of pattern p into items at the small/large boundary and the chunk sizes.
+void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, std::vector<WorkItem>& large,
+                std::vector<WorkItem>& small, int p, int n, int64_t lo, int64_t hi) {
+  if (hi <= lo) return;
+  const int k = n / 2;
+  int64_t cs, cl;
+  chunks_for(ctx, n, &cs, &cl);
+  const int s_split = std::min(k, kSmallD / 2);
+  const int64_t gsplit = size_start(t, k, s_split + 1);  // first large subset
+  auto emit = [&](int64_t a, int64_t b, int64_t chunk, std::vector<WorkItem>& out, bool is_large) {
+    for (int64_t x = a; x < b; x += chunk) {
+      WorkItem w;
+      w.lo = x;
+      w.hi = std::min(b, x + chunk);
+      w.pattern = p;
+      w.partial = (int32_t)pl.n_partials++;
+      out.push_back(w);
+      if (is_large) pl.dmax_large = std::max(pl.dmax_large, n);
+    }
+  };
+  emit(lo, std::min(hi, gsplit), cs, small, false);
+  emit(std::max(lo, gsplit), hi, cl, large, true);
+  pl.nmax = std::max(pl.nmax, n);
+  pl.kmax = std::max(pl.kmax, k);
+  pl.nslots = std::max(pl.nslots, t.prog[k].nslots);
+}
+
+// Order items so expensive ones start first: large-subset items by decreasing n, then small ones.
+void order_items(Plan& pl, std::vector<WorkItem>& large, std::vector<WorkItem>& small) {
+  auto by_n = [&](std::vector<WorkItem>& v) {
+    std::stable_sort(v.begin(), v.end(), [&](const WorkItem& a, const WorkItem& b) {
+      return pl.pats[a.pattern].n > pl.pats[b.pattern].n;
+    });
+  };
+  by_n(large);
+  by_n(small);
+  pl.items.clear();
+  pl.items.reserve(large.size() + small.size());
+  pl.items.insert(pl.items.end(), large.begin(), large.end());
+  pl.items.insert(pl.items.end(), small.begin(), small.end());
+}
+
+struct Layout {
+  size_t counter, modes, pats, items, part_off, nvec, sfact, partials, total, staged_bytes;
+};
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout_for(const Plan& pl, size_t n_modes) {
+  Layout L;
+  size_t off = 0;
+  L.counter = off;
+  off += 256;
+  const size_t stage_begin = off;
+  L.modes = off;
+  off += al(sizeof(int32_t) * n_modes);
+  L.pats = off;
+  off += al(sizeof(PatternDesc) * pl.pats.size());
+  L.items = off;
+  off += al(sizeof(WorkItem) * pl.items.size());
+  L.part_off = off;
+  off += al(sizeof(int64_t) * pl.part_off.size());
+  L.nvec = off;
+  off += al(sizeof(int32_t) * pl.nvec.size());
+  L.sfact = off;
+  off += al(sizeof(double) * pl.sfact.size());
+  L.staged_bytes = off - stage_begin;
+  L.partials = off;
+  off += al(sizeof(gbs_partial) * (size_t)pl.n_partials);
+  L.total = off;
+  return L;
+}
+
+int ensure_ws(gbs_ctx* ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return GBS_OK;
+  if (!ctx->ws_owned && ctx->ws)
+    return fail(ctx, GBS_ENOMEM, "workspace of %zu bytes is smaller than the %zu the plan needs", ctx->ws_bytes,
+                bytes);
+  size_t nb = std::max(bytes, ctx->ws_bytes * 2);
+  if (ctx->ws) {
+    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+  }
+  if (hipMalloc(&ctx->ws, nb) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(ctx, GBS_ENOMEM, "hipMalloc of %zu workspace bytes failed", nb);
+  }
+  ctx->ws_bytes = nb;
+  ctx->ws_owned = true;
+  return GBS_OK;
+}
+
+int ensure_pinned(gbs_ctx* ctx, int i, size_t bytes) {
+  if (ctx->pinned_bytes[i] >= bytes) return GBS_OK;
+  if (ctx->pinned[i]) {
+    HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[i]));
+    HIPCHK(ctx, hipHostFree(ctx->pinned[i]));
+    ctx->pinned[i] = nullptr;
+    ctx->pinned_bytes[i] = 0;
+  }
+  size_t nb = std::max(bytes, ctx->pinned_bytes[i] * 2);
+  nb = std::max(nb, size_t(1) << 20);
+  HIPCHK(ctx, hipHostMalloc(&ctx->pinned[i], nb, hipHostMallocDefault));
+  ctx->pinned_bytes[i] = nb;
+  return GBS_OK;
+}
+
+// Copy the staged part of the plan to the device, launch the engine and the finalize kernel.
+int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_modes, const double2* A,
+             int32_t m, const double* prefactor_dev, double* prob_out, double2* haf_out, gbs_partial* partial_out,
+             hipStream_t stream) {
+  const Tables& T = tables();
+  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
+  DeviceGuard dg(ctx->device);
+  const Layout L = layout_for(pl, n_modes);
+  int rc = ensure_ws(ctx, L.total);
+  if (rc) return rc;
+  // stage into the next pinned buffer (wait until its previous copy has finished)
+  const int pi = ctx->pin_idx;
+  ctx->pin_idx ^= 1;
+  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
+  rc = ensure_pinned(ctx, pi, L.staged_bytes);
+  if (rc) return rc;
+  unsigned char* h = static_cast<unsigned char*>(ctx->pinned[pi]);
+  const size_t base = L.modes;
+  if (n_modes) std::memcpy(h + (L.modes - base), modes_host, sizeof(int32_t) * n_modes);
+  if (!pl.pats.empty()) std::memcpy(h + (L.pats - base), pl.pats.data(), sizeof(PatternDesc) * pl.pats.size());
+  if (!pl.items.empty()) std::memcpy(h + (L.items - base), pl.items.data(), sizeof(WorkItem) * pl.items.size());
+  std::memcpy(h + (L.part_off - base), pl.part_off.data(), sizeof(int64_t) * pl.part_off.size());
+  if (!pl.nvec.empty()) std::memcpy(h + (L.nvec - base), pl.nvec.data(), sizeof(int32_t) * pl.nvec.size());
+  if (!pl.sfact.empty()) std::memcpy(h + (L.sfact - base), pl.sfact.data(), sizeof(double) * pl.sfact.size());
+
+  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(stream, ctx->done_ev, 0));
+  HIPCHK(ctx, hipMemcpyAsync(ws + base, h, L.staged_bytes, hipMemcpyHostToDevice, stream));
+  HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], stream));
+  ctx->pinned_used[pi] = true;
+
+  EngineArgs ea{};
+  ea.A = A;
+  ea.modes = modes_host ? reinterpret_cast<const int32_t*>(ws + L.modes) : nullptr;
+  ea.m = m;
+  ea.n_items = (int32_t)pl.items.size();
+  ea.pats = reinterpret_cast<const PatternDesc*>(ws + L.pats);
+  ea.items = reinterpret_cast<const WorkItem*>(ws + L.items);
+  ea.partials = reinterpret_cast<gbs_partial*>(ws + L.partials);
+  ea.counter = reinterpret_cast<int32_t*>(ws + L.counter);
+  ea.persistent = ctx->persistent;
+  ea.stage_A = pl.nmax <= 32 ? 1 : 0;
+  ea.nmax = std::max(pl.nmax, 2);
+  ea.kmax = std::max(pl.kmax, 1);
+  ea.slot_stride = pl.dmax_large + 1;
+  ea.slot_elems = pl.dmax_large * (pl.dmax_large + 1);
+  ea.nslots = pl.nslots;
+  const size_t lds = engine_lds_bytes(ea.nmax, ea.kmax, ea.slot_elems, ea.stage_A, ea.nslots);
+  if (lds > kLdsBudget) return fail(ctx, GBS_EUNSUPPORTED, "plan needs %zu bytes of LDS", lds);
+  int grid = ea.n_items;
+  if (ctx->persistent) grid = std::min<int64_t>(ea.n_items, (int64_t)ctx->ncu * engine_blocks_per_cu(lds));
+
+  FinalizeArgs fa{};
+  fa.partials = ea.partials;
+  fa.part_off = reinterpret_cast<const int64_t*>(ws + L.part_off);
+  fa.n = reinterpret_cast<const int32_t*>(ws + L.nvec);
+  fa.sfact = reinterpret_cast<const double*>(ws + L.sfact);
+  fa.prefactor = prefactor_dev;
+  fa.batch = (int64_t)pl.part_off.size() - 1;
+  fa.prob_out = prob_out;
+  fa.haf_out = haf_out;
+  fa.partial_out = partial_out;
+
+  auto enqueue = [&](hipStream_t s) {
+    if (ea.n_items > 0) {
+      if (ctx->persistent) launch_reset(ea.counter, 1, s);
+      launch_engine(ea, grid, lds, s);
+    }
+    if (fa.batch > 0) launch_finalize(fa, s);
+  };
+
+  if (ctx->use_graph) {
+    GraphKey key;
+    key.v = {grid, (int64_t)lds, ea.n_items, ea.nmax, ea.kmax, ea.slot_stride, ea.nslots, ea.stage_A,
+             ea.persistent, (int64_t)(intptr_t)A, (int64_t)(intptr_t)ea.modes, m, fa.batch,
+             (int64_t)(intptr_t)prefactor_dev, (int64_t)(intptr_t)prob_out, (int64_t)(intptr_t)haf_out,
+             (int64_t)(intptr_t)partial_out, (int64_t)(intptr_t)ctx->ws, (int64_t)L.pats, (int64_t)L.items,
+             (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact};
+    hipGraphExec_t exec = nullptr;
+    for (auto itg = ctx->graphs.begin(); itg != ctx->graphs.end(); ++itg)
+      if (!(itg->first < key) && !(key < itg->first)) {
+        exec = itg->second;
+        ctx->graphs.splice(ctx->graphs.begin(), ctx->graphs, itg);
+        break;
+      }
+    if (!exec) {
+      hipGraph_t g = nullptr;
+      HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+      enqueue(ctx->cap_stream);
+      HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &g));
+      hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(ctx, GBS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      ctx->graphs.emplace_front(key, exec);
+      while (ctx->graphs.size() > 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.back().second);
+        ctx->graphs.pop_back();
+      }
+    }
+    HIPCHK(ctx, hipGraphLaunch(exec, stream));
+  } else {
+    enqueue(stream);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, stream));
+  ctx->done_recorded = true;
+  return GBS_OK;
+}
+
+bool check_gfx950(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return false;
+  return std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+}
+
+// Validate one mode list and compute prod_j s_j! (collision multiplicities, Eq. ProOri).
+int pattern_sfact(gbs_ctx* ctx, const int32_t* modes, int64_t len, int32_t m, double* sfact) {
+  int32_t tmp[GBS_N_MAX];
+  for (int64_t i = 0; i < len; ++i) {
+    if (modes[i] < 0 || modes[i] >= m) return fail(ctx, GBS_ERANGE, "mode %d outside [0, %d)", modes[i], m);
+    tmp[i] = modes[i];
+  }
+  std::sort(tmp, tmp + len);
+  double f = 1.0;
+  int64_t run = 1;
+  for (int64_t i = 1; i <= len; ++i) {
+    if (i < len && tmp[i] == tmp[i - 1]) {
+      ++run;
+      f *= (double)run;
+    } else {
+      run = 1;
+    }
+  }
+  *sfact = f;
+  return GBS_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char* gbs_status_str(int status) {
+  switch (status) {
+    case GBS_OK: return "ok";
+    case GBS_EINVAL: return "invalid argument";
+    case GBS_ERANGE: return "value out of range";
+    case GBS_ENOMEM: return "out of memory";
+    case GBS_EHIP: return "HIP runtime error";
+    case GBS_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* gbs_last_error(const gbs_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_ctx** out) {
+  if (!out) return GBS_EINVAL;
+  *out = nullptr;
+  if (workspace_dev == nullptr && workspace_bytes != 0) return GBS_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GBS_EINVAL;
+  if (!check_gfx950(device)) return GBS_EUNSUPPORTED;
+  const Tables& T = tables();
+  if (!T.ok) return T.err;
+  DeviceGuard dg(device);
+  gbs_ctx* c = new gbs_ctx();
+  c->device = device;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) {
+    delete c;
+    return GBS_EHIP;
+  }
+  c->ncu = p.multiProcessorCount;
+  if (upload_tables(T.host) != 0 || hipEventCreateWithFlags(&c->pinned_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->pinned_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    gbs_ctx_destroy(c);
+    return GBS_EHIP;
+  }
+  if (workspace_dev) {
+    c->ws = workspace_dev;
+    c->ws_bytes = workspace_bytes;
+    c->ws_owned = false;
+  }
+  *out = c;
+  return GBS_OK;
+}
+
+int gbs_ctx_destroy(gbs_ctx* c) {
+  if (!c) return GBS_EINVAL;
+  DeviceGuard dg(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  for (int i = 0; i < 2; ++i) {
+    if (c->pinned[i]) (void)hipHostFree(c->pinned[i]);
+    if (c->pinned_ev[i]) (void)hipEventDestroy(c->pinned_ev[i]);
+  }
+  if (c->done_ev) (void)hipEventDestroy(c->done_ev);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+  delete c;
+  return GBS_OK;
+}
+
+int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->use_graph = use_graph ? 1 : 0;
+  ctx->persistent = persistent ? 1 : 0;
+  return GBS_OK;
+}
+
+int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chunk_large) {
+  if (!ctx) return GBS_EINVAL;
+  if (n < 0 || n > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n = %d outside [0, %d]", n, GBS_N_MAX);
+  ctx->tuning[n] = {chunk_small, chunk_large};
+  return GBS_OK;
+}
+
+int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int64_t* chunk_large) {
+  if (!ctx || !chunk_small || !chunk_large) return GBS_EINVAL;
+  if (n < 0 || n > GBS_N_MAX) return GBS_ERANGE;
+  chunks_for(ctx, n, chunk_small, chunk_large);
+  return GBS_OK;
+}
+
+int64_t gbs_subset_count(int32_t n) { return (n < 0 || n > GBS_N_MAX) ? 0 : subset_count(n); }
+
+double gbs_haf_flops(int32_t n) {
+  if (n <= 0 || (n & 1) || n > GBS_N_MAX) return 0.0;
+  const Tables& T = tables();
+  if (!T.ok) return 0.0;
+  const int k = n / 2;
+  double f = 0.0;
+  for (int s = 1; s <= k; ++s) f += (double)T.host.binom[k][s] * flops_subset(T.host.prog[k], k, s);
+  return f;
+}
+
+int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_off_host, const int32_t* n_host,
+                     int64_t batch, gbs_c128* haf_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (batch == 0) return GBS_OK;
+  if (!elem_off_host || !n_host || !haf_out_dev) return fail(ctx, GBS_EINVAL, "null pointer");
+  bool any_data = false;
+  for (int64_t b = 0; b < batch && !any_data; ++b) any_data = n_host[b] > 0;
+  if (any_data && !A_dev) return fail(ctx, GBS_EINVAL, "null matrix pointer");
+  if (batch > (int64_t)1 << 30) return fail(ctx, GBS_ERANGE, "batch too large");
+  const Tables& T = tables();
+  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
+  Plan pl;
+  pl.pats.resize(batch);
+  pl.part_off.resize(batch + 1);
+  pl.nvec.resize(batch);
+  pl.sfact.assign(batch, 1.0);
+  std::vector<WorkItem> large, small;
+  pl.part_off[0] = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    const int n = n_host[b];
+    if (n < 0 || n > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n = %d outside [0, %d]", n, GBS_N_MAX);
+    if (elem_off_host[b] < 0) return fail(ctx, GBS_EINVAL, "negative matrix offset");
+    pl.pats[b] = PatternDesc{elem_off_host[b], n, 0};
+    pl.nvec[b] = n;
+    plan_range(ctx, T.host, pl, large, small, (int)b, n, 0, subset_count(n));
+    pl.part_off[b + 1] = pl.n_partials;
+  }
+  order_items(pl, large, small);
+  return run_plan(ctx, pl, nullptr, 0, reinterpret_cast<const double2*>(A_dev), 0, nullptr, nullptr,
+                  reinterpret_cast<double2*>(haf_out_dev), nullptr, static_cast<hipStream_t>(stream));
+}
+
+int haf_batch(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t batch, int64_t stride_elems,
+              gbs_c128* haf_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (n < 0 || n > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n = %d outside [0, %d]", n, GBS_N_MAX);
+  if (batch > 1 && stride_elems < (int64_t)n * n) return fail(ctx, GBS_EINVAL, "stride smaller than n*n");
+  if (batch == 0) return GBS_OK;
+  std::vector<int64_t> off(batch);
+  std::vector<int32_t> nn(batch, n);
+  for (int64_t b = 0; b < batch; ++b) off[b] = b * stride_elems;
+  return haf_batch_varlen(ctx, A_dev, off.data(), nn.data(), batch, haf_out_dev, stream);
+}
+
+int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const double* r_host, void* stream,
+                     gbs_state** out) {
+  if (!ctx || !out) return GBS_EINVAL;
+  *out = nullptr;
+  ctx->last_error.clear();
+  if (!U_dev || !r_host) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (m <= 0 || m > 4096) return fail(ctx, GBS_ERANGE, "m = %d outside [1, 4096]", m);
+  for (int i = 0; i < m; ++i)
+    if (!std::isfinite(r_host[i])) return fail(ctx, GBS_EINVAL, "non-finite squeezing parameter");
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gbs_state* st = new gbs_state();
+  st->device = ctx->device;
+  st->m = m;
+  const size_t mm = (size_t)m * m;
+  if (hipMalloc(&st->U, sizeof(double2) * mm) != hipSuccess || hipMalloc(&st->B, sizeof(double2) * mm) != hipSuccess ||
+      hipMalloc(&st->r, sizeof(double) * m) != hipSuccess || hipMalloc(&st->pref, sizeof(double)) != hipSuccess ||
+      hipEventCreateWithFlags(&st->ready, hipEventDisableTiming) != hipSuccess) {
+    gbs_state_destroy(st);
+    return fail(ctx, GBS_ENOMEM, "state allocation failed");
+  }
+  hipError_t e = hipMemcpyAsync(st->U, U_dev, sizeof(double2) * mm, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(st->r, r_host, sizeof(double) * m, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    launch_state(st->U, st->r, m, st->B, st->pref, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&st->pref_host, st->pref, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(st->ready, s);
+  if (e != hipSuccess) {
+    gbs_state_destroy(st);
+    return fail(ctx, GBS_EHIP, "state setup: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return GBS_OK;
+}
+
+int gbs_state_destroy(gbs_state* st) {
+  if (!st) return GBS_EINVAL;
+  DeviceGuard dg(st->device);
+  if (st->ready) (void)hipEventSynchronize(st->ready);
+  if (st->U) (void)hipFree(st->U);
+  if (st->B) (void)hipFree(st->B);
+  if (st->r) (void)hipFree(st->r);
+  if (st->pref) (void)hipFree(st->pref);
+  if (st->ready) (void)hipEventDestroy(st->ready);
+  delete st;
+  return GBS_OK;
+}
+
+int gbs_state_info(const gbs_state* st, const gbs_c128** B_dev, int32_t* m, double* prefactor) {
+  if (!st) return GBS_EINVAL;
+  if (B_dev) *B_dev = reinterpret_cast<const gbs_c128*>(st->B);
+  if (m) *m = st->m;
+  if (prefactor) {
+    DeviceGuard dg(st->device);
+    if (hipEventSynchronize(st->ready) != hipSuccess) return GBS_EHIP;
+    *prefactor = st->pref_host;
+  }
+  return GBS_OK;
+}
+
+int gbs_state_copy_B(const gbs_state* st, gbs_c128* dst_dev, void* stream) {
+  if (!st || !dst_dev) return GBS_EINVAL;
+  DeviceGuard dg(st->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipStreamWaitEvent(s, st->ready, 0) != hipSuccess) return GBS_EHIP;
+  if (hipMemcpyAsync(dst_dev, st->B, sizeof(double2) * (size_t)st->m * st->m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return GBS_EHIP;
+  return GBS_OK;
+}
+
+namespace {
+
+int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, const int64_t* offsets_host,
+                int64_t batch, const int64_t* lo_host, const int64_t* hi_host, double* prob_out, double2* haf_out,
+                gbs_partial* partial_out, hipStream_t stream) {
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (batch == 0) return GBS_OK;
+  if (!st || !offsets_host) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (st->device != ctx->device) return fail(ctx, GBS_EINVAL, "state and context are on different devices");
+  if (batch > (int64_t)1 << 30) return fail(ctx, GBS_ERANGE, "batch too large");
+  if (offsets_host[0] != 0) return fail(ctx, GBS_EINVAL, "offsets[0] must be 0");
+  const int64_t total = offsets_host[batch];
+  if (total > 0 && !modes_host) return fail(ctx, GBS_EINVAL, "null modes");
+  const Tables& T = tables();
+  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
+  Plan pl;
+  pl.pats.resize(batch);
+  pl.part_off.resize(batch + 1);
+  pl.nvec.resize(batch);
+  pl.sfact.resize(batch);
+  pl.part_off[0] = 0;
+  std::vector<WorkItem> large, small;
+  for (int64_t b = 0; b < batch; ++b) {
+    const int64_t len = offsets_host[b + 1] - offsets_host[b];
+    if (len < 0) return fail(ctx, GBS_EINVAL, "offsets must be non-decreasing");
+    if (len > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "pattern %lld has n = %lld > %d", (long long)b, (long long)len,
+                                     GBS_N_MAX);
+    const int n = (int)len;
+    int rc = pattern_sfact(ctx, modes_host + offsets_host[b], len, st->m, &pl.sfact[b]);
+    if (rc) return rc;
+    pl.pats[b] = PatternDesc{offsets_host[b], n, 0};
+    pl.nvec[b] = n;
+    int64_t lo = 0, hi = subset_count(n);
+    if (lo_host) {
+      if (lo_host[b] < 0 || hi_host[b] < lo_host[b] || hi_host[b] > hi)
+        return fail(ctx, GBS_ERANGE, "slice %lld: [%lld, %lld) outside [0, %lld]", (long long)b, (long long)lo_host[b],
+                    (long long)hi_host[b], (long long)hi);
+      lo = lo_host[b];
+      hi = hi_host[b];
+    }
+    plan_range(ctx, T.host, pl, large, small, (int)b, n, lo, hi);
+    pl.part_off[b + 1] = pl.n_partials;
+  }
+  order_items(pl, large, small);
+  return run_plan(ctx, pl, modes_host, (size_t)total, st->B, st->m, st->pref, prob_out, haf_out, partial_out, stream);
+}
+
+}  // namespace
+
+int gbs_prob_batch(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, const int64_t* offsets_host,
+                   int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  if (batch > 0 && !prob_out_dev) return fail(ctx, GBS_EINVAL, "null prob_out");
+  return prob_common(ctx, st, modes_host, offsets_host, batch, nullptr, nullptr, prob_out_dev,
+                     reinterpret_cast<double2*>(haf_out_dev), nullptr, static_cast<hipStream_t>(stream));
+}
+
+int gbs_prob_slices(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, const int64_t* offsets_host,
+                    const int64_t* lo_host, const int64_t* hi_host, int64_t batch, gbs_partial* partials_dev,
+                    void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  if (batch > 0 && (!lo_host || !hi_host || !partials_dev)) return fail(ctx, GBS_EINVAL, "null pointer");
+  return prob_common(ctx, st, modes_host, offsets_host, batch, lo_host, hi_host, nullptr, nullptr, partials_dev,
+                     static_cast<hipStream_t>(stream));
+}
+
+int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_dev, const int64_t* part_off_host,
+                 const int32_t* n_host, const double* sfact_host, int64_t batch, double* prob_out_dev,
+                 gbs_c128* haf_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (batch == 0) return GBS_OK;
+  if (!part_off_host || !n_host || (!partials_dev && part_off_host[batch] > 0))
+    return fail(ctx, GBS_EINVAL, "null pointer");
+  if (prob_out_dev && (!st || !sfact_host)) return fail(ctx, GBS_EINVAL, "prob_out needs a state and sfact");
+  if (part_off_host[0] < 0) return fail(ctx, GBS_EINVAL, "negative partial offset");
+  for (int64_t b = 0; b < batch; ++b) {
+    if (part_off_host[b + 1] < part_off_host[b]) return fail(ctx, GBS_EINVAL, "partial offsets must be non-decreasing");
+    if (n_host[b] < 0 || n_host[b] > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n out of range");
+  }
+  // The finalize kernel reads partials through a device offset table; stage it like a plan.
+  Plan pl;
+  pl.part_off.assign(part_off_host, part_off_host + batch + 1);
+  pl.nvec.assign(n_host, n_host + batch);
+  pl.sfact.assign(batch, 1.0);
+  if (sfact_host) pl.sfact.assign(sfact_host, sfact_host + batch);
+  DeviceGuard dg(ctx->device);
+  const Layout L = layout_for(pl, 0);
+  int rc = ensure_ws(ctx, L.total);
+  if (rc) return rc;
+  const int pi = ctx->pin_idx;
+  ctx->pin_idx ^= 1;
+  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
+  rc = ensure_pinned(ctx, pi, L.staged_bytes);
+  if (rc) return rc;
+  unsigned char* h = static_cast<unsigned char*>(ctx->pinned[pi]);
+  const size_t base = L.modes;
+  std::memcpy(h + (L.part_off - base), pl.part_off.data(), sizeof(int64_t) * pl.part_off.size());
+  std::memcpy(h + (L.nvec - base), pl.nvec.data(), sizeof(int32_t) * pl.nvec.size());
+  std::memcpy(h + (L.sfact - base), pl.sfact.data(), sizeof(double) * pl.sfact.size());
+  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->done_ev, 0));
+  HIPCHK(ctx, hipMemcpyAsync(ws + base, h, L.staged_bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], s));
+  ctx->pinned_used[pi] = true;
+  FinalizeArgs fa{};
+  fa.partials = partials_dev;
+  fa.part_off = reinterpret_cast<const int64_t*>(ws + L.part_off);
+  fa.n = reinterpret_cast<const int32_t*>(ws + L.nvec);
+  fa.sfact = reinterpret_cast<const double*>(ws + L.sfact);
+  fa.prefactor = st ? st->pref : nullptr;
+  fa.batch = batch;
+  fa.prob_out = prob_out_dev;
+  fa.haf_out = reinterpret_cast<double2*>(haf_out_dev);
+  launch_finalize(fa, s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
+  ctx->done_recorded = true;
+  return GBS_OK;
+}
+
+}  // extern "C"

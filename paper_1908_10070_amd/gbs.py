@@ -1,0 +1,301 @@
+"""Thin Python binding of libgbs (include/gbs.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every computation runs in the HIP
+library. There is no CPU fallback: if libgbs.so is missing or the device is not gfx950,
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = pathlib.Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libgbs.so"
+
+GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6)
+GBS_N_MAX = 48
+
+# Every function declared in include/gbs.h.
+EXPORTS = [
+    "gbs_ctx_create", "gbs_ctx_destroy", "gbs_status_str", "gbs_last_error", "gbs_ctx_set_exec",
+    "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops", "haf_batch", "haf_batch_varlen",
+    "gbs_state_create", "gbs_state_destroy", "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch",
+    "gbs_subset_count",
+    "gbs_prob_slices", "gbs_finalize",
+]
+
+_lib = None
+
+
+class GBSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class PartialT(ctypes.Structure):
+    _fields_ = [("s_re", ctypes.c_double), ("s_im", ctypes.c_double), ("c_re", ctypes.c_double),
+                ("c_im", ctypes.c_double)]
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree libgbs.so (built by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(str(LIB_PATH))
+    vp, i32, i64, sz, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+    sig = {
+        "gbs_ctx_create": (ctypes.c_int, [ctypes.c_int, vp, sz, ctypes.POINTER(vp)]),
+        "gbs_ctx_destroy": (ctypes.c_int, [vp]),
+        "gbs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+        "gbs_last_error": (ctypes.c_char_p, [vp]),
+        "gbs_ctx_set_exec": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "gbs_ctx_set_tuning": (ctypes.c_int, [vp, i32, i64, i64]),
+        "gbs_ctx_get_tuning": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "gbs_haf_flops": (ctypes.c_double, [i32]),
+        "haf_batch": (ctypes.c_int, [vp, dp, i32, i64, i64, dp, vp]),
+        "haf_batch_varlen": (ctypes.c_int, [vp, dp, dp, dp, i64, dp, vp]),
+        "gbs_state_create": (ctypes.c_int, [vp, dp, i32, dp, vp, ctypes.POINTER(vp)]),
+        "gbs_state_destroy": (ctypes.c_int, [vp]),
+        "gbs_state_info": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+        "gbs_state_copy_B": (ctypes.c_int, [vp, dp, vp]),
+        "gbs_prob_batch": (ctypes.c_int, [vp, vp, dp, dp, i64, dp, dp, vp]),
+        "gbs_subset_count": (i64, [i32]),
+        "gbs_prob_slices": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, vp]),
+        "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, dp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def haf_flops(n: int) -> float:
+    """Algorithmic FP64 flops of one size-n hafnian as the library schedules it."""
+    return float(lib().gbs_haf_flops(int(n)))
+
+
+def subset_count(n: int) -> int:
+    return int(lib().gbs_subset_count(int(n)))
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _t_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream) -> Optional[ctypes.c_void_p]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def pack_patterns(patterns) -> Tuple[np.ndarray, np.ndarray]:
+    """Mode lists (or an (count, n) int array) -> (modes int32, offsets int64)."""
+    if isinstance(patterns, tuple) and len(patterns) == 2:
+        modes = np.ascontiguousarray(patterns[0], dtype=np.int32)
+        offsets = np.ascontiguousarray(patterns[1], dtype=np.int64)
+        if offsets.ndim != 1 or len(offsets) < 1 or offsets[-1] > len(modes) or offsets[0] != 0:
+            raise ValueError("offsets must start at 0 and end within the modes array")
+        return modes, offsets
+    if isinstance(patterns, np.ndarray) and patterns.ndim == 2:
+        cnt, n = patterns.shape
+        return (np.ascontiguousarray(patterns, dtype=np.int32).reshape(-1),
+                np.arange(cnt + 1, dtype=np.int64) * n)
+    lens = np.fromiter((len(p) for p in patterns), dtype=np.int64, count=len(patterns))
+    offsets = np.zeros(len(patterns) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    modes = np.zeros(int(offsets[-1]), dtype=np.int32)
+    for i, p in enumerate(patterns):
+        modes[offsets[i]:offsets[i + 1]] = p
+    return modes, offsets
+
+
+class State:
+    """A resident GBS state: U, B = U diag(tanh r) U^t and 1/prod cosh r on the device."""
+
+    def __init__(self, ctx: "Context", U, r, stream=None):
+        import torch
+        if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.complex128):
+            raise TypeError("U must be a complex128 CUDA tensor")
+        U = U.contiguous()
+        m = U.shape[0]
+        if U.shape != (m, m):
+            raise ValueError("U must be square")
+        r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=np.float64), (m,)))
+        self._ctx = ctx
+        self.m = m
+        self._U = U
+        self._r = r
+        h = ctypes.c_void_p()
+        ctx._check(lib().gbs_state_create(ctx.handle, _t_ptr(U), m, _np_ptr(r), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def info(self):
+        b = ctypes.c_void_p()
+        m = ctypes.c_int32()
+        pf = ctypes.c_double()
+        rc = lib().gbs_state_info(self.handle, ctypes.byref(b), ctypes.byref(m), ctypes.byref(pf))
+        if rc:
+            raise GBSError(rc, "gbs_state_info failed")
+        return b.value, m.value, pf.value
+
+    def B(self, stream=None):
+        """A complex128 CUDA tensor copy of B."""
+        import torch
+        out = torch.empty((self.m, self.m), dtype=torch.complex128, device=self._ctx.torch_device)
+        rc = lib().gbs_state_copy_B(self.handle, _t_ptr(out), _stream_ptr(stream))
+        if rc:
+            raise GBSError(rc, "gbs_state_copy_B failed")
+        return out
+
+    @property
+    def prefactor(self) -> float:
+        return self.info()[2]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gbs_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A libgbs context on one device (staging buffers, workspace, graphs, tuning table)."""
+
+    def __init__(self, device: int = 0, workspace=None, use_graph: bool = True, persistent: bool = True):
+        import torch
+        self.device = int(device)
+        self.torch_device = torch.device("cuda", self.device)
+        self._ws = workspace
+        h = ctypes.c_void_p()
+        ws_ptr = _t_ptr(workspace) if workspace is not None else None
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        rc = lib().gbs_ctx_create(self.device, ws_ptr, ws_bytes, ctypes.byref(h))
+        if rc:
+            raise GBSError(rc, f"gbs_ctx_create: {lib().gbs_status_str(rc).decode()}")
+        self.handle = h
+        self.set_exec(use_graph, persistent)
+
+    # -- errors
+    def _check(self, rc: int):
+        if rc:
+            msg = lib().gbs_last_error(self.handle).decode()
+            raise GBSError(rc, f"{lib().gbs_status_str(rc).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gbs_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- options
+    def set_exec(self, use_graph: bool = True, persistent: bool = True):
+        self._check(lib().gbs_ctx_set_exec(self.handle, int(use_graph), int(persistent)))
+
+    def set_tuning(self, n: int, chunk_small: int, chunk_large: int):
+        self._check(lib().gbs_ctx_set_tuning(self.handle, int(n), int(chunk_small), int(chunk_large)))
+
+    def get_tuning(self, n: int) -> Tuple[int, int]:
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().gbs_ctx_get_tuning(self.handle, int(n), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # -- hafnians
+    def haf_batch(self, A, out=None, stream=None):
+        """Hafnians of a (batch, n, n) complex128 CUDA tensor -> (batch,) complex128 tensor."""
+        import torch
+        if not (isinstance(A, torch.Tensor) and A.is_cuda and A.dtype == torch.complex128 and A.ndim == 3):
+            raise TypeError("A must be a (batch, n, n) complex128 CUDA tensor")
+        if A.shape[1] != A.shape[2]:
+            raise ValueError("matrices must be square")
+        A = A.contiguous()
+        b, n = A.shape[0], A.shape[1]
+        if out is None:
+            out = torch.empty(b, dtype=torch.complex128, device=A.device)
+        self._check(lib().haf_batch(self.handle, _t_ptr(A), n, b, n * n, _t_ptr(out), _stream_ptr(stream)))
+        return out
+
+    def haf_batch_varlen(self, A_flat, elem_off, ns, out=None, stream=None):
+        import torch
+        elem_off = np.ascontiguousarray(elem_off, dtype=np.int64)
+        ns = np.ascontiguousarray(ns, dtype=np.int32)
+        if out is None:
+            out = torch.empty(len(ns), dtype=torch.complex128, device=A_flat.device)
+        self._check(lib().haf_batch_varlen(self.handle, _t_ptr(A_flat), _np_ptr(elem_off), _np_ptr(ns), len(ns),
+                                           _t_ptr(out), _stream_ptr(stream)))
+        return out
+
+    # -- probabilities
+    def state(self, U, r, stream=None) -> State:
+        return State(self, U, r, stream)
+
+    def prob_batch(self, state: State, patterns, want_haf: bool = False, prob_out=None, haf_out=None, stream=None):
+        """Probabilities (and optionally hafnians) of output patterns against `state`."""
+        import torch
+        modes, offsets = pack_patterns(patterns)
+        b = len(offsets) - 1
+        if prob_out is None:
+            prob_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
+        if want_haf and haf_out is None:
+            haf_out = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
+        self._check(lib().gbs_prob_batch(self.handle, state.handle, _np_ptr(modes), _np_ptr(offsets), b,
+                                         _t_ptr(prob_out), _t_ptr(haf_out), _stream_ptr(stream)))
+        return (prob_out, haf_out) if want_haf else prob_out
+
+    def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, stream=None):
+        """Compensated partial sums over subset ranges [lo, hi) -> (batch, 4) float64 tensor."""
+        import torch
+        modes, offsets = pack_patterns(patterns)
+        b = len(offsets) - 1
+        lo = np.ascontiguousarray(lo, dtype=np.int64)
+        hi = np.ascontiguousarray(hi, dtype=np.int64)
+        if partials_out is None:
+            partials_out = torch.empty((b, 4), dtype=torch.float64, device=self.torch_device)
+        self._check(lib().gbs_prob_slices(self.handle, state.handle, _np_ptr(modes), _np_ptr(offsets), _np_ptr(lo),
+                                          _np_ptr(hi), b, _t_ptr(partials_out), _stream_ptr(stream)))
+        return partials_out
+
+    def finalize(self, state: Optional[State], partials, part_off, ns, sfact=None, want_prob=True, stream=None):
+        import torch
+        part_off = np.ascontiguousarray(part_off, dtype=np.int64)
+        ns = np.ascontiguousarray(ns, dtype=np.int32)
+        b = len(ns)
+        sf = None if sfact is None else np.ascontiguousarray(sfact, dtype=np.float64)
+        prob = torch.empty(b, dtype=torch.float64, device=self.torch_device) if want_prob else None
+        haf = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
+        self._check(lib().gbs_finalize(self.handle, state.handle if state is not None else None, _t_ptr(partials),
+                                       _np_ptr(part_off), _np_ptr(ns), _np_ptr(sf), b, _t_ptr(prob), _t_ptr(haf),
+                                       _stream_ptr(stream)))
+        return prob, haf
+
+
+def sfact_of(modes: Sequence[int]) -> float:
+    """prod_j s_j! of a mode list (host-side helper for schedulers)."""
+    _, counts = np.unique(np.asarray(modes, dtype=np.int64), return_counts=True)
+    f = 1.0
+    for c in counts:
+        for v in range(2, int(c) + 1):
+            f *= v
+    return f

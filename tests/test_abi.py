@@ -1,0 +1,76 @@
+"""CPU checks of the C ABI: the library loads, exports what include/gbs.h declares, and its
+host-only entry points behave (no GPU compute is called here)."""
+import ctypes
+import pathlib
+import re
+
+import pytest
+
+from paper_1908_10070_amd import gbs
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+def header_functions():
+    text = (ROOT / "include" / "gbs.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not gbs.LIB_PATH.exists():
+        from paper_1908_10070_amd.csrc import build
+        build.build(force=False)
+    return gbs.lib()
+
+
+def test_header_functions_parsed():
+    fns = header_functions()
+    assert "gbs_prob_batch" in fns and "haf_batch" in fns and len(fns) >= 15
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert sorted(gbs.EXPORTS) == header_functions()
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.gbs_status_str(s)
+    assert lib.gbs_status_str(99) == b"unknown status"
+
+
+def test_subset_count_and_flops(lib):
+    assert gbs.subset_count(0) == 0
+    assert gbs.subset_count(3) == 0
+    assert gbs.subset_count(24) == 4095
+    assert gbs.subset_count(44) == 2 ** 22 - 1
+    assert gbs.subset_count(gbs.GBS_N_MAX + 2) == 0
+    # the flop model of the power-trace schedule: products + inner products + coefficient recursion
+    assert abs(gbs.haf_flops(8) - 2.066e4) / 2.066e4 < 2e-3
+    assert abs(gbs.haf_flops(24) - 3.215e8) / 3.215e8 < 2e-3
+    assert gbs.haf_flops(7) == 0.0
+
+
+def test_null_context_rejected(lib):
+    vp = ctypes.c_void_p
+    assert lib.haf_batch(None, None, 4, 1, 16, None, None) == gbs.GBS_EINVAL
+    assert lib.gbs_prob_batch(None, None, None, None, 1, None, None, None) == gbs.GBS_EINVAL
+    assert lib.gbs_ctx_destroy(None) == gbs.GBS_EINVAL
+    assert lib.gbs_state_destroy(None) == gbs.GBS_EINVAL
+    assert lib.gbs_ctx_set_exec(None, 1, 1) == gbs.GBS_EINVAL
+    out = vp()
+    assert lib.gbs_ctx_create(0, None, 0, None) == gbs.GBS_EINVAL
+    assert lib.gbs_ctx_create(0, None, 123, ctypes.byref(out)) == gbs.GBS_EINVAL
+
+
+def test_pack_patterns():
+    import numpy as np
+    modes, off = gbs.pack_patterns([[1, 2], [], [3, 4, 5, 6]])
+    assert modes.tolist() == [1, 2, 3, 4, 5, 6] and off.tolist() == [0, 2, 2, 6]
+    modes, off = gbs.pack_patterns(np.array([[0, 1], [2, 3]]))
+    assert off.tolist() == [0, 2, 4]
+    assert gbs.sfact_of([1, 1, 2, 2, 2, 5]) == 2 * 6

@@ -1,0 +1,206 @@
+"""Parity of the HIP path with the CPU oracle, called through the C ABI (gfx950 only).
+
+Tolerance: relative error 1e-9 on hafnians and probabilities (complex128 throughout).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_10070_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_1908_10070_amd import gbs
+    return gbs.Context(0)
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def relerr(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return np.abs(x - ref) / np.maximum(np.abs(ref), 1e-300)
+
+
+def dfact(n):
+    return math.prod(range(n - 1, 0, -2)) if n > 0 else 1
+
+
+def test_state_B_and_prefactor(ctx, torch_dev):
+    st_in, _ = inputs.config1()
+    st = ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    B = st.B().cpu().numpy()
+    Bref = oracle.state_B(st_in.U, st_in.r)
+    assert np.max(np.abs(B - Bref)) < 1e-14
+    assert abs(st.prefactor - 0.1463386077562255) < 1e-16
+
+
+@pytest.mark.parametrize("n", list(range(0, 25)) + [26, 28])
+def test_haf_sizes_vs_oracle(ctx, torch_dev, n):
+    """Every size up to 24 (odd ones give 0), a few beyond: several tiles and ragged tails."""
+    rng = np.random.default_rng(100 + n)
+    A = inputs.random_symmetric(n, 3, rng)
+    h = ctx.haf_batch(to_dev(A, torch_dev)).cpu().numpy()
+    for i in range(3):
+        ref = oracle.haf_enum(A[i]) if n <= 24 else oracle.haf_pt_ld(A[i])
+        if n % 2:
+            assert h[i] == 0
+        elif n == 0:
+            assert h[i] == 1
+        else:
+            assert relerr(h[i], ref) < TOL, (n, i, h[i], ref)
+
+
+def test_config1_full(ctx, torch_dev):
+    """m = 16, r = 0.5: all 12,870 collision-free 8-photon patterns plus the vacuum."""
+    st_in, pats = inputs.config1()
+    st = ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    allp = [[]] + [list(p) for p in pats]
+    prob, haf = ctx.prob_batch(st, allp, want_haf=True)
+    prob, haf = prob.cpu().numpy(), haf.cpu().numpy()
+    href = oracle.haf_ref_patterns(st_in.U, st_in.r, pats)
+    pref = oracle.prob_ref_patterns(st_in.U, st_in.r, pats)
+    assert abs(prob[0] - 0.1463386077562255) < 1e-16
+    assert haf[0] == 1
+    assert np.max(relerr(haf[1:], href)) < TOL
+    assert np.max(relerr(prob[1:], pref)) < TOL
+
+
+def test_config2_sampled(ctx, torch_dev):
+    """4096 random complex-symmetric 24 x 24 matrices; oracle on a seeded sample."""
+    A = inputs.config2()
+    h = ctx.haf_batch(to_dev(A, torch_dev)).cpu().numpy()
+    idx = np.random.default_rng(5).choice(len(A), 24, replace=False)
+    idx = np.concatenate([[0, len(A) - 1], idx])
+    ref = np.array([oracle.haf_enum(A[i]) for i in idx])
+    err = relerr(h[idx], ref)
+    assert np.max(err) < TOL, err
+
+
+def test_collisions(ctx, torch_dev):
+    rng = np.random.default_rng(11)
+    m = 10
+    U = inputs.haar_unitary(m, rng)
+    r = rng.uniform(0.2, 0.9, size=m)
+    st = ctx.state(to_dev(U, torch_dev), r)
+    pats = [[0, 0], [1, 1, 1, 1], [2, 3, 3, 4], [5, 5, 6, 6, 7, 7], [9, 0, 9, 0, 1, 2, 3, 3], [4, 4, 4], [8]]
+    prob, haf = ctx.prob_batch(st, pats, want_haf=True)
+    prob, haf = prob.cpu().numpy(), haf.cpu().numpy()
+    for i, p in enumerate(pats):
+        ref = oracle.prob_ref(U, r, p)
+        if len(p) % 2:
+            assert prob[i] == 0 and haf[i] == 0
+        else:
+            assert relerr(prob[i], ref) < TOL, p
+            assert relerr(haf[i], oracle.haf_enum(oracle.pattern_matrix(oracle.state_B(U, r), p))) < TOL
+
+
+def test_all_ones_closed_form(ctx, torch_dev):
+    import torch
+    for n in (2, 8, 16, 18, 24, 32):
+        A = torch.ones((1, n, n), dtype=torch.complex128, device=torch_dev)
+        h = ctx.haf_batch(A).cpu().numpy()[0]
+        assert relerr(h, dfact(n)) < TOL, n
+
+
+def test_bipartite_is_permanent(ctx, torch_dev):
+    """Haf([[0, W], [W^t, 0]]) = Per(W) (Ryser's formula, vectorised, as the reference)."""
+    for k in (5, 9, 12):
+        rng = np.random.default_rng(200 + k)
+        W = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2)
+        A = np.block([[np.zeros((k, k)), W], [W.T, np.zeros((k, k))]])
+        h = ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
+        masks = np.arange(1, 1 << k)
+        sel = ((masks[:, None] >> np.arange(k)[None, :]) & 1).astype(np.float64)
+        rows = sel @ W.T  # (2^k-1, k): row sums over selected columns
+        signs = (-1.0) ** sel.sum(axis=1)
+        per = (-1) ** k * np.sum(signs * np.prod(rows, axis=1))
+        assert relerr(h, per) < TOL, k
+
+
+def test_batch_composition_is_bitwise_invariant(ctx, torch_dev):
+    """A pattern's result does not depend on what else is in the batch, nor on the launch mode."""
+    from paper_1908_10070_amd import gbs
+    rng = np.random.default_rng(21)
+    A = inputs.random_symmetric(20, 6, rng)
+    full = ctx.haf_batch(to_dev(A, torch_dev)).cpu().numpy()
+    alone = np.array([ctx.haf_batch(to_dev(A[i:i + 1], torch_dev)).cpu().numpy()[0] for i in range(6)])
+    assert np.array_equal(full, alone)
+    for use_graph, persistent in [(False, True), (False, False), (True, False)]:
+        c2 = gbs.Context(0, use_graph=use_graph, persistent=persistent)
+        assert np.array_equal(c2.haf_batch(to_dev(A, torch_dev)).cpu().numpy(), full)
+
+
+def test_graph_replays(ctx, torch_dev):
+    import torch
+    rng = np.random.default_rng(22)
+    A = to_dev(inputs.random_symmetric(16, 40, rng), torch_dev)
+    out = torch.empty(40, dtype=torch.complex128, device=torch_dev)
+    ref = ctx.haf_batch(A, out=out).clone()
+    for _ in range(4):
+        out.zero_()
+        torch.cuda.synchronize()
+        ctx.haf_batch(A, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+
+
+def test_slices_and_finalize(ctx, torch_dev):
+    from paper_1908_10070_amd import gbs
+    rng = np.random.default_rng(23)
+    m = 30
+    U = inputs.haar_unitary(m, rng)
+    r = np.full(m, 0.88)
+    st = ctx.state(to_dev(U, torch_dev), r)
+    pats = [sorted(rng.choice(m, n, replace=False).tolist()) for n in (18, 22, 12)]
+    prob = ctx.prob_batch(st, pats).cpu().numpy()
+    # cut each pattern's subset range into uneven slices
+    sl_pats, lo, hi, part_off, ns, sf = [], [], [], [0], [], []
+    for p in pats:
+        cnt = gbs.subset_count(len(p))
+        cuts = sorted(set([0, cnt] + rng.integers(0, cnt, 4).tolist()))
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            sl_pats.append(p)
+            lo.append(a)
+            hi.append(b)
+        part_off.append(part_off[-1] + len(cuts) - 1)
+        ns.append(len(p))
+        sf.append(gbs.sfact_of(p))
+    parts = ctx.prob_slices(st, sl_pats, lo, hi)
+    p2, h2 = ctx.finalize(st, parts, part_off, ns, sf)
+    assert np.max(relerr(p2.cpu().numpy(), prob)) < TOL
+
+
+def test_invalid_inputs_raise(ctx, torch_dev):
+    from paper_1908_10070_amd import gbs
+    st_in, _ = inputs.config1()
+    st = ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    with pytest.raises(gbs.GBSError) as e:
+        ctx.prob_batch(st, [[0, 16]])
+    assert e.value.status == gbs.GBS_ERANGE
+    with pytest.raises(gbs.GBSError) as e:
+        ctx.prob_batch(st, [list(range(16)) * 4])
+    assert e.value.status == gbs.GBS_ERANGE
+    with pytest.raises(ValueError):
+        ctx.prob_batch(st, (np.array([0, 1], np.int32), np.array([0, 3], np.int64)))
+    with pytest.raises(gbs.GBSError) as e:
+        ctx.prob_batch(st, (np.array([0, 1, 2], np.int32), np.array([0, 2, 1], np.int64)))
+    assert e.value.status == gbs.GBS_EINVAL
