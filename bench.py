@@ -1,0 +1,134 @@
+"""Benchmark: batched complex128 hafnians on one MI355X, against the per-pattern GPU path and the
+CPU oracle, plus the latency of served probability requests.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one haf_batch call over 4096 random complex-symmetric 24x24 matrices (resident in HBM),
+i.e. one pass of the whole hot path: planning, staging, the subset engine and the finalize kernel,
+replayed from a HIP graph. Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "n=24 complex128 hafnians/s + p50/p99 prob-request latency vs per-pattern path"
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+
+
+def _oracle_worker(args):
+    import oracle
+    mats, = args
+    t0 = time.perf_counter()
+    for a in mats:
+        oracle.haf_pt(a)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(A, n_per_core=12):
+    """The oracle's power-trace hafnian timed on the host cores over a bounded sample."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    sample = A[: cores * n_per_core]
+    chunks = [(sample[i::cores],) for i in range(cores)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_worker, chunks)
+    wall = time.perf_counter() - t0
+    return {"value": len(sample) / wall, "unit": "hafnians/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle haf_pt (FP64 power trace) on the first {len(sample)} of the 4096 matrices, "
+                      f"{cores} worker processes, {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-per-pattern", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1908_10070_amd import inputs
+
+    n, batch = 24, 4096
+    A_host = inputs.config2(batch=batch, n=n)
+    # The CPU leg runs first, in worker processes forked before anything touches the GPU.
+    cpu = None if args.no_cpu else cpu_baseline(A_host)
+
+    import torch
+    from paper_1908_10070_amd import gbs
+
+    dev = torch.device("cuda", 0)
+    A = torch.from_numpy(A_host).to(dev)
+    out = torch.empty(batch, dtype=torch.complex128, device=dev)
+    ctx = gbs.Context(0, use_graph=True, persistent=True)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.haf_batch(A, out=out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    step_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.haf_batch(A, out=out)
+        e1.record(stream)
+        step_ms.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = [a.elapsed_time(b) for a, b in step_ms]
+    ms_per_step = wall * 1e3 / args.steps
+    value = batch / (wall / args.steps)
+
+    flops_per_haf = gbs.haf_flops(n)
+    kern_ms = float(np.mean(gpu_ms))
+    achieved = flops_per_haf * batch / (kern_ms * 1e-3) / 1e12
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "hafnians/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
+        "config": {"workload": "config2: 4096 random complex-symmetric 24x24 matrices (seed 1002), haf_batch, "
+                               "persistent launch replayed from a HIP graph", "n": n, "batch": batch},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms},
+    }
+
+    if not args.no_per_pattern:
+        pp = gbs.Context(0, use_graph=False, persistent=False)
+        cnt = 256
+        for i in range(4):
+            pp.haf_batch(A[i:i + 1], out=out[i:i + 1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(cnt):
+            pp.haf_batch(A[i:i + 1], out=out[i:i + 1])
+        torch.cuda.synchronize()
+        pp_rate = cnt / (time.perf_counter() - t1)
+        res["per_pattern"] = {"value": pp_rate, "unit": "hafnians/s", "sample": f"{cnt} one-launch-per-matrix calls",
+                              "speedup_batched": value / pp_rate}
+
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GBS_N_MAX 48
+#define GBS_N_MAX 46
 
 typedef struct {
   double re, im;

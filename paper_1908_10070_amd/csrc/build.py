@@ -15,8 +15,8 @@ ROOT = PKG.parent
 INCLUDE = ROOT / "include"
 OUT = PKG / "libgbs.so"
 
-SOURCES = ["gbs_kernels.hip", "gbs_runtime.cpp", "gbs_chain.cpp"]
-HEADERS = ["gbs_internal.h"]
+SOURCES = ["gbs_kernels.hip", "gbs_runtime.cpp"]
+HEADERS = ["gbs_internal.h", "gbs_wave_engine.h", "gbs_chain_table.h"]
 
 ARCH = "gfx950"
 COMMON = [

@@ -10,10 +10,7 @@ namespace gbs {
 
 constexpr int kMaxK = GBS_N_MAX / 2;  // largest pair count k = n/2
 constexpr int kMaxOps = 64;           // ops in one chain program
-constexpr int kMaxSlots = 6;          // LDS matrix slots a chain program may use
-constexpr int kBatchG = 16;           // subsets whose traces are buffered before the coefficient step
-constexpr int kThreads = 256;         // workgroup size of the subset engine (4 waves)
-constexpr int kSmallD = 16;           // subsets with d = 2|Z| <= 16 run one per wave
+constexpr int kThreads = 256;         // workgroup size of the register engine (4 waves)
 
 enum OpType : uint8_t { OP_MUL = 1, OP_TDIAG = 2, OP_TPAIR = 3 };
 
@@ -66,10 +63,7 @@ struct EngineArgs {
   int32_t persistent;
   int32_t stage_A;            // copy each pattern matrix into LDS (n <= 32)
   int32_t nmax;               // largest n among the items (LDS sizing)
-  int32_t slot_stride;        // row stride (complex) of a large-subset slot
-  int32_t slot_elems;         // complex elements per large-subset slot
   int32_t kmax;               // largest k among the items
-  int32_t nslots;             // largest slot count of the chain programs in use
 };
 
 struct FinalizeArgs {
@@ -85,10 +79,12 @@ struct FinalizeArgs {
 };
 
 // Host-side launchers (defined in gbs_kernels.hip).
-size_t engine_lds_bytes(int nmax, int kmax, int slot_elems, int stage_A, int nslots);
-int engine_blocks_per_cu(size_t lds_bytes);
+constexpr int kEngineClasses = 7;  // subset-engine kernel variants (see gbs_kernels.hip)
+int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
+size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);
+int engine_blocks_per_cu(int cls, size_t lds);
+void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream_t s);
 void launch_reset(int32_t* counter, int n, hipStream_t s);
-void launch_engine(const EngineArgs& a, int grid, size_t lds, hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
 void launch_state(const double2* U, const double* r, int m, double2* B, double* prefactor, hipStream_t s);
 int upload_tables(const ConstTables& t);

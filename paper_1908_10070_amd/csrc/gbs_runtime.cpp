@@ -17,9 +17,7 @@
 #include "gbs.h"
 #include "gbs_internal.h"
 
-namespace gbs {
-bool build_chain_program(int k, int slot_limit, ChainProgram* out);
-}
+#include "gbs_chain_table.h"
 
 using namespace gbs;
 
@@ -51,21 +49,7 @@ const Tables& tables() {
     for (int b = 1; b <= kMaxK; ++b) t.binom[a][b] = a == 0 ? 0 : t.binom[a - 1][b - 1] + t.binom[a - 1][b];
   }
   for (int q = 1; q <= kMaxK; ++q) t.inv[q] = 1.0 / (double)q;
-  for (int k = 1; k <= kMaxK; ++k) {
-    const int n = 2 * k;
-    const size_t fixed = engine_lds_bytes(n, k, 0, n <= 32, 0);
-    int limit = kMaxSlots;
-    while (limit > 1) {
-      size_t small = sizeof(double) * 2 * 4 * (size_t)limit * kSmallD * (kSmallD + 1);
-      size_t large = k > kSmallD / 2 ? limit * slot_bytes_large(n) : 0;
-      if (fixed + std::max(small, large) + 64 <= kLdsBudget) break;
-      --limit;
-    }
-    if (!build_chain_program(k, limit, &t.prog[k])) {
-      g_tab.err = GBS_EUNSUPPORTED;
-      return g_tab;
-    }
-  }
+  for (int k = 0; k <= kMaxK; ++k) t.prog[k] = kChainTable[k];
   g_tab.ok = true;
   return g_tab;
 }
@@ -184,24 +168,41 @@ void chunks_for(const gbs_ctx* ctx, int n, int64_t* cs, int64_t* cl) {
 // Host-side plan of one call, laid out exactly as it is copied into the device workspace.
 struct Plan {
   std::vector<PatternDesc> pats;
-  std::vector<WorkItem> items;
+  std::vector<WorkItem> items;  // grouped by engine kernel
+  struct Group {
+    int cls;                     // engine kernel variant
+    int64_t first, count;
+  };
+  std::vector<Group> groups;
   std::vector<int64_t> part_off;  // batch + 1 (finalize groups)
   std::vector<int32_t> nvec;
   std::vector<double> sfact;
   int64_t n_partials = 0;
-  int nmax = 0, kmax = 0, dmax_large = 0, nslots = 1;
+  int nmax = 0, kmax = 0;
 };
 
-// Split [lo, hi) of pattern p into items at the small/large boundary and the chunk sizes.
-void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, std::vector<WorkItem>& large,
-                std::vector<WorkItem>& small, int p, int n, int64_t lo, int64_t hi) {
+// Split [lo, hi) of pattern p into items at the engine boundaries and the chunk sizes:
+// |Z| <= 8 (one 16x16 tile), 8 < |Z| <= 16 (2x2 tiles; both on the register engine) and
+// |Z| > 16 (workgroup engine with LDS-resident powers).
+struct ItemLists {
+  std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
+};
+
+// Split [lo, hi) of pattern p into items: ranges of equal engine variant (subset sizes |Z| <= 8,
+// 9..16, >= 17 use one, 2x2 and 3x3 tiles), cut into chunks.
+void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L, int p, int n, int64_t lo,
+                int64_t hi) {
   if (hi <= lo) return;
   const int k = n / 2;
   int64_t cs, cl;
   chunks_for(ctx, n, &cs, &cl);
-  const int s_split = std::min(k, kSmallD / 2);
-  const int64_t gsplit = size_start(t, k, s_split + 1);  // first large subset
-  auto emit = [&](int64_t a, int64_t b, int64_t chunk, std::vector<WorkItem>& out, bool is_large) {
+  const int bounds[3][2] = {{1, 8}, {9, 16}, {17, kMaxK}};
+  for (const auto& bd : bounds) {
+    if (bd[0] > k) break;
+    const int64_t a = std::max(lo, size_start(t, k, bd[0]));
+    const int64_t b = std::min(hi, size_start(t, k, std::min(bd[1], k) + 1));
+    const int64_t chunk = bd[0] == 1 ? cs : cl;
+    std::vector<WorkItem>& out = L.cls[engine_class(bd[0], k)];
     for (int64_t x = a; x < b; x += chunk) {
       WorkItem w;
       w.lo = x;
@@ -209,29 +210,31 @@ void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, std::vector<
       w.pattern = p;
       w.partial = (int32_t)pl.n_partials++;
       out.push_back(w);
-      if (is_large) pl.dmax_large = std::max(pl.dmax_large, n);
     }
-  };
-  emit(lo, std::min(hi, gsplit), cs, small, false);
-  emit(std::max(lo, gsplit), hi, cl, large, true);
+  }
   pl.nmax = std::max(pl.nmax, n);
   pl.kmax = std::max(pl.kmax, k);
-  pl.nslots = std::max(pl.nslots, t.prog[k].nslots);
 }
 
-// Order items so expensive ones start first: large-subset items by decreasing n, then small ones.
-void order_items(Plan& pl, std::vector<WorkItem>& large, std::vector<WorkItem>& small) {
-  auto by_n = [&](std::vector<WorkItem>& v) {
+// Item order: launches with the biggest tiles first; within a launch larger n first, so long items
+// start early.
+void order_items(Plan& pl, ItemLists& L) {
+  pl.items.clear();
+  pl.groups.clear();
+  const int order[kEngineClasses] = {6, 5, 4, 3, 2, 1, 0};
+  for (int cls : order) {
+    std::vector<WorkItem>& v = L.cls[cls];
+    if (v.empty()) continue;
     std::stable_sort(v.begin(), v.end(), [&](const WorkItem& a, const WorkItem& b) {
       return pl.pats[a.pattern].n > pl.pats[b.pattern].n;
     });
-  };
-  by_n(large);
-  by_n(small);
-  pl.items.clear();
-  pl.items.reserve(large.size() + small.size());
-  pl.items.insert(pl.items.end(), large.begin(), large.end());
-  pl.items.insert(pl.items.end(), small.begin(), small.end());
+    Plan::Group g;
+    g.cls = cls;
+    g.first = (int64_t)pl.items.size();
+    g.count = (int64_t)v.size();
+    pl.items.insert(pl.items.end(), v.begin(), v.end());
+    pl.groups.push_back(g);
+  }
 }
 
 struct Layout {
@@ -244,7 +247,7 @@ Layout layout_for(const Plan& pl, size_t n_modes) {
   Layout L;
   size_t off = 0;
   L.counter = off;
-  off += 256;
+  off += 256;  // one work counter per engine launch
   const size_t stage_begin = off;
   L.modes = off;
   off += al(sizeof(int32_t) * n_modes);
@@ -334,26 +337,41 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], stream));
   ctx->pinned_used[pi] = true;
 
+  // register engine (|Z| <= 16) and workgroup engine (|Z| > 16): separate item lists and counters
   EngineArgs ea{};
   ea.A = A;
   ea.modes = modes_host ? reinterpret_cast<const int32_t*>(ws + L.modes) : nullptr;
   ea.m = m;
-  ea.n_items = (int32_t)pl.items.size();
   ea.pats = reinterpret_cast<const PatternDesc*>(ws + L.pats);
-  ea.items = reinterpret_cast<const WorkItem*>(ws + L.items);
   ea.partials = reinterpret_cast<gbs_partial*>(ws + L.partials);
-  ea.counter = reinterpret_cast<int32_t*>(ws + L.counter);
   ea.persistent = ctx->persistent;
   ea.stage_A = pl.nmax <= 32 ? 1 : 0;
   ea.nmax = std::max(pl.nmax, 2);
   ea.kmax = std::max(pl.kmax, 1);
-  ea.slot_stride = pl.dmax_large + 1;
-  ea.slot_elems = pl.dmax_large * (pl.dmax_large + 1);
-  ea.nslots = pl.nslots;
-  const size_t lds = engine_lds_bytes(ea.nmax, ea.kmax, ea.slot_elems, ea.stage_A, ea.nslots);
-  if (lds > kLdsBudget) return fail(ctx, GBS_EUNSUPPORTED, "plan needs %zu bytes of LDS", lds);
-  int grid = ea.n_items;
-  if (ctx->persistent) grid = std::min<int64_t>(ea.n_items, (int64_t)ctx->ncu * engine_blocks_per_cu(lds));
+
+  struct Launch {
+    int cls;
+    EngineArgs a;
+    int grid;
+    size_t lds;
+  };
+  std::vector<Launch> launches;
+  int32_t* counters = reinterpret_cast<int32_t*>(ws + L.counter);
+  for (size_t gi = 0; gi < pl.groups.size(); ++gi) {
+    const Plan::Group& g = pl.groups[gi];
+    Launch ln;
+    ln.cls = g.cls;
+    ln.a = ea;
+    ln.a.n_items = (int32_t)g.count;
+    ln.a.items = reinterpret_cast<const WorkItem*>(ws + L.items) + g.first;
+    ln.a.counter = counters + gi;
+    ln.lds = engine_lds_bytes(g.cls, ea.nmax, ea.kmax, ea.stage_A);
+    const int per_cu = engine_blocks_per_cu(g.cls, ln.lds);
+    if (ln.lds > kLdsBudget) return fail(ctx, GBS_EUNSUPPORTED, "plan needs %zu bytes of LDS", ln.lds);
+    ln.grid = (int)g.count;
+    if (ctx->persistent) ln.grid = (int)std::min<int64_t>(g.count, (int64_t)ctx->ncu * per_cu);
+    launches.push_back(ln);
+  }
 
   FinalizeArgs fa{};
   fa.partials = ea.partials;
@@ -367,20 +385,23 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   fa.partial_out = partial_out;
 
   auto enqueue = [&](hipStream_t s) {
-    if (ea.n_items > 0) {
-      if (ctx->persistent) launch_reset(ea.counter, 1, s);
-      launch_engine(ea, grid, lds, s);
-    }
+    if (ctx->persistent && !launches.empty()) launch_reset(counters, (int)launches.size(), s);
+    for (const Launch& ln : launches) launch_engine(ln.cls, ln.a, ln.grid, ln.lds, s);
     if (fa.batch > 0) launch_finalize(fa, s);
   };
 
   if (ctx->use_graph) {
     GraphKey key;
-    key.v = {grid, (int64_t)lds, ea.n_items, ea.nmax, ea.kmax, ea.slot_stride, ea.nslots, ea.stage_A,
-             ea.persistent, (int64_t)(intptr_t)A, (int64_t)(intptr_t)ea.modes, m, fa.batch,
-             (int64_t)(intptr_t)prefactor_dev, (int64_t)(intptr_t)prob_out, (int64_t)(intptr_t)haf_out,
-             (int64_t)(intptr_t)partial_out, (int64_t)(intptr_t)ctx->ws, (int64_t)L.pats, (int64_t)L.items,
-             (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact};
+    key.v = {ea.nmax, ea.kmax, ea.stage_A, ea.persistent, (int64_t)(intptr_t)A,
+             (int64_t)(intptr_t)ea.modes, m, fa.batch, (int64_t)(intptr_t)prefactor_dev, (int64_t)(intptr_t)prob_out,
+             (int64_t)(intptr_t)haf_out, (int64_t)(intptr_t)partial_out, (int64_t)(intptr_t)ctx->ws, (int64_t)L.pats,
+             (int64_t)L.items, (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact};
+    for (const Launch& ln : launches) {
+      key.v.push_back(ln.cls);
+      key.v.push_back(ln.grid);
+      key.v.push_back((int64_t)ln.lds);
+      key.v.push_back(ln.a.n_items);
+    }
     hipGraphExec_t exec = nullptr;
     for (auto itg = ctx->graphs.begin(); itg != ctx->graphs.end(); ++itg)
       if (!(itg->first < key) && !(key < itg->first)) {
@@ -561,7 +582,7 @@ int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_of
   pl.part_off.resize(batch + 1);
   pl.nvec.resize(batch);
   pl.sfact.assign(batch, 1.0);
-  std::vector<WorkItem> large, small;
+  ItemLists lists;
   pl.part_off[0] = 0;
   for (int64_t b = 0; b < batch; ++b) {
     const int n = n_host[b];
@@ -569,10 +590,10 @@ int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_of
     if (elem_off_host[b] < 0) return fail(ctx, GBS_EINVAL, "negative matrix offset");
     pl.pats[b] = PatternDesc{elem_off_host[b], n, 0};
     pl.nvec[b] = n;
-    plan_range(ctx, T.host, pl, large, small, (int)b, n, 0, subset_count(n));
+    plan_range(ctx, T.host, pl, lists, (int)b, n, 0, subset_count(n));
     pl.part_off[b + 1] = pl.n_partials;
   }
-  order_items(pl, large, small);
+  order_items(pl, lists);
   return run_plan(ctx, pl, nullptr, 0, reinterpret_cast<const double2*>(A_dev), 0, nullptr, nullptr,
                   reinterpret_cast<double2*>(haf_out_dev), nullptr, static_cast<hipStream_t>(stream));
 }
@@ -685,7 +706,7 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
   pl.nvec.resize(batch);
   pl.sfact.resize(batch);
   pl.part_off[0] = 0;
-  std::vector<WorkItem> large, small;
+  ItemLists lists;
   for (int64_t b = 0; b < batch; ++b) {
     const int64_t len = offsets_host[b + 1] - offsets_host[b];
     if (len < 0) return fail(ctx, GBS_EINVAL, "offsets must be non-decreasing");
@@ -704,10 +725,10 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
       lo = lo_host[b];
       hi = hi_host[b];
     }
-    plan_range(ctx, T.host, pl, large, small, (int)b, n, lo, hi);
+    plan_range(ctx, T.host, pl, lists, (int)b, n, lo, hi);
     pl.part_off[b + 1] = pl.n_partials;
   }
-  order_items(pl, large, small);
+  order_items(pl, lists);
   return run_plan(ctx, pl, modes_host, (size_t)total, st->B, st->m, st->pref, prob_out, haf_out, partial_out, stream);
 }
 

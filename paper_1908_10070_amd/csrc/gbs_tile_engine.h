@@ -1,0 +1,225 @@
+// Tile-per-wave subset engine for subsets with 16 < d = 2|Z| <= 16 T (T = 2 or 3), gfx950.
+//
+// A workgroup of T*T waves evaluates one subset at a time. Wave (I, J) keeps tile (I, J) of M_Z and
+// of every power in registers, in the v_mfma_f64_16x16x4f64 accumulator layout (see the register
+// engine). A product Z = X Y publishes each wave's tiles of X and Y to LDS once; wave (I, J) then
+// accumulates Z(I, J) = sum_K X(I, K) Y(K, J) with the A operand X(I, K) read from tile (K, I) at lane
+// l ^ 17 (the pair symmetry Q^t = X Q X of every power) and the B operand from tile (K, J). Trace
+// inner products pair a tile with the same tile of the other factor, so they stay local; each wave
+// reduces its k partial traces with a butterfly, and the T*T wave results are added in wave order.
+// Coefficient recursion, compensated summation and partials are as in the register engine.
+#pragma once
+
+namespace gbs {
+namespace {
+
+template <int T>
+__device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMat<1>& Z, int d, int lane, int w,
+                                         int I, int J, double2* xbuf) {
+  constexpr int NT = T * T;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    xbuf[((0 * NT + w) * 4 + r) * 64 + lane] = make_double2(X.r[0][0][r], X.i[0][0][r]);
+    xbuf[((1 * NT + w) * 4 + r) * 64 + lane] = make_double2(Y.r[0][0][r], Y.i[0][0][r]);
+  }
+  __syncthreads();
+  d4 accr = d4{0.0, 0.0, 0.0, 0.0}, acci = d4{0.0, 0.0, 0.0, 0.0};
+  if (16 * I < d && 16 * J < d) {
+#pragma unroll
+    for (int K = 0; K < T; ++K)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (16 * K + 4 * r < d) {
+          const double2 a = xbuf[((0 * NT + K * T + I) * 4 + r) * 64 + (lane ^ 17)];
+          const double2 b = xbuf[((1 * NT + K * T + J) * 4 + r) * 64 + lane];
+          accr = mfma(a.x, b.x, accr);
+          acci = mfma(a.x, b.y, acci);
+          accr = mfma(-a.y, b.y, accr);
+          acci = mfma(a.y, b.x, acci);
+        }
+      }
+  }
+  __syncthreads();
+  Z.r[0][0] = accr;
+  Z.i[0][0] = acci;
+}
+
+template <int K, int T, int OI, int NS>
+__device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double2 (&tp)[K + 1], int d, int lane, int w, int I,
+                                             int J, double2* xbuf) {
+  if constexpr (OI < kChainTable[K].nops) {
+    constexpr Op op = kChainTable[K].ops[OI];
+    if constexpr (op.type == OP_MUL) {
+      tile_mul<T>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
+    } else if constexpr (op.type == OP_TDIAG) {
+      if (I == J) tdiag<1>(S[op.a], tp[op.x], lane);
+    } else {
+      tpair<1>(S[op.a], S[op.b], tp[op.x]);
+    }
+    run_ops_tile<K, T, OI + 1, NS>(S, tp, d, lane, w, I, J, xbuf);
+  }
+}
+
+// One subset on the whole workgroup; the wave sums of the traces land in tred[w][component].
+template <int K, int T>
+__device__ __forceinline__ void eval_subset_tile(const PatternView& P, const int32_t* pl, int d, int lane, int w,
+                                                 double2* xbuf, double* tred) {
+  constexpr int NS = kChainTable[K].nslots;
+  const int I = w / T, J = w % T;
+  CMat<1> S[NS];
+  const int x = lane & 15, y = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = 16 * I + y + 4 * r;
+    const int c = 16 * J + x;
+    double vr = 0.0, vi = 0.0;
+    if (a < d && c < d) {
+      const int b = a ^ 1;
+      const double2 e = P.at(2 * pl[b >> 1] + (b & 1), 2 * pl[c >> 1] + (c & 1));
+      vr = e.x;
+      vi = e.y;
+    }
+    S[0].r[0][0][r] = vr;
+    S[0].i[0][0][r] = vi;
+  }
+  double2 tp[K + 1];
+#pragma unroll
+  for (int j = 0; j <= K; ++j) tp[j] = make_double2(0.0, 0.0);
+  run_ops_tile<K, T, 0, NS>(S, tp, d, lane, w, I, J, xbuf);
+  reduce_traces<K>(tp, lane, [&](int idx, double v) { tred[w * 2 * K + idx] = v; });
+}
+
+template <int K, int T>
+__device__ void tile_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double2* xbuf, double* tred,
+                           double* trw, int32_t* sz, double2* terms, int tid, double& sr, double& si, double& cr,
+                           double& ci) {
+  constexpr int NT = T * T;
+  const int w = tid >> 6, lane = tid & 63;
+  for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
+    const int cnt = (int)((hi - g0) < kWaveG ? (hi - g0) : kWaveG);
+    for (int u = 0; u < cnt; ++u) {
+      int s;
+      const uint32_t mask = unrank(K, g0 + u, &s);
+      __syncthreads();  // previous subset done with the pair list and tred
+      if (tid < K && ((mask >> tid) & 1u)) pl[__popc(mask & ((1u << tid) - 1u))] = tid;
+      if (tid == 0) sz[u] = s;
+      __syncthreads();
+      eval_subset_tile<K, T>(P, pl, 2 * s, lane, w, xbuf, tred);
+      __syncthreads();
+      if (tid < 2 * K) {
+        double v = tred[tid];
+#pragma unroll
+        for (int q = 1; q < NT; ++q) v += tred[q * 2 * K + tid];
+        trw[((tid >> 1) + 1) * (2 * kWaveG) + 2 * u + (tid & 1)] = 0.5 * v;
+      }
+    }
+    __syncthreads();
+    if (w == 0) combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+struct TileLds {
+  size_t A, modes, pl, xbuf, tred, trw, sz, terms, item, total;
+};
+
+__host__ __device__ inline TileLds tile_lds_layout(int T, int nmax, int kmax, int stage_A) {
+  TileLds L;
+  size_t off = 0;
+  L.A = off;
+  off += stage_A ? wal16(sizeof(double) * 2 * nmax * nmax) : 0;
+  L.modes = off;
+  off += wal16(sizeof(int32_t) * GBS_N_MAX);
+  L.pl = off;
+  off += wal16(sizeof(int32_t) * kMaxK);
+  L.xbuf = off;
+  off += wal16(sizeof(double) * 2 * 2 * T * T * 4 * 64);
+  L.tred = off;
+  off += wal16(sizeof(double) * T * T * 2 * kmax);
+  L.trw = off;
+  off += wal16(sizeof(double) * (kmax + 1) * 2 * kWaveG);
+  L.sz = off;
+  off += wal16(sizeof(int32_t) * kWaveG);
+  L.terms = off;
+  off += wal16(sizeof(double) * 2 * kWaveG);
+  L.item = off;
+  off += 16;
+  L.total = off;
+  return L;
+}
+
+template <int T, int KLO, int KHI>
+__global__ __launch_bounds__(T * T * 64) void tile_engine_kernel(EngineArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NTH = T * T * 64;
+  const TileLds L = tile_lds_layout(T, args.nmax, args.kmax, args.stage_A);
+  double2* Alds = reinterpret_cast<double2*>(smem + L.A);
+  int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
+  int32_t* pl = reinterpret_cast<int32_t*>(smem + L.pl);
+  double2* xbuf = reinterpret_cast<double2*>(smem + L.xbuf);
+  double* tred = reinterpret_cast<double*>(smem + L.tred);
+  double* trw = reinterpret_cast<double*>(smem + L.trw);
+  int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz);
+  double2* terms = reinterpret_cast<double2*>(smem + L.terms);
+  int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
+  const int tid = threadIdx.x;
+
+  int it = args.persistent ? 0 : (int)blockIdx.x;
+  for (;;) {
+    if (args.persistent) {
+      __syncthreads();
+      if (tid == 0) item_sh[0] = atomicAdd(args.counter, 1);
+      __syncthreads();
+      it = item_sh[0];
+    }
+    if (it >= args.n_items) break;
+    const WorkItem item = args.items[it];
+    const PatternDesc pd = args.pats[item.pattern];
+    const int n = pd.n, k = n >> 1;
+    const bool prob = args.modes != nullptr;
+    if (prob && tid < n) mlds[tid] = args.modes[pd.src + tid];
+    __syncthreads();
+    const bool staged = args.stage_A && n <= 32;
+    if (staged) {
+      for (int e = tid; e < n * n; e += NTH) {
+        const int i = e / n, j = e - (e / n) * n;
+        Alds[e] = prob ? args.A[(int64_t)mlds[i] * args.m + mlds[j]] : args.A[pd.src + e];
+      }
+    }
+    __syncthreads();
+    PatternView P;
+    P.lds = staged ? Alds : nullptr;
+    P.A = args.A;
+    P.modes = prob ? mlds : nullptr;
+    P.src = pd.src;
+    P.n = n;
+    P.m = args.m;
+    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
+    switch (k) {
+#define GBS_K_CASE(KK)                                                                            \
+  case KK:                                                                                        \
+    if constexpr (KK >= KLO && KK <= KHI)                                                         \
+      tile_range<KK, T>(P, item.lo, item.hi, pl, xbuf, tred, trw, sz, terms, tid, sr, si, cr, ci); \
+    break;
+      GBS_K_CASE(9) GBS_K_CASE(10) GBS_K_CASE(11) GBS_K_CASE(12) GBS_K_CASE(13) GBS_K_CASE(14)
+      GBS_K_CASE(15) GBS_K_CASE(16) GBS_K_CASE(17) GBS_K_CASE(18) GBS_K_CASE(19) GBS_K_CASE(20)
+      GBS_K_CASE(21) GBS_K_CASE(22) GBS_K_CASE(23)
+#undef GBS_K_CASE
+      default:
+        break;
+    }
+    if (tid == 0) {
+      gbs_partial p;
+      p.s_re = sr;
+      p.s_im = si;
+      p.c_re = cr;
+      p.c_im = ci;
+      args.partials[item.partial] = p;
+    }
+    if (!args.persistent) break;
+  }
+}
+
+}  // namespace gbs

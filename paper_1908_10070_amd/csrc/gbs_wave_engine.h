@@ -1,0 +1,451 @@
+// Register-resident subset engine for subsets with d = 2|Z| <= 32 (gfx950).
+//
+// One wave evaluates one subset at a time with no workgroup barriers:
+//   * M_Z = X A_Z is gathered straight into MFMA accumulator layout: a d x d complex matrix is a
+//     T x T grid (T = 1 or 2) of 16x16 FP64 tiles, each tile a pair (re, im) of 4-double registers;
+//     lane l = x + 16 y, register r of a tile holds element (row y + 4 r, column x) -- the output
+//     layout of v_mfma_f64_16x16x4f64. Entries beyond d are zero.
+//   * Every power Q of M_Z satisfies Q^t = X Q X (X swaps the two indices of each pair, and A_Z is
+//     symmetric). So Q[i][c] = Q[c^1][i^1], and the A operand of a product -- which needs Q by rows
+//     where the accumulator layout holds it by columns -- is the same register of the transposed
+//     tile read from lane l ^ 17 (x^1, y^1). The B operand is the accumulator register itself.
+//     A 16x16 complex product is then 4 register steps x 4 MFMAs with no LDS traffic.
+//   * tr(P Q) = sum_{i,c} P[i][c] Q[i^1][c^1] is, per lane, the product of P with Q read from lane
+//     l ^ 17; the k traces of a subset are reduced across the wave together with a butterfly.
+//   * The schedule (which powers, which traces) is the compile-time chain table for k, so slots and
+//     traces are plain registers.
+// A workgroup (4 waves) takes one work item -- a range of one pattern's canonical subset order --
+// stages the pattern matrix in LDS once (n <= 32), and gives each wave a contiguous quarter. Traces
+// of 32 subsets are buffered per wave; 32 lanes then run the coefficient recursion and one lane adds
+// the signed terms into a compensated running sum. The four wave partials are combined in wave
+// order, so an item's partial depends only on its range.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gbs_chain_table.h"
+#include "gbs_internal.h"
+
+namespace gbs {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaveG = 32;  // subsets buffered per wave before the coefficient step
+
+template <int T>
+struct CMat {
+  d4 r[T][T];
+  d4 i[T][T];
+};
+
+__device__ __forceinline__ double swap17(double v) { return __shfl_xor(v, 17, 64); }
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double pick(const d4& v, int r) {
+  double o = v[0];
+  o = r == 1 ? v[1] : o;
+  o = r == 2 ? v[2] : o;
+  o = r == 3 ? v[3] : o;
+  return o;
+}
+
+// Z = X Y (Z may alias X or Y).
+template <int T>
+__device__ __forceinline__ void cmul_mat(const CMat<T>& X, const CMat<T>& Y, CMat<T>& Z, int d) {
+  CMat<T> acc;
+#pragma unroll
+  for (int I = 0; I < T; ++I)
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      acc.r[I][J] = d4{0.0, 0.0, 0.0, 0.0};
+      acc.i[I][J] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+  for (int K = 0; K < T; ++K)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (16 * K + 4 * r < d) {  // register r of tile row K holds rows 16K + 4r .. 16K + 4r + 3
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+          const double ar = swap17(X.r[K][I][r]);
+          const double ai = swap17(X.i[K][I][r]);
+#pragma unroll
+          for (int J = 0; J < T; ++J) {
+            const double br = Y.r[K][J][r];
+            const double bi = Y.i[K][J][r];
+            acc.r[I][J] = mfma(ar, br, acc.r[I][J]);
+            acc.i[I][J] = mfma(ar, bi, acc.i[I][J]);
+            acc.r[I][J] = mfma(-ai, bi, acc.r[I][J]);
+            acc.i[I][J] = mfma(ai, br, acc.i[I][J]);
+          }
+        }
+      }
+    }
+  Z = acc;
+}
+
+// per-lane partial of tr(X): the diagonal element this lane holds, if any
+template <int T>
+__device__ __forceinline__ void tdiag(const CMat<T>& X, double2& t, int lane) {
+  const int x = lane & 15, y = lane >> 4;
+  if (x >= y && ((x - y) & 3) == 0) {
+    const int r = (x - y) >> 2;
+#pragma unroll
+    for (int I = 0; I < T; ++I) {
+      t.x += pick(X.r[I][I], r);
+      t.y += pick(X.i[I][I], r);
+    }
+  }
+}
+
+// per-lane partial of tr(X Y) = sum X[i][c] Y[i^1][c^1]
+template <int T>
+__device__ __forceinline__ void tpair(const CMat<T>& X, const CMat<T>& Y, double2& t) {
+#pragma unroll
+  for (int I = 0; I < T; ++I)
+#pragma unroll
+    for (int C = 0; C < T; ++C)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double yr = swap17(Y.r[I][C][r]);
+        const double yi = swap17(Y.i[I][C][r]);
+        const double xr = X.r[I][C][r], xi = X.i[I][C][r];
+        t.x = fma(xr, yr, t.x);
+        t.x = fma(-xi, yi, t.x);
+        t.y = fma(xr, yi, t.y);
+        t.y = fma(xi, yr, t.y);
+      }
+}
+
+template <int K, int T, int OI, int NS>
+__device__ __forceinline__ void run_ops(CMat<T> (&S)[NS], double2 (&tp)[K + 1], int d, int lane) {
+  if constexpr (OI < kChainTable[K].nops) {
+    constexpr Op op = kChainTable[K].ops[OI];
+    if constexpr (op.type == OP_MUL) {
+      cmul_mat<T>(S[op.a], S[op.b], S[op.x], d);
+    } else if constexpr (op.type == OP_TDIAG) {
+      tdiag<T>(S[op.a], tp[op.x], lane);
+    } else {
+      tpair<T>(S[op.a], S[op.b], tp[op.x]);
+    }
+    run_ops<K, T, OI + 1, NS>(S, tp, d, lane);
+  }
+}
+
+// Wave butterfly over the 2K partial trace components. Afterwards lanes with (lane & 7) == 0 hold
+// the wave totals; store(idx, v) is called there for component idx (t_{idx/2+1}, re/im = idx & 1).
+template <int K, typename Store>
+__device__ __forceinline__ void reduce_traces(const double2 (&tp)[K + 1], int lane, Store store) {
+  constexpr int V = 2 * K;
+  constexpr int VP = ((V + 7) / 8) * 8;
+  constexpr int H1 = VP / 2, H2 = VP / 4, H3 = VP / 8;
+  double v[VP];
+#pragma unroll
+  for (int j = 1; j <= K; ++j) {
+    v[2 * (j - 1)] = tp[j].x;
+    v[2 * (j - 1) + 1] = tp[j].y;
+  }
+#pragma unroll
+  for (int q = V; q < VP; ++q) v[q] = 0.0;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double w1[H1];
+#pragma unroll
+  for (int q = 0; q < H1; ++q) {
+    const double send = b5 ? v[q] : v[q + H1];
+    const double keep = b5 ? v[q + H1] : v[q];
+    w1[q] = keep + __shfl_xor(send, 32, 64);
+  }
+  double w2[H2];
+#pragma unroll
+  for (int q = 0; q < H2; ++q) {
+    const double send = b4 ? w1[q] : w1[q + H2];
+    const double keep = b4 ? w1[q + H2] : w1[q];
+    w2[q] = keep + __shfl_xor(send, 16, 64);
+  }
+  double w3[H3];
+#pragma unroll
+  for (int q = 0; q < H3; ++q) {
+    const double send = b3 ? w2[q] : w2[q + H3];
+    const double keep = b3 ? w2[q + H3] : w2[q];
+    w3[q] = keep + __shfl_xor(send, 8, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H3; ++q) {
+    w3[q] += __shfl_xor(w3[q], 4, 64);
+    w3[q] += __shfl_xor(w3[q], 2, 64);
+    w3[q] += __shfl_xor(w3[q], 1, 64);
+  }
+  if ((lane & 7) == 0) {
+    const int base = (b5 ? H1 : 0) + (b4 ? H2 : 0) + (b3 ? H3 : 0);
+#pragma unroll
+    for (int q = 0; q < H3; ++q) {
+      const int idx = base + q;
+      if (idx < V) store(idx, w3[q]);
+    }
+  }
+}
+
+struct PatternView {
+  const double2* lds;     // staged n x n matrix (row-major) or nullptr
+  const double2* A;       // global matrix (haf path) or B (prob path)
+  const int32_t* modes;   // LDS mode list (prob path) or nullptr
+  int64_t src;
+  int n, m;
+  __device__ __forceinline__ double2 at(int i, int j) const {
+    if (lds) return lds[i * n + j];
+    if (modes) return A[(int64_t)modes[i] * m + modes[j]];
+    return A[src + (int64_t)i * n + j];
+  }
+};
+
+// One subset: build M_Z, run the chain program, reduce the traces into the wave's buffer slot u.
+template <int K, int T>
+__device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t* pl, int d, double* trw, int u,
+                                            int lane) {
+  constexpr int NS = kChainTable[K].nslots;
+  CMat<T> S[NS];
+  const int x = lane & 15, y = lane >> 4;
+#pragma unroll
+  for (int I = 0; I < T; ++I)
+#pragma unroll
+    for (int J = 0; J < T; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * I + y + 4 * r;  // row of M_Z
+        const int c = 16 * J + x;          // column
+        double vr = 0.0, vi = 0.0;
+        if (a < d && c < d) {
+          const int b = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
+          const int ia = 2 * pl[b >> 1] + (b & 1);
+          const int ic = 2 * pl[c >> 1] + (c & 1);
+          const double2 e = P.at(ia, ic);
+          vr = e.x;
+          vi = e.y;
+        }
+        S[0].r[I][J][r] = vr;
+        S[0].i[I][J][r] = vi;
+      }
+  double2 tp[K + 1];
+#pragma unroll
+  for (int j = 0; j <= K; ++j) tp[j] = make_double2(0.0, 0.0);
+  run_ops<K, T, 0, NS>(S, tp, d, lane);
+  reduce_traces<K>(tp, lane, [&](int idx, double v) {
+    trw[((idx >> 1) + 1) * (2 * kWaveG) + 2 * u + (idx & 1)] = 0.5 * v;
+  });
+}
+
+__device__ __forceinline__ uint32_t unrank(int k, int64_t g, int* s_out) {
+  int s = 1;
+  uint64_t rem = (uint64_t)g;
+  while (s < k && rem >= c_tab.binom[k][s]) {
+    rem -= c_tab.binom[k][s];
+    ++s;
+  }
+  uint32_t mask = 0;
+  int c = k - 1;
+  for (int i = s; i >= 1; --i) {
+    while (c_tab.binom[c][i] > rem) --c;
+    mask |= 1u << c;
+    rem -= c_tab.binom[c][i];
+    --c;
+  }
+  *s_out = s;
+  return mask;
+}
+
+// Coefficient recursion for the buffered subsets (one lane each) and the compensated sum.
+template <int K>
+__device__ __forceinline__ void combine_batch(const double* trw, const int32_t* sz, double2* terms, int cnt, int lane,
+                                              double& sr, double& si, double& cr, double& ci) {
+  if (lane < cnt) {
+    double2 c[K + 1];
+    c[0] = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int q = 1; q <= K; ++q) {
+      double ar = 0.0, ai = 0.0;
+#pragma unroll
+      for (int j = 1; j <= q; ++j) {
+        const double tr = trw[j * (2 * kWaveG) + 2 * lane];
+        const double ti = trw[j * (2 * kWaveG) + 2 * lane + 1];
+        ar = fma(tr, c[q - j].x, ar);
+        ar = fma(-ti, c[q - j].y, ar);
+        ai = fma(tr, c[q - j].y, ai);
+        ai = fma(ti, c[q - j].x, ai);
+      }
+      const double iq = c_tab.inv[q];
+      c[q] = make_double2(ar * iq, ai * iq);
+    }
+    double2 ck = c[K];
+    if ((K - sz[lane]) & 1) {
+      ck.x = -ck.x;
+      ck.y = -ck.y;
+    }
+    terms[lane] = ck;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane == 0) {
+    for (int u = 0; u < cnt; ++u) {
+      neumaier(sr, cr, terms[u].x);
+      neumaier(si, ci, terms[u].y);
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The subsets [lo, hi) of one pattern, all with the same tile count T, on one wave.
+template <int K, int T>
+__device__ void wave_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double* trw, int32_t* sz,
+                           double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
+  for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
+    const int cnt = (int)((hi - g0) < kWaveG ? (hi - g0) : kWaveG);
+    for (int u = 0; u < cnt; ++u) {
+      int s;
+      const uint32_t mask = unrank(K, g0 + u, &s);
+      wave_sync();  // previous subset's pair list no longer read
+      if (lane < K && ((mask >> lane) & 1u)) pl[__popc(mask & ((1u << lane) - 1u))] = lane;
+      if (lane == 0) sz[u] = s;
+      wave_sync();
+      eval_subset<K, T>(P, pl, 2 * s, trw, u, lane);
+    }
+    wave_sync();
+    combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    wave_sync();
+  }
+}
+
+}  // namespace
+
+struct WaveLds {
+  size_t A, modes, pl, trw, sz, terms, part, item, total;
+};
+
+__host__ __device__ inline size_t wal16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ inline WaveLds wave_lds_layout(int nmax, int kmax, int stage_A) {
+  WaveLds L;
+  size_t off = 0;
+  L.A = off;
+  off += stage_A ? wal16(sizeof(double) * 2 * nmax * nmax) : 0;
+  L.modes = off;
+  off += wal16(sizeof(int32_t) * GBS_N_MAX);
+  L.pl = off;
+  off += wal16(sizeof(int32_t) * 4 * kMaxK);
+  L.trw = off;
+  off += wal16(sizeof(double) * 4 * (kmax + 1) * 2 * kWaveG);
+  L.sz = off;
+  off += wal16(sizeof(int32_t) * 4 * kWaveG);
+  L.terms = off;
+  off += wal16(sizeof(double) * 2 * 4 * kWaveG);
+  L.part = off;
+  off += wal16(sizeof(double) * 4 * 4);
+  L.item = off;
+  off += 16;
+  L.total = off;
+  return L;
+}
+
+template <int T, int KLO, int KHI>
+__global__ __launch_bounds__(kThreads) void wave_engine_kernel(EngineArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
+  double2* Alds = reinterpret_cast<double2*>(smem + L.A);
+  int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int32_t* pl = reinterpret_cast<int32_t*>(smem + L.pl) + wave * kMaxK;
+  double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
+  int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
+  double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
+  double* part = reinterpret_cast<double*>(smem + L.part);
+  int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
+
+  int it = args.persistent ? 0 : (int)blockIdx.x;
+  for (;;) {
+    if (args.persistent) {
+      __syncthreads();
+      if (tid == 0) item_sh[0] = atomicAdd(args.counter, 1);
+      __syncthreads();
+      it = item_sh[0];
+    }
+    if (it >= args.n_items) break;
+    const WorkItem item = args.items[it];
+    const PatternDesc pd = args.pats[item.pattern];
+    const int n = pd.n, k = n >> 1;
+    const bool prob = args.modes != nullptr;
+    if (prob && tid < n) mlds[tid] = args.modes[pd.src + tid];
+    __syncthreads();
+    const bool staged = args.stage_A && n <= 32;
+    if (staged) {
+      for (int e = tid; e < n * n; e += kThreads) {
+        const int i = e / n, j = e - (e / n) * n;
+        Alds[e] = prob ? args.A[(int64_t)mlds[i] * args.m + mlds[j]] : args.A[pd.src + e];
+      }
+    }
+    __syncthreads();
+    PatternView P;
+    P.lds = staged ? Alds : nullptr;
+    P.A = args.A;
+    P.modes = prob ? mlds : nullptr;
+    P.src = pd.src;
+    P.n = n;
+    P.m = args.m;
+
+    // this wave's quarter of the item
+    const int64_t len = item.hi - item.lo;
+    const int64_t q = (len + 3) / 4;
+    const int64_t lo = item.lo + q * wave < item.hi ? item.lo + q * wave : item.hi;
+    const int64_t hi = lo + q < item.hi ? lo + q : item.hi;
+    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
+    if (lo < hi) {
+      switch (k) {
+#define GBS_K_CASE(KK)                                                                   \
+  case KK:                                                                               \
+    if constexpr (KK >= KLO && KK <= KHI && (T == 1 || KK > 8))                          \
+      wave_range<KK, T>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);            \
+    break;
+        GBS_K_CASE(1) GBS_K_CASE(2) GBS_K_CASE(3) GBS_K_CASE(4) GBS_K_CASE(5) GBS_K_CASE(6)
+        GBS_K_CASE(7) GBS_K_CASE(8) GBS_K_CASE(9) GBS_K_CASE(10) GBS_K_CASE(11) GBS_K_CASE(12)
+        GBS_K_CASE(13) GBS_K_CASE(14) GBS_K_CASE(15) GBS_K_CASE(16) GBS_K_CASE(17) GBS_K_CASE(18)
+        GBS_K_CASE(19) GBS_K_CASE(20) GBS_K_CASE(21) GBS_K_CASE(22) GBS_K_CASE(23)
+#undef GBS_K_CASE
+        default:
+          break;
+      }
+    }
+    if (lane == 0) {
+      part[wave * 4 + 0] = sr;
+      part[wave * 4 + 1] = si;
+      part[wave * 4 + 2] = cr;
+      part[wave * 4 + 3] = ci;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double r0 = part[0], i0 = part[1], c0 = part[2], d0 = part[3];
+      for (int w = 1; w < 4; ++w) {
+        neumaier(r0, c0, part[w * 4 + 0]);
+        neumaier(i0, d0, part[w * 4 + 1]);
+        c0 += part[w * 4 + 2];
+        d0 += part[w * 4 + 3];
+      }
+      gbs_partial p;
+      p.s_re = r0;
+      p.s_im = i0;
+      p.c_re = c0;
+      p.c_im = d0;
+      args.partials[item.partial] = p;
+    }
+    if (!args.persistent) break;
+  }
+}
+
+}  // namespace gbs

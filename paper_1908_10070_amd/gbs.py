@@ -16,7 +16,7 @@ _HERE = pathlib.Path(__file__).resolve().parent
 LIB_PATH = _HERE / "libgbs.so"
 
 GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6)
-GBS_N_MAX = 48
+GBS_N_MAX = 46
 
 # Every function declared in include/gbs.h.
 EXPORTS = [

@@ -123,7 +123,7 @@ def test_all_ones_closed_form(ctx, torch_dev):
 
 def test_bipartite_is_permanent(ctx, torch_dev):
     """Haf([[0, W], [W^t, 0]]) = Per(W) (Ryser's formula, vectorised, as the reference)."""
-    for k in (5, 9, 12):
+    for k in (5, 9, 12, 14, 16):
         rng = np.random.default_rng(200 + k)
         W = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2)
         A = np.block([[np.zeros((k, k)), W], [W.T, np.zeros((k, k))]])
@@ -204,3 +204,23 @@ def test_invalid_inputs_raise(ctx, torch_dev):
     with pytest.raises(gbs.GBSError) as e:
         ctx.prob_batch(st, (np.array([0, 1, 2], np.int32), np.array([0, 2, 1], np.int64)))
     assert e.value.status == gbs.GBS_EINVAL
+
+
+@pytest.mark.parametrize("k", [17, 18, 20, 22])
+def test_bipartite_permanent_large(ctx, torch_dev, k):
+    """n = 34..44 (the 3x3-tile engine): Haf of the bipartite block matrix against Ryser's formula."""
+    rng = np.random.default_rng(300 + k)
+    W = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2)
+    A = np.block([[np.zeros((k, k)), W], [W.T, np.zeros((k, k))]])
+    h = ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
+    per = 0j
+    step = 1 << 16
+    cols = np.arange(k)
+    for s0 in range(1, 1 << k, step):
+        masks = np.arange(s0, min(1 << k, s0 + step))
+        sel = ((masks[:, None] >> cols[None, :]) & 1).astype(np.float64)
+        rows = sel @ W.T
+        per += np.sum((-1.0) ** sel.sum(axis=1) * np.prod(rows, axis=1))
+    per *= (-1) ** k
+    print(f"k={k} n={2*k} rel err {relerr(h, per):.3e}")
+    assert relerr(h, per) < 1e-8
