@@ -18,6 +18,8 @@
 //     item order, so the result depends only on n and the chunking, never on the batch around it.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "gbs_internal.h"
 
 namespace gbs {
@@ -163,36 +165,45 @@ int upload_tables(const ConstTables& t) {
 
 // Subset engines (same translation unit: they read c_tab).
 #include "gbs_wave_engine.h"
+#include "gbs_quad_engine.h"
 #include "gbs_tile_engine.h"
 
 namespace gbs {
 
-// Engine kernel variants. Register engine (one subset per wave, d <= 16): classes 0-2 by k range.
-// Tile engine (one subset per workgroup of T*T waves): T = 2 (16 < d <= 32) classes 3-5, T = 3
-// (32 < d <= 48) class 6. The k range bounds the register budget of each variant.
+// Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
+//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= 6, k = 1..23
+//   classes 23..39  register engine (one subset per wave, one 16x16 tile), |Z| = 7, 8, k = 7..23
+//   classes 40..54  tile engine T = 2 (2x2 tiles, 4 waves), 9 <= |Z| <= 16, k = 9..23
+//   classes 55..61  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
 struct EngineVariant {
   void (*fn)(EngineArgs);
   int threads;
   int tiles;
 };
 
+template <int C>
+static EngineVariant variant_c() {
+  if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, 1};
+  else if constexpr (C < 40) return {wave_engine_kernel<C - 23 + 7>, kThreads, 1};
+  else if constexpr (C < 55) return {tile_engine_kernel<2, C - 40 + 9>, 256, 2};
+  else return {tile_engine_kernel<3, C - 55 + 17>, 576, 3};
+}
+
+template <int... C>
+static EngineVariant variant_table(int cls, std::integer_sequence<int, C...>) {
+  static const EngineVariant tab[] = {variant_c<C>()...};
+  return (cls >= 0 && cls < (int)sizeof...(C)) ? tab[cls] : EngineVariant{nullptr, 0, 0};
+}
+
 static EngineVariant variant(int cls) {
-  switch (cls) {
-    case 0: return {wave_engine_kernel<1, 1, 12>, kThreads, 1};
-    case 1: return {wave_engine_kernel<1, 13, 16>, kThreads, 1};
-    case 2: return {wave_engine_kernel<1, 17, 23>, kThreads, 1};
-    case 3: return {tile_engine_kernel<2, 9, 12>, 256, 2};
-    case 4: return {tile_engine_kernel<2, 13, 16>, 256, 2};
-    case 5: return {tile_engine_kernel<2, 17, 23>, 256, 2};
-    case 6: return {tile_engine_kernel<3, 17, 23>, 576, 3};
-    default: return {nullptr, 0, 0};
-  }
+  return variant_table(cls, std::make_integer_sequence<int, kEngineClasses>{});
 }
 
 int engine_class(int s, int k) {
-  if (2 * s <= 16) return k <= 12 ? 0 : (k <= 16 ? 1 : 2);
-  if (2 * s <= 32) return k <= 12 ? 3 : (k <= 16 ? 4 : 5);
-  return 6;
+  if (s <= 6) return k - 1;
+  if (s <= 8) return 23 + (k - 7);
+  if (s <= 16) return 40 + (k - 9);
+  return 55 + (k - 17);
 }
 
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {

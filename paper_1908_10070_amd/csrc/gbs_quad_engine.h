@@ -1,0 +1,306 @@
+// Quad subset engine for small subsets (d = 2|Z| <= 12), gfx950.
+//
+// v_mfma_f64_4x4x4_4b_f64 computes four independent 4x4x4 products, one per block b = (lane >> 2) & 3.
+// Here each block carries a different subset: a wave evaluates four consecutive subsets of the
+// canonical order at once. A d x d complex matrix is a T4 x T4 grid (T4 = ceil(d/4) <= 3) of 4x4
+// tiles; one double register per tile holds, for block b, element (row y, column x) of that tile at
+// lane x + 4b + 16y -- the instruction's output (and B-operand) layout. As in the register engine,
+// every power Q of M_Z has Q[i][c] = Q[c^1][i^1], so the A operand of a product is the transposed
+// tile read from lane l ^ 17 (block bits untouched), and tr(P Q) pairs each tile with the same tile of
+// Q read from lane l ^ 17. The k traces of the four subsets are reduced with a butterfly over the 16
+// lanes of each block; all lanes store a share of the results.
+#pragma once
+
+namespace gbs {
+namespace {
+
+template <int T4>
+struct QMat {
+  double r[T4][T4];
+  double i[T4][T4];
+};
+
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int T4>
+__device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<T4>& Z) {
+  QMat<T4> acc;
+#pragma unroll
+  for (int I = 0; I < T4; ++I)
+#pragma unroll
+    for (int J = 0; J < T4; ++J) {
+      acc.r[I][J] = 0.0;
+      acc.i[I][J] = 0.0;
+    }
+#pragma unroll
+  for (int K = 0; K < T4; ++K)
+#pragma unroll
+    for (int I = 0; I < T4; ++I) {
+      const double ar = swap17(X.r[K][I]);
+      const double ai = swap17(X.i[K][I]);
+#pragma unroll
+      for (int J = 0; J < T4; ++J) {
+        acc.r[I][J] = mfma4(ar, Y.r[K][J], acc.r[I][J]);
+        acc.i[I][J] = mfma4(ar, Y.i[K][J], acc.i[I][J]);
+        acc.r[I][J] = mfma4(-ai, Y.i[K][J], acc.r[I][J]);
+        acc.i[I][J] = mfma4(ai, Y.r[K][J], acc.i[I][J]);
+      }
+    }
+  Z = acc;
+}
+
+template <int T4>
+__device__ __forceinline__ void qdiag(const QMat<T4>& X, double2& t, int lane) {
+  if ((lane & 3) == (lane >> 4)) {
+#pragma unroll
+    for (int I = 0; I < T4; ++I) {
+      t.x += X.r[I][I];
+      t.y += X.i[I][I];
+    }
+  }
+}
+
+template <int T4>
+__device__ __forceinline__ void qpair(const QMat<T4>& X, const QMat<T4>& Y, double2& t) {
+#pragma unroll
+  for (int I = 0; I < T4; ++I)
+#pragma unroll
+    for (int C = 0; C < T4; ++C) {
+      const double yr = swap17(Y.r[I][C]);
+      const double yi = swap17(Y.i[I][C]);
+      t.x = fma(X.r[I][C], yr, t.x);
+      t.x = fma(-X.i[I][C], yi, t.x);
+      t.y = fma(X.r[I][C], yi, t.y);
+      t.y = fma(X.i[I][C], yr, t.y);
+    }
+}
+
+template <int K, int T4, int OI, int NS>
+__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double2 (&tp)[K + 1], int lane) {
+  if constexpr (OI < kChainTable[K].nops) {
+    constexpr Op op = kChainTable[K].ops[OI];
+    if constexpr (op.type == OP_MUL) {
+      qmul<T4>(S[op.a], S[op.b], S[op.x]);
+    } else if constexpr (op.type == OP_TDIAG) {
+      qdiag<T4>(S[op.a], tp[op.x], lane);
+    } else {
+      qpair<T4>(S[op.a], S[op.b], tp[op.x]);
+    }
+    run_ops_quad<K, T4, OI + 1, NS>(S, tp, lane);
+  }
+}
+
+// Butterfly over lane bits 5, 4, 1, 0 (the 16 lanes of a block); store(idx, v) for component idx
+// of this lane's block.
+template <int K, typename Store>
+__device__ __forceinline__ void reduce_traces_quad(const double2 (&tp)[K + 1], int lane, Store store) {
+  constexpr int V = 2 * K;
+  constexpr int VP = ((V + 15) / 16) * 16;
+  constexpr int H1 = VP / 2, H2 = VP / 4, H3 = VP / 8, H4 = VP / 16;
+  double v[VP];
+#pragma unroll
+  for (int j = 1; j <= K; ++j) {
+    v[2 * (j - 1)] = tp[j].x;
+    v[2 * (j - 1) + 1] = tp[j].y;
+  }
+#pragma unroll
+  for (int q = V; q < VP; ++q) v[q] = 0.0;
+  const bool b5 = lane & 32, b4 = lane & 16, b1 = lane & 2, b0 = lane & 1;
+  double w1[H1], w2[H2], w3[H3], w4[H4];
+#pragma unroll
+  for (int q = 0; q < H1; ++q) {
+    const double send = b5 ? v[q] : v[q + H1];
+    const double keep = b5 ? v[q + H1] : v[q];
+    w1[q] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H2; ++q) {
+    const double send = b4 ? w1[q] : w1[q + H2];
+    const double keep = b4 ? w1[q + H2] : w1[q];
+    w2[q] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H3; ++q) {
+    const double send = b1 ? w2[q] : w2[q + H3];
+    const double keep = b1 ? w2[q + H3] : w2[q];
+    w3[q] = keep + __shfl_xor(send, 2, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H4; ++q) {
+    const double send = b0 ? w3[q] : w3[q + H4];
+    const double keep = b0 ? w3[q + H4] : w3[q];
+    w4[q] = keep + __shfl_xor(send, 1, 64);
+  }
+  const int base = (b5 ? H1 : 0) + (b4 ? H2 : 0) + (b1 ? H3 : 0) + (b0 ? H4 : 0);
+#pragma unroll
+  for (int q = 0; q < H4; ++q) {
+    const int idx = base + q;
+    if (idx < V) store(idx, w4[q]);
+  }
+}
+
+// Four subsets (one per block) with matrices of at most 4*T4 rows.
+template <int K, int T4>
+__device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* pl4, int d_b, bool valid_b, double* trw,
+                                          int u_b, int lane) {
+  constexpr int NS = kChainTable[K].nslots;
+  const int b = (lane >> 2) & 3;
+  const int x = lane & 3, y = lane >> 4;
+  const int32_t* pl = pl4 + b * kMaxK;
+  QMat<T4> S[NS];
+#pragma unroll
+  for (int I = 0; I < T4; ++I)
+#pragma unroll
+    for (int J = 0; J < T4; ++J) {
+      const int a = 4 * I + y, c = 4 * J + x;
+      double vr = 0.0, vi = 0.0;
+      if (valid_b && a < d_b && c < d_b) {
+        const int bb = a ^ 1;
+        const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
+        vr = e.x;
+        vi = e.y;
+      }
+      S[0].r[I][J] = vr;
+      S[0].i[I][J] = vi;
+    }
+  double2 tp[K + 1];
+#pragma unroll
+  for (int j = 0; j <= K; ++j) tp[j] = make_double2(0.0, 0.0);
+  run_ops_quad<K, T4, 0, NS>(S, tp, lane);
+  reduce_traces_quad<K>(tp, lane, [&](int idx, double v) {
+    if (valid_b) trw[((idx >> 1) + 1) * (2 * kWaveG) + 2 * u_b + (idx & 1)] = 0.5 * v;
+  });
+}
+
+// Subsets [lo, hi) of one pattern (all with |Z| <= 6) on one wave, four at a time.
+template <int K>
+__device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl4, double* trw, int32_t* sz,
+                           double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
+  const int b = (lane >> 2) & 3;
+  int s = 1;
+  uint32_t mask = lo < hi ? unrank(K, lo, &s) : 0u;
+  for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
+    const int cnt = (int)((hi - g0) < kWaveG ? (hi - g0) : kWaveG);
+    for (int u0 = 0; u0 < cnt; u0 += 4) {
+      // masks and sizes of the four subsets u0 .. u0+3 (uniform across the wave)
+      uint32_t m4[4];
+      int s4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (u0 + q > 0 || g0 > lo) {
+          if (u0 + q < cnt) mask = next_subset(mask, K, &s);
+        }
+        m4[q] = mask;
+        s4[q] = s;
+      }
+      const int nv = cnt - u0 < 4 ? cnt - u0 : 4;
+      wave_sync();
+      // pair lists: element e < 4K of the (list, pair) grid is list e / K, pair e % K (4K may exceed 64)
+      for (int e = lane; e < 4 * K; e += 64) {
+        const int q = e / K, t = e - (e / K) * K;
+        const uint32_t mq = m4[0] * (q == 0) + m4[1] * (q == 1) + m4[2] * (q == 2) + m4[3] * (q == 3);
+        if (q < nv && ((mq >> t) & 1u)) pl4[q * kMaxK + __popc(mq & ((1u << t) - 1u))] = t;
+      }
+      if (lane < nv) sz[u0 + lane] = lane == 0 ? s4[0] : (lane == 1 ? s4[1] : (lane == 2 ? s4[2] : s4[3]));
+      wave_sync();
+      int smax = s4[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (q < nv && s4[q] > smax) smax = s4[q];
+      const int d_b = 2 * (b == 0 ? s4[0] : (b == 1 ? s4[1] : (b == 2 ? s4[2] : s4[3])));
+      const bool valid_b = b < nv;
+      const int u_b = u0 + b;
+      if (smax <= 2)
+        eval_quad<K, 1>(P, pl4, d_b, valid_b, trw, u_b, lane);
+      else if (smax <= 4)
+        eval_quad<K, 2>(P, pl4, d_b, valid_b, trw, u_b, lane);
+      else
+        eval_quad<K, 3>(P, pl4, d_b, valid_b, trw, u_b, lane);
+    }
+    wave_sync();
+    combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    wave_sync();
+  }
+}
+
+}  // namespace
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void quad_engine_kernel(EngineArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
+  double2* Alds = reinterpret_cast<double2*>(smem + L.A);
+  int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int32_t* pl4 = reinterpret_cast<int32_t*>(smem + L.pl) + wave * 4 * kMaxK;
+  double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
+  int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
+  double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
+  double* part = reinterpret_cast<double*>(smem + L.part);
+  int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
+
+  int it = args.persistent ? 0 : (int)blockIdx.x;
+  for (;;) {
+    if (args.persistent) {
+      __syncthreads();
+      if (tid == 0) item_sh[0] = atomicAdd(args.counter, 1);
+      __syncthreads();
+      it = item_sh[0];
+    }
+    if (it >= args.n_items) break;
+    const WorkItem item = args.items[it];
+    const PatternDesc pd = args.pats[item.pattern];
+    const int n = pd.n, k = n >> 1;
+    const bool prob = args.modes != nullptr;
+    if (prob && tid < n) mlds[tid] = args.modes[pd.src + tid];
+    __syncthreads();
+    const bool staged = args.stage_A && n <= 32;
+    if (staged) {
+      for (int e = tid; e < n * n; e += kThreads) {
+        const int i = e / n, j = e - (e / n) * n;
+        Alds[e] = prob ? args.A[(int64_t)mlds[i] * args.m + mlds[j]] : args.A[pd.src + e];
+      }
+    }
+    __syncthreads();
+    PatternView P;
+    P.lds = staged ? Alds : nullptr;
+    P.A = args.A;
+    P.modes = prob ? mlds : nullptr;
+    P.src = pd.src;
+    P.n = n;
+    P.m = args.m;
+    const int64_t len = item.hi - item.lo;
+    const int64_t q = (len + 3) / 4;
+    const int64_t lo = item.lo + q * wave < item.hi ? item.lo + q * wave : item.hi;
+    const int64_t hi = lo + q < item.hi ? lo + q : item.hi;
+    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
+    if (lo < hi && k == K) quad_range<K>(P, lo, hi, pl4, trw, sz, terms, lane, sr, si, cr, ci);
+    if (lane == 0) {
+      part[wave * 4 + 0] = sr;
+      part[wave * 4 + 1] = si;
+      part[wave * 4 + 2] = cr;
+      part[wave * 4 + 3] = ci;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double r0 = part[0], i0 = part[1], c0 = part[2], d0 = part[3];
+      for (int w = 1; w < 4; ++w) {
+        neumaier(r0, c0, part[w * 4 + 0]);
+        neumaier(i0, d0, part[w * 4 + 1]);
+        c0 += part[w * 4 + 2];
+        d0 += part[w * 4 + 3];
+      }
+      gbs_partial p;
+      p.s_re = r0;
+      p.s_im = i0;
+      p.c_re = c0;
+      p.c_im = d0;
+      args.partials[item.partial] = p;
+    }
+    if (!args.persistent) break;
+  }
+}
+
+}  // namespace gbs

@@ -181,27 +181,25 @@ struct Plan {
   int nmax = 0, kmax = 0;
 };
 
-// Split [lo, hi) of pattern p into items at the engine boundaries and the chunk sizes:
-// |Z| <= 8 (one 16x16 tile), 8 < |Z| <= 16 (2x2 tiles; both on the register engine) and
-// |Z| > 16 (workgroup engine with LDS-resident powers).
 struct ItemLists {
   std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
 };
 
-// Split [lo, hi) of pattern p into items: ranges of equal engine variant (subset sizes |Z| <= 8,
-// 9..16, >= 17 use one, 2x2 and 3x3 tiles), cut into chunks.
+// Split [lo, hi) of pattern p into items: ranges of equal engine variant (subset sizes |Z| <= 6 on
+// the quad engine, 7..8 on the one-tile register engine, 9..16 and >= 17 on the 2x2 and 3x3 tile
+// engines), cut into chunks.
 void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L, int p, int n, int64_t lo,
                 int64_t hi) {
   if (hi <= lo) return;
   const int k = n / 2;
   int64_t cs, cl;
   chunks_for(ctx, n, &cs, &cl);
-  const int bounds[3][2] = {{1, 8}, {9, 16}, {17, kMaxK}};
+  const int bounds[4][2] = {{1, 6}, {7, 8}, {9, 16}, {17, kMaxK}};
   for (const auto& bd : bounds) {
     if (bd[0] > k) break;
     const int64_t a = std::max(lo, size_start(t, k, bd[0]));
     const int64_t b = std::min(hi, size_start(t, k, std::min(bd[1], k) + 1));
-    const int64_t chunk = bd[0] == 1 ? cs : cl;
+    const int64_t chunk = bd[0] <= 7 ? cs : cl;
     std::vector<WorkItem>& out = L.cls[engine_class(bd[0], k)];
     for (int64_t x = a; x < b; x += chunk) {
       WorkItem w;
@@ -221,8 +219,7 @@ void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L
 void order_items(Plan& pl, ItemLists& L) {
   pl.items.clear();
   pl.groups.clear();
-  const int order[kEngineClasses] = {6, 5, 4, 3, 2, 1, 0};
-  for (int cls : order) {
+  for (int cls = kEngineClasses - 1; cls >= 0; --cls) {
     std::vector<WorkItem>& v = L.cls[cls];
     if (v.empty()) continue;
     std::stable_sort(v.begin(), v.end(), [&](const WorkItem& a, const WorkItem& b) {

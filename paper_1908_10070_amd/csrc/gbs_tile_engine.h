@@ -95,11 +95,12 @@ __device__ void tile_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
                            double& ci) {
   constexpr int NT = T * T;
   const int w = tid >> 6, lane = tid & 63;
+  int s = 1;
+  uint32_t mask = lo < hi ? unrank(K, lo, &s) : 0u;
   for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
     const int cnt = (int)((hi - g0) < kWaveG ? (hi - g0) : kWaveG);
     for (int u = 0; u < cnt; ++u) {
-      int s;
-      const uint32_t mask = unrank(K, g0 + u, &s);
+      if (u > 0 || g0 > lo) mask = next_subset(mask, K, &s);
       __syncthreads();  // previous subset done with the pair list and tred
       if (tid < K && ((mask >> tid) & 1u)) pl[__popc(mask & ((1u << tid) - 1u))] = tid;
       if (tid == 0) sz[u] = s;
@@ -150,7 +151,7 @@ __host__ __device__ inline TileLds tile_lds_layout(int T, int nmax, int kmax, in
   return L;
 }
 
-template <int T, int KLO, int KHI>
+template <int T, int K>
 __global__ __launch_bounds__(T * T * 64) void tile_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NTH = T * T * 64;
@@ -197,19 +198,7 @@ __global__ __launch_bounds__(T * T * 64) void tile_engine_kernel(EngineArgs args
     P.n = n;
     P.m = args.m;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    switch (k) {
-#define GBS_K_CASE(KK)                                                                            \
-  case KK:                                                                                        \
-    if constexpr (KK >= KLO && KK <= KHI)                                                         \
-      tile_range<KK, T>(P, item.lo, item.hi, pl, xbuf, tred, trw, sz, terms, tid, sr, si, cr, ci); \
-    break;
-      GBS_K_CASE(9) GBS_K_CASE(10) GBS_K_CASE(11) GBS_K_CASE(12) GBS_K_CASE(13) GBS_K_CASE(14)
-      GBS_K_CASE(15) GBS_K_CASE(16) GBS_K_CASE(17) GBS_K_CASE(18) GBS_K_CASE(19) GBS_K_CASE(20)
-      GBS_K_CASE(21) GBS_K_CASE(22) GBS_K_CASE(23)
-#undef GBS_K_CASE
-      default:
-        break;
-    }
+    if (k == K) tile_range<K, T>(P, item.lo, item.hi, pl, xbuf, tred, trw, sz, terms, tid, sr, si, cr, ci);
     if (tid == 0) {
       gbs_partial p;
       p.s_re = sr;

@@ -257,6 +257,17 @@ __device__ __forceinline__ uint32_t unrank(int k, int64_t g, int* s_out) {
   return mask;
 }
 
+// Next subset in canonical order: the next larger bitmask with the same popcount (Gosper's
+// construction), or the smallest mask of the next size once the current size is exhausted.
+__device__ __forceinline__ uint32_t next_subset(uint32_t mask, int k, int* s) {
+  const uint32_t low = mask & (0u - mask);
+  const uint32_t ripple = mask + low;
+  const uint32_t nxt = (((ripple ^ mask) >> 2) >> __builtin_ctz(mask)) | ripple;
+  if (ripple != 0u && nxt < (1u << k)) return nxt;
+  *s += 1;
+  return (1u << *s) - 1u;
+}
+
 // Coefficient recursion for the buffered subsets (one lane each) and the compensated sum.
 template <int K>
 __device__ __forceinline__ void combine_batch(const double* trw, const int32_t* sz, double2* terms, int cnt, int lane,
@@ -307,11 +318,12 @@ __device__ __forceinline__ void wave_sync() {
 template <int K, int T>
 __device__ void wave_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double* trw, int32_t* sz,
                            double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
+  int s = 1;
+  uint32_t mask = lo < hi ? unrank(K, lo, &s) : 0u;
   for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
     const int cnt = (int)((hi - g0) < kWaveG ? (hi - g0) : kWaveG);
     for (int u = 0; u < cnt; ++u) {
-      int s;
-      const uint32_t mask = unrank(K, g0 + u, &s);
+      if (u > 0 || g0 > lo) mask = next_subset(mask, K, &s);
       wave_sync();  // previous subset's pair list no longer read
       if (lane < K && ((mask >> lane) & 1u)) pl[__popc(mask & ((1u << lane) - 1u))] = lane;
       if (lane == 0) sz[u] = s;
@@ -340,7 +352,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(int nmax, int kmax, int stage
   L.modes = off;
   off += wal16(sizeof(int32_t) * GBS_N_MAX);
   L.pl = off;
-  off += wal16(sizeof(int32_t) * 4 * kMaxK);
+  off += wal16(sizeof(int32_t) * 16 * kMaxK);  // four pair lists per wave (quad engine)
   L.trw = off;
   off += wal16(sizeof(double) * 4 * (kmax + 1) * 2 * kWaveG);
   L.sz = off;
@@ -355,7 +367,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(int nmax, int kmax, int stage
   return L;
 }
 
-template <int T, int KLO, int KHI>
+template <int K>
 __global__ __launch_bounds__(kThreads) void wave_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
@@ -406,22 +418,7 @@ __global__ __launch_bounds__(kThreads) void wave_engine_kernel(EngineArgs args) 
     const int64_t lo = item.lo + q * wave < item.hi ? item.lo + q * wave : item.hi;
     const int64_t hi = lo + q < item.hi ? lo + q : item.hi;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    if (lo < hi) {
-      switch (k) {
-#define GBS_K_CASE(KK)                                                                   \
-  case KK:                                                                               \
-    if constexpr (KK >= KLO && KK <= KHI && (T == 1 || KK > 8))                          \
-      wave_range<KK, T>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);            \
-    break;
-        GBS_K_CASE(1) GBS_K_CASE(2) GBS_K_CASE(3) GBS_K_CASE(4) GBS_K_CASE(5) GBS_K_CASE(6)
-        GBS_K_CASE(7) GBS_K_CASE(8) GBS_K_CASE(9) GBS_K_CASE(10) GBS_K_CASE(11) GBS_K_CASE(12)
-        GBS_K_CASE(13) GBS_K_CASE(14) GBS_K_CASE(15) GBS_K_CASE(16) GBS_K_CASE(17) GBS_K_CASE(18)
-        GBS_K_CASE(19) GBS_K_CASE(20) GBS_K_CASE(21) GBS_K_CASE(22) GBS_K_CASE(23)
-#undef GBS_K_CASE
-        default:
-          break;
-      }
-    }
+    if (lo < hi && k == K) wave_range<K, 1>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);
     if (lane == 0) {
       part[wave * 4 + 0] = sr;
       part[wave * 4 + 1] = si;
