@@ -47,6 +47,70 @@ def cpu_baseline(A, n_per_core=12):
                       f"{cores} worker processes, {wall:.1f} s wall"}
 
 
+def _timed(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def extras(gbs, torch, dev, args):
+    """Probability throughput (configs 1 and 3) and served-request latency (config 4)."""
+    from paper_1908_10070_amd import inputs, serve
+
+    out = {}
+    ctx = gbs.Context(0)
+    # config 1: m = 16, all 12,870 eight-photon patterns plus the vacuum
+    st1_in, pats1 = inputs.config1()
+    st1 = ctx.state(torch.from_numpy(st1_in.U).to(dev), st1_in.r)
+    allp = np.concatenate([np.zeros((0, 8), np.int32), pats1])
+    t = _timed(lambda: ctx.prob_batch(st1, allp))
+    out["config1"] = {"probs_per_s": len(allp) / t, "ms": t * 1e3, "patterns": int(len(allp))}
+    # config 3: m = 50, r = 0.88, 100,000 twenty-photon patterns
+    st3_in, pats3 = inputs.config3()
+    st3 = ctx.state(torch.from_numpy(st3_in.U).to(dev), st3_in.r)
+    prob = torch.empty(len(pats3), dtype=torch.float64, device=dev)
+    t = _timed(lambda: ctx.prob_batch(st3, pats3, prob_out=prob))
+    f20 = gbs.haf_flops(20)
+    out["config3"] = {"probs_per_s": len(pats3) / t, "ms": t * 1e3, "patterns": int(len(pats3)),
+                      "tflops": f20 * len(pats3) / t / 1e12, "frac_fp64_peak": f20 * len(pats3) / t / 1e12 / FP64_PEAK_TFLOPS}
+    # config 4: served mixed stream on the config-3 state
+    nreq = args.serve_requests
+    warm = max(nreq // 10, 50)
+    mix_rng = np.random.default_rng(3004)
+    mix = [inputs.collision_free_patterns(50, int(2 * mix_rng.integers(4, 17)), 1, mix_rng)[0] for _ in range(2000)]
+    t = _timed(lambda: ctx.prob_batch(st3, mix), reps=2)
+    capacity = len(mix) / t
+    srv_out = {"batched_capacity_req_s": capacity}
+    for load in (0.5,):
+        rate = load * capacity
+        arr, pats = inputs.config4_requests(nreq + warm, rate)
+        be = serve.GpuBackend(ctx, st3, pool_entries=1 << 16)
+        cont = serve.Server(be, pool_entries=1 << 16, step_flops=2e11, max_slice=4096).start()
+        serve.replay(cont, arr, pats)
+        cont.stop()
+        lat_c = np.array(cont.latencies[warm:]) * 1e3
+        pp = gbs.Context(0, use_graph=False, persistent=False)
+        fifo = serve.FifoServer(pp, st3).start()
+        serve.replay(fifo, arr, pats)
+        fifo.stop(timeout=600)
+        lat_f = np.array(fifo.latencies[warm:]) * 1e3
+        srv_out[f"load_{load}"] = {
+            "arrival_rate_req_s": rate, "requests": nreq, "warmup_requests": warm,
+            "continuous": {"p50_ms": float(np.percentile(lat_c, 50)), "p99_ms": float(np.percentile(lat_c, 99)),
+                           "mean_ms": float(lat_c.mean()), "throughput_req_s": cont.stats()["throughput_req_s"],
+                           "steps": cont.steps},
+            "fifo_per_pattern": {"p50_ms": float(np.percentile(lat_f, 50)), "p99_ms": float(np.percentile(lat_f, 99)),
+                                 "mean_ms": float(lat_f.mean()), "throughput_req_s": fifo.stats()["throughput_req_s"]},
+        }
+    out["config4_serving"] = srv_out
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-pattern", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the probability and serving measurements")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -126,6 +192,9 @@ def main():
 
     if cpu is not None:
         res["cpu_baseline"] = cpu
+
+    if not args.no_extras:
+        res["extras"] = extras(gbs, torch, dev, args)
 
     print(json.dumps(res))
 

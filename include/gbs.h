@@ -150,20 +150,24 @@ int gbs_prob_batch(gbs_ctx* ctx, const gbs_state* state, const int32_t* modes_ho
 int64_t gbs_subset_count(int32_t n);
 
 /* Partial sums of the subset terms over index ranges [lo_host[b], hi_host[b]) of pattern b
- * (0 <= lo <= hi <= gbs_subset_count(n)). partials_dev[b] receives the compensated partial.
+ * (0 <= lo <= hi <= gbs_subset_count(n)). Slice b's compensated partial is written to
+ * partials_dev[out_idx_host ? out_idx_host[b] : b] (indices >= 0; the caller sizes partials_dev).
  * Summing the partials of consecutive ranges covering [0, count) with gbs_finalize gives the
- * pattern's hafnian. Patterns as in gbs_prob_batch. */
+ * pattern's hafnian; a slice's partial depends only on the pattern and its range, so a scheduler
+ * may split one pattern over several calls. Patterns as in gbs_prob_batch. */
 int gbs_prob_slices(gbs_ctx* ctx, const gbs_state* state, const int32_t* modes_host,
                     const int64_t* offsets_host, const int64_t* lo_host, const int64_t* hi_host,
-                    int64_t batch, gbs_partial* partials_dev, void* stream);
+                    int64_t batch, gbs_partial* partials_dev, const int64_t* out_idx_host, void* stream);
 
-/* Combine partials: pattern b owns partials_dev[part_off_host[b] .. part_off_host[b+1]), summed in
- * that order with compensation. n_host[b] is its photon number, sfact_host[b] its prod_j s_j!.
+/* Combine partials: pattern b's partials are partials_dev[part_lo_host[b] .. part_hi_host[b]),
+ * summed in that order with compensation (ranges may be anywhere in partials_dev and may differ in
+ * length). n_host[b] is its photon number, sfact_host[b] its prod_j s_j!.
  * haf_out_dev[b] = sum (1 for n = 0, 0 for odd n); prob_out_dev[b] = prefactor |haf|^2 / sfact
- * (prefactor taken from `state`; prob_out_dev may be NULL, then state may be NULL). */
+ * (prefactor from `state`). Either output may be NULL; prob_out_dev needs a state and sfact_host. */
 int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partials_dev,
-                 const int64_t* part_off_host, const int32_t* n_host, const double* sfact_host,
-                 int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev, void* stream);
+                 const int64_t* part_lo_host, const int64_t* part_hi_host, const int32_t* n_host,
+                 const double* sfact_host, int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev,
+                 void* stream);
 
 #ifdef __cplusplus
 }

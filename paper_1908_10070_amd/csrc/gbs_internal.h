@@ -68,7 +68,8 @@ struct EngineArgs {
 
 struct FinalizeArgs {
   const gbs_partial* partials;
-  const int64_t* part_off;    // batch + 1
+  const int64_t* part_lo;     // pattern b sums partials[part_lo[b] .. part_hi[b])
+  const int64_t* part_hi;
   const int32_t* n;           // photon number per pattern
   const double* sfact;        // prod_j s_j! per pattern (prob path)
   const double* prefactor;    // 1 / prod cosh r_i (device scalar), or nullptr
@@ -76,6 +77,7 @@ struct FinalizeArgs {
   double* prob_out;           // nullable
   double2* haf_out;           // nullable
   gbs_partial* partial_out;   // nullable: write the combined compensated partial instead
+  const int64_t* out_idx;     // nullable: partial b goes to partial_out[out_idx[b]]
 };
 
 // Host-side launchers (defined in gbs_kernels.hip).

@@ -45,15 +45,6 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = t;
 }
 
-__device__ __forceinline__ double2 wave_sum(double2 v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
-  }
-  return v;
-}
-
 // Canonical subset order for k pairs: all subsets of size 1, then size 2, ...; within a size,
 // increasing bitmask (colexicographic order of the pair sets).
 __device__ __forceinline__ uint32_t unrank_subset(int k, int64_t g, int* s_out) {
@@ -81,7 +72,7 @@ __global__ void finalize_kernel(FinalizeArgs a) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < a.batch;
        b += (int64_t)gridDim.x * blockDim.x) {
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    for (int64_t q = a.part_off[b]; q < a.part_off[b + 1]; ++q) {
+    for (int64_t q = a.part_lo[b]; q < a.part_hi[b]; ++q) {
       const gbs_partial p = a.partials[q];
       neumaier(sr, cr, p.s_re);
       neumaier(si, ci, p.s_im);
@@ -94,7 +85,7 @@ __global__ void finalize_kernel(FinalizeArgs a) {
       o.s_im = si;
       o.c_re = cr;
       o.c_im = ci;
-      a.partial_out[b] = o;
+      a.partial_out[a.out_idx ? a.out_idx[b] : b] = o;
       continue;
     }
     const int n = a.n[b];

@@ -177,6 +177,7 @@ struct Plan {
   std::vector<int64_t> part_off;  // batch + 1 (finalize groups)
   std::vector<int32_t> nvec;
   std::vector<double> sfact;
+  std::vector<int64_t> out_idx;  // optional destination index per finalize group
   int64_t n_partials = 0;
   int nmax = 0, kmax = 0;
 };
@@ -235,7 +236,7 @@ void order_items(Plan& pl, ItemLists& L) {
 }
 
 struct Layout {
-  size_t counter, modes, pats, items, part_off, nvec, sfact, partials, total, staged_bytes;
+  size_t counter, modes, pats, items, part_off, nvec, sfact, out_idx, partials, total, staged_bytes;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -258,6 +259,8 @@ Layout layout_for(const Plan& pl, size_t n_modes) {
   off += al(sizeof(int32_t) * pl.nvec.size());
   L.sfact = off;
   off += al(sizeof(double) * pl.sfact.size());
+  L.out_idx = off;
+  off += al(sizeof(int64_t) * pl.out_idx.size());
   L.staged_bytes = off - stage_begin;
   L.partials = off;
   off += al(sizeof(gbs_partial) * (size_t)pl.n_partials);
@@ -327,6 +330,8 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   std::memcpy(h + (L.part_off - base), pl.part_off.data(), sizeof(int64_t) * pl.part_off.size());
   if (!pl.nvec.empty()) std::memcpy(h + (L.nvec - base), pl.nvec.data(), sizeof(int32_t) * pl.nvec.size());
   if (!pl.sfact.empty()) std::memcpy(h + (L.sfact - base), pl.sfact.data(), sizeof(double) * pl.sfact.size());
+  if (!pl.out_idx.empty())
+    std::memcpy(h + (L.out_idx - base), pl.out_idx.data(), sizeof(int64_t) * pl.out_idx.size());
 
   unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
   if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(stream, ctx->done_ev, 0));
@@ -372,7 +377,8 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
 
   FinalizeArgs fa{};
   fa.partials = ea.partials;
-  fa.part_off = reinterpret_cast<const int64_t*>(ws + L.part_off);
+  fa.part_lo = reinterpret_cast<const int64_t*>(ws + L.part_off);
+  fa.part_hi = fa.part_lo + 1;
   fa.n = reinterpret_cast<const int32_t*>(ws + L.nvec);
   fa.sfact = reinterpret_cast<const double*>(ws + L.sfact);
   fa.prefactor = prefactor_dev;
@@ -380,6 +386,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   fa.prob_out = prob_out;
   fa.haf_out = haf_out;
   fa.partial_out = partial_out;
+  fa.out_idx = pl.out_idx.empty() ? nullptr : reinterpret_cast<const int64_t*>(ws + L.out_idx);
 
   auto enqueue = [&](hipStream_t s) {
     if (ctx->persistent && !launches.empty()) launch_reset(counters, (int)launches.size(), s);
@@ -392,7 +399,8 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
     key.v = {ea.nmax, ea.kmax, ea.stage_A, ea.persistent, (int64_t)(intptr_t)A,
              (int64_t)(intptr_t)ea.modes, m, fa.batch, (int64_t)(intptr_t)prefactor_dev, (int64_t)(intptr_t)prob_out,
              (int64_t)(intptr_t)haf_out, (int64_t)(intptr_t)partial_out, (int64_t)(intptr_t)ctx->ws, (int64_t)L.pats,
-             (int64_t)L.items, (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact};
+             (int64_t)L.items, (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact,
+             (int64_t)L.out_idx, (int64_t)pl.out_idx.size()};
     for (const Launch& ln : launches) {
       key.v.push_back(ln.cls);
       key.v.push_back(ln.grid);
@@ -685,7 +693,7 @@ namespace {
 
 int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, const int64_t* offsets_host,
                 int64_t batch, const int64_t* lo_host, const int64_t* hi_host, double* prob_out, double2* haf_out,
-                gbs_partial* partial_out, hipStream_t stream) {
+                gbs_partial* partial_out, const int64_t* out_idx_host, hipStream_t stream) {
   ctx->last_error.clear();
   if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
   if (batch == 0) return GBS_OK;
@@ -726,6 +734,11 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
     pl.part_off[b + 1] = pl.n_partials;
   }
   order_items(pl, lists);
+  if (out_idx_host) {
+    for (int64_t b = 0; b < batch; ++b)
+      if (out_idx_host[b] < 0) return fail(ctx, GBS_EINVAL, "negative output index");
+    pl.out_idx.assign(out_idx_host, out_idx_host + batch);
+  }
   return run_plan(ctx, pl, modes_host, (size_t)total, st->B, st->m, st->pref, prob_out, haf_out, partial_out, stream);
 }
 
@@ -736,36 +749,40 @@ int gbs_prob_batch(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host,
   if (!ctx) return GBS_EINVAL;
   if (batch > 0 && !prob_out_dev) return fail(ctx, GBS_EINVAL, "null prob_out");
   return prob_common(ctx, st, modes_host, offsets_host, batch, nullptr, nullptr, prob_out_dev,
-                     reinterpret_cast<double2*>(haf_out_dev), nullptr, static_cast<hipStream_t>(stream));
+                     reinterpret_cast<double2*>(haf_out_dev), nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 int gbs_prob_slices(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, const int64_t* offsets_host,
                     const int64_t* lo_host, const int64_t* hi_host, int64_t batch, gbs_partial* partials_dev,
-                    void* stream) {
+                    const int64_t* out_idx_host, void* stream) {
   if (!ctx) return GBS_EINVAL;
   if (batch > 0 && (!lo_host || !hi_host || !partials_dev)) return fail(ctx, GBS_EINVAL, "null pointer");
   return prob_common(ctx, st, modes_host, offsets_host, batch, lo_host, hi_host, nullptr, nullptr, partials_dev,
-                     static_cast<hipStream_t>(stream));
+                     out_idx_host, static_cast<hipStream_t>(stream));
 }
 
-int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_dev, const int64_t* part_off_host,
-                 const int32_t* n_host, const double* sfact_host, int64_t batch, double* prob_out_dev,
-                 gbs_c128* haf_out_dev, void* stream) {
+int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_dev, const int64_t* part_lo_host,
+                 const int64_t* part_hi_host, const int32_t* n_host, const double* sfact_host, int64_t batch,
+                 double* prob_out_dev, gbs_c128* haf_out_dev, void* stream) {
   if (!ctx) return GBS_EINVAL;
   ctx->last_error.clear();
   if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
   if (batch == 0) return GBS_OK;
-  if (!part_off_host || !n_host || (!partials_dev && part_off_host[batch] > 0))
-    return fail(ctx, GBS_EINVAL, "null pointer");
+  if (!part_lo_host || !part_hi_host || !n_host) return fail(ctx, GBS_EINVAL, "null pointer");
   if (prob_out_dev && (!st || !sfact_host)) return fail(ctx, GBS_EINVAL, "prob_out needs a state and sfact");
-  if (part_off_host[0] < 0) return fail(ctx, GBS_EINVAL, "negative partial offset");
+  bool any = false;
   for (int64_t b = 0; b < batch; ++b) {
-    if (part_off_host[b + 1] < part_off_host[b]) return fail(ctx, GBS_EINVAL, "partial offsets must be non-decreasing");
+    if (part_lo_host[b] < 0 || part_hi_host[b] < part_lo_host[b])
+      return fail(ctx, GBS_EINVAL, "partial range %lld is malformed", (long long)b);
     if (n_host[b] < 0 || n_host[b] > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n out of range");
+    any |= part_hi_host[b] > part_lo_host[b];
   }
-  // The finalize kernel reads partials through a device offset table; stage it like a plan.
+  if (any && !partials_dev) return fail(ctx, GBS_EINVAL, "null partials");
+  // stage the ranges (lo then hi, in the part_off region), n and sfact
   Plan pl;
-  pl.part_off.assign(part_off_host, part_off_host + batch + 1);
+  pl.part_off.resize(2 * batch);
+  std::copy(part_lo_host, part_lo_host + batch, pl.part_off.begin());
+  std::copy(part_hi_host, part_hi_host + batch, pl.part_off.begin() + batch);
   pl.nvec.assign(n_host, n_host + batch);
   pl.sfact.assign(batch, 1.0);
   if (sfact_host) pl.sfact.assign(sfact_host, sfact_host + batch);
@@ -791,7 +808,8 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_
   ctx->pinned_used[pi] = true;
   FinalizeArgs fa{};
   fa.partials = partials_dev;
-  fa.part_off = reinterpret_cast<const int64_t*>(ws + L.part_off);
+  fa.part_lo = reinterpret_cast<const int64_t*>(ws + L.part_off);
+  fa.part_hi = fa.part_lo + batch;
   fa.n = reinterpret_cast<const int32_t*>(ws + L.nvec);
   fa.sfact = reinterpret_cast<const double*>(ws + L.sfact);
   fa.prefactor = st ? st->pref : nullptr;

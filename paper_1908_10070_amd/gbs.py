@@ -67,8 +67,8 @@ def lib() -> ctypes.CDLL:
         "gbs_state_copy_B": (ctypes.c_int, [vp, dp, vp]),
         "gbs_prob_batch": (ctypes.c_int, [vp, vp, dp, dp, i64, dp, dp, vp]),
         "gbs_subset_count": (i64, [i32]),
-        "gbs_prob_slices": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, vp]),
-        "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, dp, vp]),
+        "gbs_prob_slices": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, dp, vp]),
+        "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, dp, i64, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -264,31 +264,48 @@ class Context:
                                          _t_ptr(prob_out), _t_ptr(haf_out), _stream_ptr(stream)))
         return (prob_out, haf_out) if want_haf else prob_out
 
-    def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, stream=None):
-        """Compensated partial sums over subset ranges [lo, hi) -> (batch, 4) float64 tensor."""
+    def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, out_idx=None, stream=None):
+        """Compensated partial sums over subset ranges [lo, hi) -> float64 tensor of (s_re, s_im, c_re, c_im)
+        rows; slice b goes to row out_idx[b] (default b)."""
         import torch
         modes, offsets = pack_patterns(patterns)
         b = len(offsets) - 1
         lo = np.ascontiguousarray(lo, dtype=np.int64)
         hi = np.ascontiguousarray(hi, dtype=np.int64)
+        if len(lo) != b or len(hi) != b:
+            raise ValueError("one (lo, hi) pair per pattern")
+        oi = None if out_idx is None else np.ascontiguousarray(out_idx, dtype=np.int64)
+        rows = b if oi is None else (int(oi.max()) + 1 if len(oi) else 0)
         if partials_out is None:
-            partials_out = torch.empty((b, 4), dtype=torch.float64, device=self.torch_device)
+            partials_out = torch.empty((max(rows, 1), 4), dtype=torch.float64, device=self.torch_device)
+        elif partials_out.shape[0] < rows:
+            raise ValueError("partials_out too small for out_idx")
         self._check(lib().gbs_prob_slices(self.handle, state.handle, _np_ptr(modes), _np_ptr(offsets), _np_ptr(lo),
-                                          _np_ptr(hi), b, _t_ptr(partials_out), _stream_ptr(stream)))
+                                          _np_ptr(hi), b, _t_ptr(partials_out), _np_ptr(oi), _stream_ptr(stream)))
         return partials_out
 
-    def finalize(self, state: Optional[State], partials, part_off, ns, sfact=None, want_prob=True, stream=None):
+    def finalize(self, state: Optional[State], partials, part_lo, part_hi, ns, sfact=None, want_prob=True,
+                 prob_out=None, haf_out=None, stream=None):
+        """Pattern b = compensated sum of partials[part_lo[b]:part_hi[b]] -> (prob, haf) tensors."""
         import torch
-        part_off = np.ascontiguousarray(part_off, dtype=np.int64)
+        lo = np.ascontiguousarray(part_lo, dtype=np.int64)
+        hi = np.ascontiguousarray(part_hi, dtype=np.int64)
         ns = np.ascontiguousarray(ns, dtype=np.int32)
         b = len(ns)
+        if len(lo) != b or len(hi) != b:
+            raise ValueError("one partial range per pattern")
+        if b and int(hi.max()) > partials.shape[0]:
+            raise ValueError("partial range beyond the partials tensor")
         sf = None if sfact is None else np.ascontiguousarray(sfact, dtype=np.float64)
-        prob = torch.empty(b, dtype=torch.float64, device=self.torch_device) if want_prob else None
-        haf = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
+        if want_prob and prob_out is None:
+            prob_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
+        if haf_out is None:
+            haf_out = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
         self._check(lib().gbs_finalize(self.handle, state.handle if state is not None else None, _t_ptr(partials),
-                                       _np_ptr(part_off), _np_ptr(ns), _np_ptr(sf), b, _t_ptr(prob), _t_ptr(haf),
+                                       _np_ptr(lo), _np_ptr(hi), _np_ptr(ns), _np_ptr(sf), b,
+                                       _t_ptr(prob_out) if want_prob else None, _t_ptr(haf_out),
                                        _stream_ptr(stream)))
-        return prob, haf
+        return (prob_out if want_prob else None), haf_out
 
 
 def sfact_of(modes: Sequence[int]) -> float:

@@ -1,0 +1,412 @@
+"""Continuous-batching server for GBS probability requests.
+
+Requests (output patterns, i.e. mode lists) arrive at any time. The server keeps the GBS state
+(U, B) resident on the device and runs a loop of *steps*. Each step is one launch of
+``gbs_prob_slices`` over a mix of work from every admitted request:
+
+* Every pattern's 2^(n/2) - 1 subset terms are cut into slices whose boundaries depend only on n,
+  so a long request (n = 32: 65,535 subsets) is spread over several steps while short ones
+  (n = 8: 15 subsets) finish in one, and a request's result is the same whatever it was batched
+  with (each slice partial depends only on its pattern and range; slices are combined in order).
+* Admission is by device memory: a request needs one 32-byte partial per slice in a fixed device
+  pool; requests wait when the pool or the active-request table is full and are admitted as
+  earlier ones complete. A request that could never fit is rejected.
+* A step takes slices from active requests, shortest remaining work first, at most ``step_flops``
+  of modelled work and at most ``share`` of that from one request, so short requests are not held
+  behind long ones; the oldest active request always gets one slice, so long ones keep moving. Up to ``inflight`` steps are queued on the stream, so the host prepares the next
+  step while the device runs the current one.
+* When a request's last slice has been launched, a ``gbs_finalize`` launch (its slices' partials,
+  in slice order, compensated) follows on the same stream and produces the probability; the
+  request completes when that result has been copied back.
+
+``FifoServer`` is the comparison path: one request at a time through the plain per-pattern GPU
+path (``gbs_prob_batch`` with eager, non-persistent launches), in arrival order.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+PARTIAL_BYTES = 32  # one gbs_partial
+
+
+def slice_plan(n: int, max_slice: int = 4096) -> List[tuple]:
+    """Slice boundaries [lo, hi) of a size-n pattern's subset order (a function of n only)."""
+    if n <= 0 or n % 2:
+        return []
+    cnt = (1 << (n // 2)) - 1
+    return [(lo, min(cnt, lo + max_slice)) for lo in range(0, cnt, max_slice)]
+
+
+def subset_flops(n: int, lo: int, hi: int, haf_flops: Callable[[int], float]) -> float:
+    """Modelled work of a slice: its share of the pattern's flops (by subset count)."""
+    cnt = (1 << (n // 2)) - 1
+    return haf_flops(n) * (hi - lo) / max(cnt, 1)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    modes: np.ndarray
+    n: int
+    t_arrival: float
+    future: Future
+    slices: List[tuple] = dataclasses.field(default_factory=list)
+    next_slice: int = 0
+    pool_off: int = -1          # first partial slot in the device pool
+    t_done: float = 0.0
+
+
+class SliceBackend:
+    """What the server needs from the device. GpuBackend is the real one; tests use fakes.
+
+    launch_step(jobs, finished) enqueues the slices of one step -- jobs are
+    (modes, lo, hi, pool_index) -- followed by the finalize of the requests whose last slice is in
+    this (or an earlier) step, and returns a handle; done(handle) polls it; results(handle) gives the
+    finished requests' probabilities in order.
+    """
+
+    def launch_step(self, jobs: List[tuple], finished: List[Request]) -> object:
+        raise NotImplementedError
+
+    def done(self, handle) -> bool:
+        raise NotImplementedError
+
+    def results(self, handle) -> np.ndarray:
+        raise NotImplementedError
+
+    def haf_flops(self, n: int) -> float:
+        return float(2 ** (n // 2)) * max(n, 2) ** 3
+
+
+class GpuBackend(SliceBackend):
+    """libgbs on one device: slices into a device partial pool, one finalize launch per step."""
+
+    def __init__(self, ctx, state, pool_entries: int, max_finish: int = 4096, ring: int = 4, stream=None):
+        import torch
+        from . import gbs
+        self._gbs = gbs
+        self.ctx = ctx
+        self.state = state
+        self.torch = torch
+        self.stream = stream or torch.cuda.Stream(device=ctx.torch_device)
+        self.pool = torch.zeros((pool_entries, 4), dtype=torch.float64, device=ctx.torch_device)
+        self.ring = ring
+        self.max_finish = max_finish
+        self.prob = torch.zeros((ring, max_finish), dtype=torch.float64, device=ctx.torch_device)
+        self.host = torch.zeros((ring, max_finish), dtype=torch.float64).pin_memory()
+        self._slot = 0
+
+    def haf_flops(self, n: int) -> float:
+        return self._gbs.haf_flops(n) if n > 0 and n % 2 == 0 else 0.0
+
+    def launch_step(self, jobs, finished):
+        torch = self.torch
+        if jobs:
+            self.ctx.prob_slices(self.state, [j[0] for j in jobs], [j[1] for j in jobs], [j[2] for j in jobs],
+                                 partials_out=self.pool, out_idx=[j[3] for j in jobs], stream=self.stream)
+        slot = self._slot
+        self._slot = (self._slot + 1) % self.ring
+        nf = len(finished)
+        if nf > self.max_finish:
+            raise ValueError("too many requests finishing in one step")
+        if nf:
+            lo = [r.pool_off for r in finished]
+            hi = [r.pool_off + len(r.slices) for r in finished]
+            self.ctx.finalize(self.state, self.pool, lo, hi, [r.n for r in finished],
+                              [self._gbs.sfact_of(r.modes) for r in finished], want_prob=True,
+                              prob_out=self.prob[slot, :nf], stream=self.stream)
+            with torch.cuda.stream(self.stream):
+                self.host[slot, :nf].copy_(self.prob[slot, :nf], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return (ev, slot, nf)
+
+    def done(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle) -> np.ndarray:
+        _, slot, nf = handle
+        return self.host[slot, :nf].numpy().copy()
+
+
+class Server:
+    """Continuous batching over a SliceBackend. Thread-safe submit(); run in a background thread."""
+
+    def __init__(self, backend: SliceBackend, pool_entries: int, max_active: int = 1024,
+                 step_flops: float = 1e11, share: float = 0.5, inflight: int = 2, max_slice: int = 4096,
+                 max_finish: int = 4096):
+        self.b = backend
+        self.pool_entries = pool_entries
+        self.max_active = max_active
+        self.step_flops = step_flops
+        self.share = share
+        self.inflight = inflight
+        self.max_slice = max_slice
+        self.max_finish = max_finish
+        self._lock = threading.Lock()
+        self._pending: collections.deque = collections.deque()
+        self._active: List[Request] = []
+        self._steps: collections.deque = collections.deque()  # (handle, finished requests)
+        self._free_pool = [(0, pool_entries)]  # free ranges (offset, length)
+        self._rid = 0
+        self._stop = False
+        self._thread: Optional[threading.Thread] = None
+        self.latencies: List[float] = []
+        self.completed = 0
+        self.rejected = 0
+        self.failed = 0
+        self.steps = 0
+        self.max_concurrent = 0
+        self._t_first = None
+        self._t_last = None
+
+    # ------------------------------------------------------------ public API
+    def submit(self, modes: Sequence[int]) -> Future:
+        f: Future = Future()
+        m = np.asarray(modes, dtype=np.int32)
+        with self._lock:
+            r = Request(self._rid, m, len(m), time.perf_counter(), f)
+            self._rid += 1
+            r.slices = slice_plan(r.n, self.max_slice)
+            if len(r.slices) > self.pool_entries:
+                self.rejected += 1
+                f.set_exception(MemoryError(f"request needs {len(r.slices)} partial slots, pool has {self.pool_entries}"))
+                return f
+            self._pending.append(r)
+            if self._t_first is None:
+                self._t_first = r.t_arrival
+        return f
+
+    def start(self):
+        self._thread = threading.Thread(target=self._loop, name="gbs-server", daemon=True)
+        self._thread.start()
+        return self
+
+    def idle(self) -> bool:
+        with self._lock:
+            return not (self._pending or self._active or self._steps)
+
+    def stop(self, drain: bool = True, timeout: float = 60.0):
+        if drain:
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < timeout and not self.idle():
+                time.sleep(0.001)
+        self._stop = True
+        if self._thread:
+            self._thread.join(timeout)
+
+    def stats(self) -> Dict[str, float]:
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        span = (self._t_last - self._t_first) if (self._t_last and self._t_first) else float("nan")
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "completed": self.completed, "rejected": self.rejected,
+                "failed": self.failed, "throughput_req_s": self.completed / span if span == span and span > 0 else 0.0,
+                "steps": self.steps, "max_concurrent": self.max_concurrent}
+
+    # ------------------------------------------------------------ internals
+    def _alloc_pool(self, need: int) -> int:
+        for i, (off, ln) in enumerate(self._free_pool):
+            if ln >= need:
+                if ln == need:
+                    self._free_pool.pop(i)
+                else:
+                    self._free_pool[i] = (off + need, ln - need)
+                return off
+        return -1
+
+    def _free_pool_range(self, off: int, ln: int):
+        if ln <= 0:
+            return
+        self._free_pool.append((off, ln))
+        self._free_pool.sort()
+        merged = []
+        for o, l in self._free_pool:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + l)
+            else:
+                merged.append((o, l))
+        self._free_pool = merged
+
+    def _admit(self):
+        while self._pending and len(self._active) < self.max_active:
+            r = self._pending[0]
+            need = len(r.slices)
+            off = self._alloc_pool(need) if need else 0
+            if off < 0:
+                break  # wait for device memory to free up
+            self._pending.popleft()
+            r.pool_off = off
+            self._active.append(r)
+        self.max_concurrent = max(self.max_concurrent, len(self._active))
+
+    def _remaining(self, r: Request) -> float:
+        return sum(subset_flops(r.n, lo, hi, self.b.haf_flops) for lo, hi in r.slices[r.next_slice:])
+
+    def _build_step(self):
+        """Shortest remaining work first (short requests are not held behind long ones), each request at
+        most `share` of the step budget, and the oldest active request always gets a slice so long
+        requests keep moving under load."""
+        jobs, finished = [], []
+        budget = self.step_flops
+        cap = self.step_flops * self.share
+        order = sorted(self._active, key=lambda r: (self._remaining(r), r.rid))
+        oldest = min(self._active, key=lambda r: r.rid)
+        if order and order[0] is not oldest:
+            order.remove(oldest)
+            order.insert(0, oldest)
+        for r in order:
+            if len(finished) >= self.max_finish:
+                break
+            anti_starve = r is oldest and len(order) > 1
+            if budget <= 0 and not anti_starve:
+                continue
+            used = 0.0
+            while r.next_slice < len(r.slices) and (anti_starve or (budget > 0 and (used < cap or used == 0.0))):
+                lo, hi = r.slices[r.next_slice]
+                w = subset_flops(r.n, lo, hi, self.b.haf_flops)
+                jobs.append((r.modes, lo, hi, r.pool_off + r.next_slice))
+                r.next_slice += 1
+                if anti_starve:
+                    break  # one slice outside the budget; the budget goes by remaining work
+                budget -= w
+                used += w
+            if r.next_slice == len(r.slices):
+                finished.append(r)
+        for r in finished:
+            self._active.remove(r)
+        return jobs, finished
+
+    def _complete(self, reqs: List[Request], probs: Optional[np.ndarray], err: Optional[BaseException]):
+        now = time.perf_counter()
+        for i, r in enumerate(reqs):
+            self._free_pool_range(r.pool_off, len(r.slices))
+            if err is not None:
+                self.failed += 1
+                r.future.set_exception(err)
+            else:
+                r.t_done = now
+                self.latencies.append(now - r.t_arrival)
+                self.completed += 1
+                r.future.set_result(float(probs[i]))
+            self._t_last = now
+
+    def _loop(self):
+        while not self._stop:
+            progressed = False
+            with self._lock:
+                while self._steps and self.b.done(self._steps[0][0]):
+                    h, reqs = self._steps.popleft()
+                    if reqs:
+                        self._complete(reqs, self.b.results(h), None)
+                    progressed = True
+                self._admit()
+                jobs, finished = ([], [])
+                if len(self._steps) < self.inflight and self._active:
+                    jobs, finished = self._build_step()
+            if jobs or finished:
+                try:
+                    h = self.b.launch_step(jobs, finished)
+                    with self._lock:
+                        self.steps += 1
+                        self._steps.append((h, finished))
+                except Exception as e:  # a failed launch fails the requests it carried, serving goes on
+                    with self._lock:
+                        self._complete(finished, None, e)
+                        hit = {id(j[0]) for j in jobs}
+                        for r in list(self._active):
+                            if id(r.modes) in hit:
+                                self._active.remove(r)
+                                self._complete([r], None, e)
+                progressed = True
+            if not progressed:
+                time.sleep(0.0001)
+
+
+class FifoServer:
+    """One request at a time through the per-pattern GPU path (the comparison for serving)."""
+
+    def __init__(self, ctx, state):
+        self.ctx = ctx
+        self.state = state
+        self._q: collections.deque = collections.deque()
+        self._lock = threading.Lock()
+        self._stop = False
+        self.latencies: List[float] = []
+        self.completed = 0
+        self._t_first = None
+        self._t_last = None
+
+    def submit(self, modes) -> Future:
+        f: Future = Future()
+        with self._lock:
+            t = time.perf_counter()
+            self._q.append((np.asarray(modes, dtype=np.int32), t, f))
+            if self._t_first is None:
+                self._t_first = t
+        return f
+
+    def start(self):
+        self._thread = threading.Thread(target=self._loop, daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self, drain=True, timeout=120.0):
+        if drain:
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < timeout:
+                with self._lock:
+                    if not self._q:
+                        break
+                time.sleep(0.001)
+        self._stop = True
+        self._thread.join(timeout)
+
+    def _loop(self):
+        import torch
+        while not self._stop:
+            with self._lock:
+                item = self._q.popleft() if self._q else None
+            if item is None:
+                time.sleep(0.0001)
+                continue
+            modes, t0, f = item
+            try:
+                p = self.ctx.prob_batch(self.state, [modes])
+                v = float(p.cpu().item())
+                now = time.perf_counter()
+                self.latencies.append(now - t0)
+                self.completed += 1
+                self._t_last = now
+                f.set_result(v)
+            except Exception as e:
+                f.set_exception(e)
+
+    def stats(self):
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        span = (self._t_last - self._t_first) if (self._t_last and self._t_first) else float("nan")
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "completed": self.completed,
+                "throughput_req_s": self.completed / span if span == span and span > 0 else 0.0}
+
+
+def replay(server, arrivals: np.ndarray, patterns: Sequence[Sequence[int]], warmup: int = 0):
+    """Submit patterns at the given arrival times (seconds from start) in real time; returns futures."""
+    futs = []
+    t0 = time.perf_counter()
+    for i, (t, p) in enumerate(zip(arrivals, patterns)):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= t:
+                break
+            dt = t - now
+            if dt > 0.0005:
+                time.sleep(dt - 0.0003)
+        futs.append(server.submit(p))
+    return futs

@@ -47,12 +47,32 @@ def one(job):
     return rec
 
 
+def add_ld(rec):
+    """Fill in the long-double value of an existing record."""
+    if "haf_pt_ld" in rec:
+        return rec
+    st, pats = inputs.config5()
+    B = oracle.state_B(st.U, st.r)
+    A = oracle.pattern_matrix(B, pats[rec["index"]])
+    t0 = time.time()
+    hl = oracle.haf_pt_ld(A)
+    rec = dict(rec, haf_pt_ld=[hl.real, hl.imag], seconds_pt_ld=time.time() - t0)
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--ld-all", action="store_true", help="add long-double values to an existing file")
     args = ap.parse_args()
-    with mp.get_context("fork").Pool(args.jobs) as pool:
-        recs = pool.map(one, JOBS, chunksize=1)
+    if args.ld_all:
+        old = json.loads((HERE / "config5_haf.json").read_text())
+        with mp.get_context("fork").Pool(args.jobs) as pool:
+            recs = pool.map(add_ld, old["records"], chunksize=1)
+    else:
+        with mp.get_context("fork").Pool(args.jobs) as pool:
+            recs = pool.map(one, JOBS, chunksize=1)
     out = {
         "source": "oracle haf_pt / haf_pt_ld on config-5 pattern matrices (m=60, r=0.88, seeds 1005/2005)",
         "records": sorted(recs, key=lambda r: r["index"]),

@@ -1,0 +1,79 @@
+"""Served probability requests on the GPU: parity with the oracle, and each result the same alone
+and in the mix (continuous batching changes the launches a request shares, not its arithmetic)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_10070_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_10070_amd import gbs
+    dev = torch.device("cuda", 0)
+    ctx = gbs.Context(0)
+    st_in, _ = inputs.config3(count=1)
+    st = ctx.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
+    return ctx, st, st_in
+
+
+def make_requests(seed, count, sizes):
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(sizes, size=count)
+    return [inputs.collision_free_patterns(50, int(n), 1, rng)[0] for n in ns]
+
+
+def serve_all(ctx, st, pats, **kw):
+    from paper_1908_10070_amd import serve
+    be = serve.GpuBackend(ctx, st, pool_entries=4096)
+    srv = serve.Server(be, pool_entries=4096, **kw)
+    futs = [srv.submit(p) for p in pats]
+    srv.start()
+    out = np.array([f.result(timeout=120) for f in futs])
+    srv.stop()
+    return out, srv.stats()
+
+
+def test_served_match_oracle_and_alone(env):
+    ctx, st, st_in = env
+    pats = make_requests(41, 48, [8, 10, 12, 14, 16, 18, 20, 22, 24, 26, 28])
+    mixed, stats = serve_all(ctx, st, pats, step_flops=2e9, max_slice=1024)
+    assert stats["completed"] == len(pats) and stats["failed"] == 0 and stats["steps"] > 1
+    # alone: each request through its own server run
+    alone = np.array([serve_all(ctx, st, [p], step_flops=2e9, max_slice=1024)[0][0] for p in pats[:12]])
+    assert np.array_equal(mixed[:12], alone)
+    # against the oracle (enumeration up to n = 24, long-double power trace above)
+    B = oracle.state_B(st_in.U, st_in.r)
+    for i, p in enumerate(pats):
+        if len(p) > 24 and i % 3:
+            continue
+        h = oracle.haf_enum(oracle.pattern_matrix(B, p)) if len(p) <= 24 else oracle.haf_pt_ld(oracle.pattern_matrix(B, p))
+        ref = abs(h) ** 2 / float(np.prod(np.cosh(st_in.r)))
+        assert abs(mixed[i] - ref) <= 1e-9 * ref, (len(p), mixed[i], ref)
+
+
+def test_served_equals_batched_for_single_slice_patterns(env):
+    """Patterns whose subsets fit one slice are evaluated exactly as gbs_prob_batch does."""
+    ctx, st, _ = env
+    pats = make_requests(42, 32, [8, 12, 16, 20, 24])
+    served, _ = serve_all(ctx, st, pats, step_flops=5e8)
+    batched = ctx.prob_batch(st, pats).cpu().numpy()
+    assert np.array_equal(served, batched)
+
+
+def test_fifo_server(env):
+    from paper_1908_10070_amd import gbs, serve
+    ctx, st, _ = env
+    pp = gbs.Context(0, use_graph=False, persistent=False)
+    pats = make_requests(43, 10, [8, 12, 16])
+    srv = serve.FifoServer(pp, st)
+    futs = [srv.submit(p) for p in pats]
+    srv.start()
+    out = np.array([f.result(timeout=60) for f in futs])
+    srv.stop()
+    assert np.array_equal(out, ctx.prob_batch(st, pats).cpu().numpy())
