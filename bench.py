@@ -121,6 +121,7 @@ def main():
     ap.add_argument("--no-per-pattern", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the probability and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in chunk sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -141,6 +142,11 @@ def main():
     out = torch.empty(batch, dtype=torch.complex128, device=dev)
     ctx = gbs.Context(0, use_graph=True, persistent=True)
     stream = torch.cuda.current_stream()
+    # autotuned chunk sizes for this workload (measured here, not read from a cache)
+    from paper_1908_10070_amd import autotune
+    tune_log = []
+    chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(8, 16, 32, 64), cache=None,
+                           log=tune_log) if not args.no_tune else ctx.get_tuning(n)
 
     for _ in range(args.warmup):
         ctx.haf_batch(A, out=out)
@@ -171,7 +177,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
         "config": {"workload": "config2: 4096 random complex-symmetric 24x24 matrices (seed 1002), haf_batch, "
-                               "persistent launch replayed from a HIP graph", "n": n, "batch": batch},
+                               "persistent launch replayed from a HIP graph", "n": n, "batch": batch,
+                   "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1])},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms},

@@ -1,0 +1,56 @@
+"""Autotuner: cache round trip (CPU) and a quick measured tuning (GPU)."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_1908_10070_amd import autotune
+
+
+class FakeCtx:
+    def __init__(self):
+        self.t = {}
+
+    def set_tuning(self, n, cs, cl):
+        self.t[n] = (cs, cl)
+
+
+def test_cache_round_trip(tmp_path, monkeypatch):
+    path = tmp_path / "tune.json"
+    autotune.save_cache({("gfx950", 24): (512, 16), ("gfx942", 24): (1024, 32)}, path)
+    autotune.save_cache({("gfx950", 20): (256, 8)}, path)
+    data = json.loads(path.read_text())
+    assert data["gfx950:24"] == {"chunk_small": 512, "chunk_large": 16}
+    assert data["gfx950:20"]["chunk_small"] == 256
+    ctx = FakeCtx()
+    monkeypatch.setattr(autotune, "_arch", lambda c: "gfx950")
+    assert autotune.load_cache(ctx, path) == 2
+    assert ctx.t == {24: (512, 16), 20: (256, 8)}
+
+
+def test_load_cache_missing_or_corrupt(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "_arch", lambda c: "gfx950")
+    assert autotune.load_cache(FakeCtx(), tmp_path / "none.json") == 0
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not json")
+    assert autotune.load_cache(FakeCtx(), bad) == 0
+
+
+@pytest.mark.gpu
+def test_tune_on_device(tmp_path):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_10070_amd import gbs, inputs
+    import oracle
+    ctx = gbs.Context(0)
+    A_host = inputs.random_symmetric(18, 256, np.random.default_rng(9))
+    A = torch.from_numpy(A_host).cuda()
+    log = []
+    cs, cl = autotune.tune(ctx, 18, A, reps=1, small=(64, 256), large=(8, 32), cache=tmp_path / "t.json", log=log)
+    assert (cs, cl) == ctx.get_tuning(18) and len(log) == 4
+    assert json.loads((tmp_path / "t.json").read_text())
+    h = ctx.haf_batch(A).cpu().numpy()
+    for i in (0, 100, 255):
+        ref = oracle.haf_enum(A_host[i])
+        assert abs(h[i] - ref) <= 1e-9 * abs(ref)

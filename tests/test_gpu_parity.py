@@ -224,3 +224,26 @@ def test_bipartite_permanent_large(ctx, torch_dev, k):
     per *= (-1) ** k
     print(f"k={k} n={2*k} rel err {relerr(h, per):.3e}")
     assert relerr(h, per) < 1e-8
+
+
+def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
+    """Config 5 (m = 60, r = 0.88, n = 36/40/44 B_S submatrices, subset space split over the whole
+    device): against the oracle's power trace, stored by tests/golden/make_config5_golden.py.
+    The reference is the long-double value where present, else the double one; the error bound is
+    the cancellation-limited one stated for these sizes."""
+    import json
+    import pathlib
+    gold = json.loads((pathlib.Path(__file__).parent / "golden" / "config5_haf.json").read_text())["records"]
+    st_in, pats = inputs.config5()
+    st = ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    sel = [pats[g["index"]] for g in gold]
+    for g, p in zip(gold, sel):
+        assert [int(v) for v in p] == g["modes"]
+    prob, haf = ctx.prob_batch(st, sel, want_haf=True)
+    haf = haf.cpu().numpy()
+    for g, h in zip(gold, haf):
+        ref = complex(*g.get("haf_pt_ld", g["haf_pt"]))
+        err = relerr(h, ref)
+        print(f"config5 index {g['index']} n={g['n']} rel err vs {'long double' if 'haf_pt_ld' in g else 'double'} "
+              f"oracle {err:.2e}")
+        assert err < 1e-7
