@@ -274,26 +274,51 @@ def test_config1_full_sweep_is_P8():
 # ------------------------------------------- planted mistakes are caught
 
 
+def _single_mode_convolution(r, n):
+    """n-photon probability of independent single-mode squeezers r_i (Sec. II A): a passive
+    interferometer conserves photon number, so this is the n-photon total of the GBS state."""
+    dist = np.zeros(n + 1)
+    dist[0] = 1.0
+    for ri in r:
+        dist = np.convolve(dist, [oracle.smss_prob(s, ri) for s in range(n + 1)])[: n + 1]
+    return dist[n]
+
+
+def _n_photon_total(B, r, n, with_sfact=True):
+    m = B.shape[0]
+    tot = 0.0
+    for p in oracle.multisets(m, n):
+        h = oracle.haf_enum(B[np.ix_(p, p)])
+        sf = math.prod(math.factorial(c) for c in np.bincount(p, minlength=m)) if with_sfact else 1
+        tot += abs(h) ** 2 / (sf * float(np.prod(np.cosh(r))))
+    return tot
+
+
+def test_nonuniform_n_photon_total_is_convolution():
+    """Per-mode r_i: sum of p over all n-photon patterns = the single-mode convolution."""
+    rng = np.random.default_rng(17)
+    m, n = 4, 4
+    U = inputs.haar_unitary(m, rng)
+    r = np.array([0.3, 0.5, 0.7, 0.9])
+    B = oracle.state_B(U, r)
+    assert abs(_n_photon_total(B, r, n) - _single_mode_convolution(r, n)) < 1e-14
+
+
 def test_pins_catch_planted_mistakes():
-    """A conjugate transpose instead of a transpose, a dropped s!, or a dropped tanh
-    each break the P_n pin."""
+    """A conjugate transpose instead of a transpose, a dropped s!, or a dropped tanh each break a
+    photon-number pin. (With one r on every mode U tanh(r) U^dagger = tanh(r) I is itself a valid
+    state, so the conjugate-transpose plant needs per-mode squeezing to show.)"""
     rng = np.random.default_rng(16)
     m, n, r = 4, 4, 0.7
     U = inputs.haar_unitary(m, rng)
     Pn = oracle.photon_number_prob(m, n, r)
-    pats = list(oracle.multisets(m, n))
-
-    def total(Bfun, with_sfact=True):
-        B = Bfun()
-        tot = 0.0
-        for p in pats:
-            h = oracle.haf_enum(B[np.ix_(p, p)])
-            sf = math.prod(math.factorial(c) for c in np.bincount(p, minlength=m)) if with_sfact else 1
-            tot += abs(h) ** 2 / (sf * math.cosh(r) ** m)
-        return tot
-
-    good = total(lambda: U @ np.diag(np.full(m, math.tanh(r))) @ U.T)
-    assert abs(good - Pn) < 1e-14
-    assert abs(total(lambda: U @ np.diag(np.full(m, math.tanh(r))) @ U.conj().T) - Pn) > 1e-3
-    assert abs(total(lambda: U @ np.diag(np.full(m, math.tanh(r))) @ U.T, with_sfact=False) - Pn) > 1e-3
-    assert abs(total(lambda: U @ U.T) - Pn) > 1e-3
+    ru = np.full(m, r)
+    D = np.diag(np.tanh(ru))
+    assert abs(_n_photon_total(U @ D @ U.T, ru, n) - Pn) < 1e-14
+    assert abs(_n_photon_total(U @ D @ U.T, ru, n, with_sfact=False) - Pn) > 1e-3
+    assert abs(_n_photon_total(U @ U.T, ru, n) - Pn) > 1e-3
+    rv = np.array([0.3, 0.5, 0.7, 0.9])
+    Dv = np.diag(np.tanh(rv))
+    conv = _single_mode_convolution(rv, n)
+    assert abs(_n_photon_total(U @ Dv @ U.T, rv, n) - conv) < 1e-14
+    assert abs(_n_photon_total(U @ Dv @ U.conj().T, rv, n) - conv) > 1e-3
