@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the probability and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="use the built-in chunk sizes")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -140,6 +142,12 @@ def main():
     dev = torch.device("cuda", 0)
     A = torch.from_numpy(A_host).to(dev)
     out = torch.empty(batch, dtype=torch.complex128, device=dev)
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = gbs.Context(0, use_graph=True, persistent=True)
     stream = torch.cuda.current_stream()
     # autotuned chunk sizes for this workload (measured here, not read from a cache)

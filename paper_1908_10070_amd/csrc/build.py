@@ -40,16 +40,18 @@ def _stale() -> bool:
     return any(d.stat().st_mtime > t for d in deps)
 
 
-def build(force: bool = True, verbose: bool = False) -> pathlib.Path:
-    """Compile every source and link libgbs.so. Always recompiles when force is true."""
-    if not force and not _stale():
+def build(force: bool = True, verbose: bool = False, out: pathlib.Path = None, defines=()) -> pathlib.Path:
+    """Compile every source and link libgbs.so (or `out`, with extra -D defines). Always recompiles
+    when force is true."""
+    out = pathlib.Path(out) if out else OUT
+    if not force and out == OUT and not _stale():
         return OUT
     with tempfile.TemporaryDirectory(prefix="gbs_build_") as td:
         objs = []
         for src in SOURCES:
             obj = pathlib.Path(td) / (src + ".o")
             lang = ["-x", "hip"] if src.endswith(".hip") else []
-            cmd = [hipcc(), *COMMON, *lang, "-c", str(HERE / src), "-o", str(obj)]
+            cmd = [hipcc(), *COMMON, *["-D" + d for d in defines], *lang, "-c", str(HERE / src), "-o", str(obj)]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,14 +59,14 @@ def build(force: bool = True, verbose: bool = False) -> pathlib.Path:
                 sys.stderr.write(r.stdout + r.stderr)
                 raise RuntimeError(f"hipcc failed on {src}")
             objs.append(str(obj))
-        tmp = OUT.with_name(OUT.name + f".tmp{os.getpid()}")
+        tmp = out.with_name(out.name + f".tmp{os.getpid()}")
         cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError("link of libgbs.so failed")
-        os.replace(tmp, OUT)
-    return OUT
+        os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

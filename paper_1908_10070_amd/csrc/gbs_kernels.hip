@@ -162,10 +162,10 @@ int upload_tables(const ConstTables& t) {
 namespace gbs {
 
 // Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
-//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= 6, k = 1..23
-//   classes 23..39  register engine (one subset per wave, one 16x16 tile), |Z| = 7, 8, k = 7..23
-//   classes 40..54  tile engine T = 2 (2x2 tiles, 4 waves), 9 <= |Z| <= 16, k = 9..23
-//   classes 55..61  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
+//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS, k = 1..23
+//   classes 23..41  register engine (one subset per wave, one 16x16 tile), kQuadMaxS < |Z| <= 8, k = 5..23
+//   classes 42..56  tile engine T = 2 (2x2 tiles, 4 waves), 9 <= |Z| <= 16, k = 9..23
+//   classes 57..63  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
 struct EngineVariant {
   void (*fn)(EngineArgs);
   int threads;
@@ -175,9 +175,9 @@ struct EngineVariant {
 template <int C>
 static EngineVariant variant_c() {
   if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, 1};
-  else if constexpr (C < 40) return {wave_engine_kernel<C - 23 + 7>, kThreads, 1};
-  else if constexpr (C < 55) return {tile_engine_kernel<2, C - 40 + 9>, 256, 2};
-  else return {tile_engine_kernel<3, C - 55 + 17>, 576, 3};
+  else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, 1};
+  else if constexpr (C < 57) return {tile_engine_kernel<2, C - 42 + 9>, 256, 2};
+  else return {tile_engine_kernel<3, C - 57 + 17>, 576, 3};
 }
 
 template <int... C>
@@ -191,10 +191,11 @@ static EngineVariant variant(int cls) {
 }
 
 int engine_class(int s, int k) {
-  if (s <= 6) return k - 1;
-  if (s <= 8) return 23 + (k - 7);
-  if (s <= 16) return 40 + (k - 9);
-  return 55 + (k - 17);
+  static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 6, "register-engine variants start at k = 5");
+  if (s <= kQuadMaxS) return k - 1;
+  if (s <= 8) return 23 + (k - 5);
+  if (s <= 16) return 42 + (k - 9);
+  return 57 + (k - 17);
 }
 
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {

@@ -7,12 +7,18 @@
 // lane x + 4b + 16y -- the instruction's output (and B-operand) layout. As in the register engine,
 // every power Q of M_Z has Q[i][c] = Q[c^1][i^1], so the A operand of a product is the transposed
 // tile read from lane l ^ 17 (block bits untouched), and tr(P Q) pairs each tile with the same tile of
-// Q read from lane l ^ 17. The k traces of the four subsets are reduced with a butterfly over the 16
-// lanes of each block; all lanes store a share of the results.
+// Q read from lane l ^ 17. The k traces of the four subsets are reduced over the 16 lanes of each
+// block with the register engine's VALU lane exchanges (fold over bit 5 per trace, then transposed
+// over bits 4 and 1, plain over bit 0); half the lanes store a share of the results.
 #pragma once
 
 namespace gbs {
 namespace {
+
+#ifndef GBS_QUAD_MAX_S
+#define GBS_QUAD_MAX_S 6
+#endif
+constexpr int kQuadMaxS = GBS_QUAD_MAX_S;  // largest |Z| on the quad engine (4x4 tiles, T4 = ceil(|Z|/2))
 
 template <int T4>
 struct QMat {
@@ -52,7 +58,8 @@ __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<
 }
 
 template <int T4>
-__device__ __forceinline__ void qdiag(const QMat<T4>& X, double2& t, int lane) {
+__device__ __forceinline__ double2 qdiag(const QMat<T4>& X, int lane) {
+  double2 t = make_double2(0.0, 0.0);
   if ((lane & 3) == (lane >> 4)) {
 #pragma unroll
     for (int I = 0; I < T4; ++I) {
@@ -60,10 +67,12 @@ __device__ __forceinline__ void qdiag(const QMat<T4>& X, double2& t, int lane) {
       t.y += X.i[I][I];
     }
   }
+  return t;
 }
 
 template <int T4>
-__device__ __forceinline__ void qpair(const QMat<T4>& X, const QMat<T4>& Y, double2& t) {
+__device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
+  double2 t = make_double2(0.0, 0.0);
 #pragma unroll
   for (int I = 0; I < T4; ++I)
 #pragma unroll
@@ -75,69 +84,51 @@ __device__ __forceinline__ void qpair(const QMat<T4>& X, const QMat<T4>& Y, doub
       t.y = fma(X.r[I][C], yi, t.y);
       t.y = fma(X.i[I][C], yr, t.y);
     }
+  return t;
 }
 
 template <int K, int T4, int OI, int NS>
-__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double2 (&tp)[K + 1], int lane) {
+__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], int lane) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       qmul<T4>(S[op.a], S[op.b], S[op.x]);
     } else if constexpr (op.type == OP_TDIAG) {
-      qdiag<T4>(S[op.a], tp[op.x], lane);
+      const double2 p = qdiag<T4>(S[op.a], lane);
+      w[op.x - 1] = fold32(p.x, p.y);
     } else {
-      qpair<T4>(S[op.a], S[op.b], tp[op.x]);
+      const double2 p = qpair<T4>(S[op.a], S[op.b]);
+      w[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops_quad<K, T4, OI + 1, NS>(S, tp, lane);
+    run_ops_quad<K, T4, OI + 1, NS>(S, w, lane);
   }
 }
 
-// Butterfly over lane bits 5, 4, 1, 0 (the 16 lanes of a block); store(idx, v) for component idx
-// of this lane's block.
+// Rest of the reduction over the 16 lanes of each block (lane bits 5, 4, 1, 0; the block is bits
+// 3..2) after the fold over bit 5: transposed over bits 4 and 1, plain over bit 0. Afterwards the
+// lanes with bit 0 clear call store(j, part, total) for their share of the block's (trace, part) pairs.
 template <int K, typename Store>
-__device__ __forceinline__ void reduce_traces_quad(const double2 (&tp)[K + 1], int lane, Store store) {
-  constexpr int V = 2 * K;
-  constexpr int VP = ((V + 15) / 16) * 16;
-  constexpr int H1 = VP / 2, H2 = VP / 4, H3 = VP / 8, H4 = VP / 16;
-  double v[VP];
+__device__ __forceinline__ void reduce_folded_quad(const double (&w)[K], int lane, Store store) {
+  constexpr int KP = (K + 3) / 4 * 4, H2 = KP / 2, H3 = KP / 4;
+  double v[KP];
 #pragma unroll
-  for (int j = 1; j <= K; ++j) {
-    v[2 * (j - 1)] = tp[j].x;
-    v[2 * (j - 1) + 1] = tp[j].y;
-  }
+  for (int q = 0; q < KP; ++q) v[q] = q < K ? w[q] : 0.0;
+  double u[H2];
 #pragma unroll
-  for (int q = V; q < VP; ++q) v[q] = 0.0;
-  const bool b5 = lane & 32, b4 = lane & 16, b1 = lane & 2, b0 = lane & 1;
-  double w1[H1], w2[H2], w3[H3], w4[H4];
-#pragma unroll
-  for (int q = 0; q < H1; ++q) {
-    const double send = b5 ? v[q] : v[q + H1];
-    const double keep = b5 ? v[q + H1] : v[q];
-    w1[q] = keep + __shfl_xor(send, 32, 64);
-  }
-#pragma unroll
-  for (int q = 0; q < H2; ++q) {
-    const double send = b4 ? w1[q] : w1[q + H2];
-    const double keep = b4 ? w1[q + H2] : w1[q];
-    w2[q] = keep + __shfl_xor(send, 16, 64);
-  }
+  for (int q = 0; q < H2; ++q) u[q] = fold16(v[q], v[q + H2]);
+  const bool b1 = lane & 2;
+  double z[H3];
 #pragma unroll
   for (int q = 0; q < H3; ++q) {
-    const double send = b1 ? w2[q] : w2[q + H3];
-    const double keep = b1 ? w2[q + H3] : w2[q];
-    w3[q] = keep + __shfl_xor(send, 2, 64);
+    z[q] = fold_row<kDppXor2>(u[q], u[q + H3], b1);
+    z[q] += dpp<kDppXor1>(z[q]);
   }
+  if ((lane & 1) == 0) {
+    const int base = ((lane & 16) ? H2 : 0) + (b1 ? H3 : 0);
+    const int part = lane >> 5;
 #pragma unroll
-  for (int q = 0; q < H4; ++q) {
-    const double send = b0 ? w3[q] : w3[q + H4];
-    const double keep = b0 ? w3[q + H4] : w3[q];
-    w4[q] = keep + __shfl_xor(send, 1, 64);
-  }
-  const int base = (b5 ? H1 : 0) + (b4 ? H2 : 0) + (b1 ? H3 : 0) + (b0 ? H4 : 0);
-#pragma unroll
-  for (int q = 0; q < H4; ++q) {
-    const int idx = base + q;
-    if (idx < V) store(idx, w4[q]);
+    for (int q = 0; q < H3; ++q)
+      if (base + q < K) store(base + q + 1, part, z[q]);
   }
 }
 
@@ -165,12 +156,10 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
       S[0].r[I][J] = vr;
       S[0].i[I][J] = vi;
     }
-  double2 tp[K + 1];
-#pragma unroll
-  for (int j = 0; j <= K; ++j) tp[j] = make_double2(0.0, 0.0);
-  run_ops_quad<K, T4, 0, NS>(S, tp, lane);
-  reduce_traces_quad<K>(tp, lane, [&](int idx, double v) {
-    if (valid_b) trw[((idx >> 1) + 1) * (2 * kWaveG) + 2 * u_b + (idx & 1)] = 0.5 * v;
+  double w[K];
+  run_ops_quad<K, T4, 0, NS>(S, w, lane);
+  reduce_folded_quad<K>(w, lane, [&](int j, int part, double v) {
+    if (valid_b) trw[j * (2 * kWaveG) + 2 * u_b + part] = 0.5 * v;
   });
 }
 
@@ -214,9 +203,9 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       const int u_b = u0 + b;
       if (smax <= 2)
         eval_quad<K, 1>(P, pl4, d_b, valid_b, trw, u_b, lane);
-      else if (smax <= 4)
+      else if (kQuadMaxS <= 4 || smax <= 4)
         eval_quad<K, 2>(P, pl4, d_b, valid_b, trw, u_b, lane);
-      else
+      else if constexpr (kQuadMaxS > 4)
         eval_quad<K, 3>(P, pl4, d_b, valid_b, trw, u_b, lane);
     }
     wave_sync();

@@ -186,22 +186,24 @@ struct ItemLists {
   std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
 };
 
-// Split [lo, hi) of pattern p into items: ranges of equal engine variant (subset sizes |Z| <= 6 on
-// the quad engine, 7..8 on the one-tile register engine, 9..16 and >= 17 on the 2x2 and 3x3 tile
-// engines), cut into chunks.
+// Split [lo, hi) of pattern p into items: ranges of subset sizes that share an engine variant
+// (small |Z| on the quad engine, up to 8 on the one-tile register engine, 9..16 and >= 17 on the 2x2
+// and 3x3 tile engines), cut into chunks.
 void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L, int p, int n, int64_t lo,
                 int64_t hi) {
   if (hi <= lo) return;
   const int k = n / 2;
   int64_t cs, cl;
   chunks_for(ctx, n, &cs, &cl);
-  const int bounds[4][2] = {{1, 6}, {7, 8}, {9, 16}, {17, kMaxK}};
-  for (const auto& bd : bounds) {
-    if (bd[0] > k) break;
-    const int64_t a = std::max(lo, size_start(t, k, bd[0]));
-    const int64_t b = std::min(hi, size_start(t, k, std::min(bd[1], k) + 1));
-    const int64_t chunk = bd[0] <= 7 ? cs : cl;
-    std::vector<WorkItem>& out = L.cls[engine_class(bd[0], k)];
+  // contiguous runs of subset sizes that share an engine variant
+  for (int s_lo = 1; s_lo <= k;) {
+    const int cls = engine_class(s_lo, k);
+    int s_hi = s_lo;
+    while (s_hi + 1 <= k && engine_class(s_hi + 1, k) == cls) ++s_hi;
+    const int64_t a = std::max(lo, size_start(t, k, s_lo));
+    const int64_t b = std::min(hi, size_start(t, k, s_hi + 1));
+    const int64_t chunk = s_hi <= 8 ? cs : cl;
+    std::vector<WorkItem>& out = L.cls[cls];
     for (int64_t x = a; x < b; x += chunk) {
       WorkItem w;
       w.lo = x;
@@ -210,6 +212,7 @@ void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L
       w.partial = (int32_t)pl.n_partials++;
       out.push_back(w);
     }
+    s_lo = s_hi + 1;
   }
   pl.nmax = std::max(pl.nmax, n);
   pl.kmax = std::max(pl.kmax, k);

@@ -6,7 +6,8 @@
 // accumulates Z(I, J) = sum_K X(I, K) Y(K, J) with the A operand X(I, K) read from tile (K, I) at lane
 // l ^ 17 (the pair symmetry Q^t = X Q X of every power) and the B operand from tile (K, J). Trace
 // inner products pair a tile with the same tile of the other factor, so they stay local; each wave
-// reduces its k partial traces with a butterfly, and the T*T wave results are added in wave order.
+// reduces its k partial traces with the register engine's VALU lane exchanges, and the T*T wave
+// results are added in wave order.
 // Coefficient recursion, compensated summation and partials are as in the register engine.
 #pragma once
 
@@ -45,18 +46,20 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
 }
 
 template <int K, int T, int OI, int NS>
-__device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double2 (&tp)[K + 1], int d, int lane, int w, int I,
-                                             int J, double2* xbuf) {
+__device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double (&tw)[K], int d, int lane, int w, int I, int J,
+                                             double2* xbuf) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       tile_mul<T>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
     } else if constexpr (op.type == OP_TDIAG) {
-      if (I == J) tdiag<1>(S[op.a], tp[op.x], lane);
+      const double2 p = I == J ? tdiag<1>(S[op.a], lane) : make_double2(0.0, 0.0);
+      tw[op.x - 1] = fold32(p.x, p.y);
     } else {
-      tpair<1>(S[op.a], S[op.b], tp[op.x]);
+      const double2 p = tpair<1>(S[op.a], S[op.b]);
+      tw[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops_tile<K, T, OI + 1, NS>(S, tp, d, lane, w, I, J, xbuf);
+    run_ops_tile<K, T, OI + 1, NS>(S, tw, d, lane, w, I, J, xbuf);
   }
 }
 
@@ -82,11 +85,10 @@ __device__ __forceinline__ void eval_subset_tile(const PatternView& P, const int
     S[0].r[0][0][r] = vr;
     S[0].i[0][0][r] = vi;
   }
-  double2 tp[K + 1];
-#pragma unroll
-  for (int j = 0; j <= K; ++j) tp[j] = make_double2(0.0, 0.0);
-  run_ops_tile<K, T, 0, NS>(S, tp, d, lane, w, I, J, xbuf);
-  reduce_traces<K>(tp, lane, [&](int idx, double v) { tred[w * 2 * K + idx] = v; });
+  // each wave's share of every trace, summed over the wave; added across waves in wave order later
+  double tw[K];
+  run_ops_tile<K, T, 0, NS>(S, tw, d, lane, w, I, J, xbuf);
+  reduce_folded<K>(tw, lane, [&](int j, int part, double v) { tred[w * 2 * K + 2 * (j - 1) + part] = v; });
 }
 
 template <int K, int T>

@@ -11,7 +11,10 @@
 //     tile read from lane l ^ 17 (x^1, y^1). The B operand is the accumulator register itself.
 //     A 16x16 complex product is then 4 register steps x 4 MFMAs with no LDS traffic.
 //   * tr(P Q) = sum_{i,c} P[i][c] Q[i^1][c^1] is, per lane, the product of P with Q read from lane
-//     l ^ 17; the k traces of a subset are reduced across the wave together with a butterfly.
+//     l ^ 17. Each trace's per-lane partial is folded over lane bit 5 (v_permlane32_swap, real part
+//     kept in the low half, imaginary in the high half) as soon as it is formed; the k folded traces
+//     are then reduced together by a transposed butterfly on permlane16 swaps and DPP row moves,
+//     with no LDS traffic.
 //   * The schedule (which powers, which traces) is the compile-time chain table for k, so slots and
 //     traces are plain registers.
 // A workgroup (4 waves) takes one work item -- a range of one pattern's canonical subset order --
@@ -90,7 +93,8 @@ __device__ __forceinline__ void cmul_mat(const CMat<T>& X, const CMat<T>& Y, CMa
 
 // per-lane partial of tr(X): the diagonal element this lane holds, if any
 template <int T>
-__device__ __forceinline__ void tdiag(const CMat<T>& X, double2& t, int lane) {
+__device__ __forceinline__ double2 tdiag(const CMat<T>& X, int lane) {
+  double2 t = make_double2(0.0, 0.0);
   const int x = lane & 15, y = lane >> 4;
   if (x >= y && ((x - y) & 3) == 0) {
     const int r = (x - y) >> 2;
@@ -100,11 +104,13 @@ __device__ __forceinline__ void tdiag(const CMat<T>& X, double2& t, int lane) {
       t.y += pick(X.i[I][I], r);
     }
   }
+  return t;
 }
 
 // per-lane partial of tr(X Y) = sum X[i][c] Y[i^1][c^1]
 template <int T>
-__device__ __forceinline__ void tpair(const CMat<T>& X, const CMat<T>& Y, double2& t) {
+__device__ __forceinline__ double2 tpair(const CMat<T>& X, const CMat<T>& Y) {
+  double2 t = make_double2(0.0, 0.0);
 #pragma unroll
   for (int I = 0; I < T; ++I)
 #pragma unroll
@@ -119,73 +125,101 @@ __device__ __forceinline__ void tpair(const CMat<T>& X, const CMat<T>& Y, double
         t.y = fma(xr, yi, t.y);
         t.y = fma(xi, yr, t.y);
       }
+  return t;
 }
 
+// Lane exchanges of 64-bit values on the VALU (no LDS traffic): DPP moves within a row of 16
+// lanes, v_permlane{16,32}_swap across rows. The two 32-bit halves move separately.
+__device__ __forceinline__ double join(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return join((unsigned)lo, (unsigned)hi);
+}
+
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppXor8 = 0x128;        // row_ror:8
+constexpr int kDppHalfMirror = 0x141;  // lane i of each 8-lane half <- lane 7 - i
+
+// Transposed butterfly steps. From per-lane x and y: x summed over the lane pair (l, l ^ 32) in
+// lanes 0..31 and y summed over it in lanes 32..63 (fold32); the same over (l, l ^ 16) with x in
+// rows 0 and 2, y in rows 1 and 3 (fold16).
+__device__ __forceinline__ double fold32(double x, double y) {
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+  return join(lo[0], hi[0]) + join(lo[1], hi[1]);
+}
+
+__device__ __forceinline__ double fold16(double x, double y) {
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+  return join(lo[0], hi[0]) + join(lo[1], hi[1]);
+}
+
+// The same within a row, for the lane bit that CTRL exchanges: x where the bit is clear, y where set.
+template <int CTRL>
+__device__ __forceinline__ double fold_row(double x, double y, bool bit) {
+  const double send = bit ? x : y;
+  const double keep = bit ? y : x;
+  return keep + dpp<CTRL>(send);
+}
+
+// Run the chain program for k on the slots; trace t_j's per-lane partial is folded over lane
+// bit 5 into w[j - 1] as soon as it is formed (real part in lanes 0..31, imaginary in 32..63).
 template <int K, int T, int OI, int NS>
-__device__ __forceinline__ void run_ops(CMat<T> (&S)[NS], double2 (&tp)[K + 1], int d, int lane) {
+__device__ __forceinline__ void run_ops(CMat<T> (&S)[NS], double (&w)[K], int d, int lane) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       cmul_mat<T>(S[op.a], S[op.b], S[op.x], d);
     } else if constexpr (op.type == OP_TDIAG) {
-      tdiag<T>(S[op.a], tp[op.x], lane);
+      const double2 p = tdiag<T>(S[op.a], lane);
+      w[op.x - 1] = fold32(p.x, p.y);
     } else {
-      tpair<T>(S[op.a], S[op.b], tp[op.x]);
+      const double2 p = tpair<T>(S[op.a], S[op.b]);
+      w[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops<K, T, OI + 1, NS>(S, tp, d, lane);
+    run_ops<K, T, OI + 1, NS>(S, w, d, lane);
   }
 }
 
-// Wave butterfly over the 2K partial trace components. Afterwards lanes with (lane & 7) == 0 hold
-// the wave totals; store(idx, v) is called there for component idx (t_{idx/2+1}, re/im = idx & 1).
+// Rest of the wave reduction of the folded traces: transposed over lane bits 4 and 3, plain over
+// bits 2..0. Afterwards the lanes with (lane & 7) == 0 call store(j, part, total) for their share
+// of the (trace, real/imaginary part) pairs.
 template <int K, typename Store>
-__device__ __forceinline__ void reduce_traces(const double2 (&tp)[K + 1], int lane, Store store) {
-  constexpr int V = 2 * K;
-  constexpr int VP = ((V + 7) / 8) * 8;
-  constexpr int H1 = VP / 2, H2 = VP / 4, H3 = VP / 8;
-  double v[VP];
+__device__ __forceinline__ void reduce_folded(const double (&w)[K], int lane, Store store) {
+  constexpr int KP = (K + 3) / 4 * 4, H2 = KP / 2, H3 = KP / 4;
+  double v[KP];
 #pragma unroll
-  for (int j = 1; j <= K; ++j) {
-    v[2 * (j - 1)] = tp[j].x;
-    v[2 * (j - 1) + 1] = tp[j].y;
-  }
+  for (int q = 0; q < KP; ++q) v[q] = q < K ? w[q] : 0.0;
+  double u[H2];
 #pragma unroll
-  for (int q = V; q < VP; ++q) v[q] = 0.0;
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
-  double w1[H1];
-#pragma unroll
-  for (int q = 0; q < H1; ++q) {
-    const double send = b5 ? v[q] : v[q + H1];
-    const double keep = b5 ? v[q + H1] : v[q];
-    w1[q] = keep + __shfl_xor(send, 32, 64);
-  }
-  double w2[H2];
-#pragma unroll
-  for (int q = 0; q < H2; ++q) {
-    const double send = b4 ? w1[q] : w1[q + H2];
-    const double keep = b4 ? w1[q + H2] : w1[q];
-    w2[q] = keep + __shfl_xor(send, 16, 64);
-  }
-  double w3[H3];
+  for (int q = 0; q < H2; ++q) u[q] = fold16(v[q], v[q + H2]);
+  const bool b3 = lane & 8;
+  double z[H3];
 #pragma unroll
   for (int q = 0; q < H3; ++q) {
-    const double send = b3 ? w2[q] : w2[q + H3];
-    const double keep = b3 ? w2[q + H3] : w2[q];
-    w3[q] = keep + __shfl_xor(send, 8, 64);
-  }
-#pragma unroll
-  for (int q = 0; q < H3; ++q) {
-    w3[q] += __shfl_xor(w3[q], 4, 64);
-    w3[q] += __shfl_xor(w3[q], 2, 64);
-    w3[q] += __shfl_xor(w3[q], 1, 64);
+    z[q] = fold_row<kDppXor8>(u[q], u[q + H3], b3);
+    z[q] += dpp<kDppHalfMirror>(z[q]);
+    z[q] += dpp<kDppXor1>(z[q]);
+    z[q] += dpp<kDppXor2>(z[q]);
   }
   if ((lane & 7) == 0) {
-    const int base = (b5 ? H1 : 0) + (b4 ? H2 : 0) + (b3 ? H3 : 0);
+    const int base = ((lane & 16) ? H2 : 0) + (b3 ? H3 : 0);
+    const int part = lane >> 5;
 #pragma unroll
-    for (int q = 0; q < H3; ++q) {
-      const int idx = base + q;
-      if (idx < V) store(idx, w3[q]);
-    }
+    for (int q = 0; q < H3; ++q)
+      if (base + q < K) store(base + q + 1, part, z[q]);
   }
 }
 
@@ -229,13 +263,9 @@ __device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t*
         S[0].r[I][J][r] = vr;
         S[0].i[I][J][r] = vi;
       }
-  double2 tp[K + 1];
-#pragma unroll
-  for (int j = 0; j <= K; ++j) tp[j] = make_double2(0.0, 0.0);
-  run_ops<K, T, 0, NS>(S, tp, d, lane);
-  reduce_traces<K>(tp, lane, [&](int idx, double v) {
-    trw[((idx >> 1) + 1) * (2 * kWaveG) + 2 * u + (idx & 1)] = 0.5 * v;
-  });
+  double w[K];
+  run_ops<K, T, 0, NS>(S, w, d, lane);
+  reduce_folded<K>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
 }
 
 __device__ __forceinline__ uint32_t unrank(int k, int64_t g, int* s_out) {
