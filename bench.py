@@ -20,6 +20,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "n=24 complex128 hafnians/s + p50/p99 prob-request latency vs per-pattern path"
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_haf_batch_n24_b4096.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device sources; counter-derived traffic is reported only for the kernels it was
+    measured on."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1908_10070_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def _oracle_worker(args):
@@ -115,13 +142,15 @@ def extras(gbs, torch, dev, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-pattern", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the probability and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="use the built-in chunk sizes")
+    ap.add_argument("--chunks", type=str, default="",
+                    help="fixed chunk sizes 'small,large' instead of tuning (profiling runs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM traffic counters)")
     args = ap.parse_args()
@@ -153,8 +182,15 @@ def main():
     # autotuned chunk sizes for this workload (measured here, not read from a cache)
     from paper_1908_10070_amd import autotune
     tune_log = []
-    chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(8, 16, 32, 64), cache=None,
-                           log=tune_log) if not args.no_tune else ctx.get_tuning(n)
+    if args.chunks:
+        cs, cl = (int(v) for v in args.chunks.split(","))
+        ctx.set_tuning(n, cs, cl)
+        chunks = ctx.get_tuning(n)
+    elif args.no_tune:
+        chunks = ctx.get_tuning(n)
+    else:
+        chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(8, 16, 32, 64), cache=None,
+                               log=tune_log)
 
     for _ in range(args.warmup):
         ctx.haf_batch(A, out=out)
@@ -188,8 +224,10 @@ def main():
                                "persistent launch replayed from a HIP graph", "n": n, "batch": batch,
                    "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1])},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms},
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms,
+                     "kernel_ms_median": float(np.median(gpu_ms)),
+                     "algorithmic_bytes_per_launch": batch * n * n * 16 + batch * 16},
     }
 
     if not args.no_per_pattern:

@@ -18,7 +18,11 @@ namespace {
 #ifndef GBS_QUAD_MAX_S
 #define GBS_QUAD_MAX_S 6
 #endif
-constexpr int kQuadMaxS = GBS_QUAD_MAX_S;  // largest |Z| on the quad engine (4x4 tiles, T4 = ceil(|Z|/2))
+constexpr int kQuadMaxS = GBS_QUAD_MAX_S;
+// up to this k the quad kernels fit two waves per SIMD without spilling
+#ifndef GBS_QUAD_WAVES2_KMAX
+#define GBS_QUAD_WAVES2_KMAX 12
+#endif  // largest |Z| on the quad engine (4x4 tiles, T4 = ceil(|Z|/2))
 
 template <int T4>
 struct QMat {
@@ -217,7 +221,7 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 }  // namespace
 
 template <int K>
-__global__ __launch_bounds__(kThreads) void quad_engine_kernel(EngineArgs args) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= GBS_QUAD_WAVES2_KMAX ? 2 : 1, 8))) void quad_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
   double2* Alds = reinterpret_cast<double2*>(smem + L.A);

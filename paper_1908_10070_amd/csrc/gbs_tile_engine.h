@@ -14,7 +14,7 @@
 namespace gbs {
 namespace {
 
-template <int T>
+template <int T, bool G>
 __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMat<1>& Z, int d, int lane, int w,
                                          int I, int J, double2* xbuf) {
   constexpr int NT = T * T;
@@ -25,6 +25,28 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
   }
   __syncthreads();
   d4 accr = d4{0.0, 0.0, 0.0, 0.0}, acci = d4{0.0, 0.0, 0.0, 0.0};
+  if constexpr (G) {
+    // three real products per step (see cmul_mat)
+    d4 t3 = d4{0.0, 0.0, 0.0, 0.0};
+    if (16 * I < d && 16 * J < d) {
+#pragma unroll
+      for (int K = 0; K < T; ++K)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (16 * K + 4 * r < d) {
+            const double2 a = xbuf[((0 * NT + K * T + I) * 4 + r) * 64 + (lane ^ 17)];
+            const double2 b = xbuf[((1 * NT + K * T + J) * 4 + r) * 64 + lane];
+            accr = mfma(a.x, b.x, accr);
+            acci = mfma(a.y, b.y, acci);
+            t3 = mfma(a.x + a.y, b.x + b.y, t3);
+          }
+        }
+    }
+    __syncthreads();
+    Z.r[0][0] = accr - acci;
+    Z.i[0][0] = t3 - accr - acci;
+    return;
+  }
   if (16 * I < d && 16 * J < d) {
 #pragma unroll
     for (int K = 0; K < T; ++K)
@@ -51,7 +73,7 @@ __device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double (&tw)[K], 
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      tile_mul<T>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
+      tile_mul<T, (K <= GBS_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
     } else if constexpr (op.type == OP_TDIAG) {
       const double2 p = I == J ? tdiag<1>(S[op.a], lane) : make_double2(0.0, 0.0);
       tw[op.x - 1] = fold32(p.x, p.y);

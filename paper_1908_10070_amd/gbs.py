@@ -16,7 +16,7 @@ import numpy as np
 _HERE = pathlib.Path(__file__).resolve().parent
 # GBS_LIB selects another build of the same library (e.g. a variant compiled with different engine
 # limits for a comparison); by default the in-tree libgbs.so.
-LIB_PATH = pathlib.Path(os.environ.get("GBS_LIB", _HERE / "libgbs.so"))
+LIB_PATH = pathlib.Path(os.environ.get("GBS_LIB") or (_HERE / "libgbs.so"))
 
 GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6)
 GBS_N_MAX = 46
