@@ -24,23 +24,30 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
     xbuf[((1 * NT + w) * 4 + r) * 64 + lane] = make_double2(Y.r[0][0][r], Y.i[0][0][r]);
   }
   __syncthreads();
-  d4 accr = d4{0.0, 0.0, 0.0, 0.0}, acci = d4{0.0, 0.0, 0.0, 0.0};
+  // The first step (K = 0, r = 0) always runs for a tile inside d and starts the accumulators.
+  const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
+  d4 accr, acci;
   if constexpr (G) {
     // three real products per step (see cmul_mat)
-    d4 t3 = d4{0.0, 0.0, 0.0, 0.0};
+    d4 t3;
     if (16 * I < d && 16 * J < d) {
 #pragma unroll
       for (int K = 0; K < T; ++K)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if (16 * K + 4 * r < d) {
+          const bool first = K == 0 && r == 0;
+          if (first || 16 * K + 4 * r < d) {
             const double2 a = xbuf[((0 * NT + K * T + I) * 4 + r) * 64 + (lane ^ 17)];
             const double2 b = xbuf[((1 * NT + K * T + J) * 4 + r) * 64 + lane];
-            accr = mfma(a.x, b.x, accr);
-            acci = mfma(a.y, b.y, acci);
-            t3 = mfma(a.x + a.y, b.x + b.y, t3);
+            accr = mfma(a.x, b.x, first ? zero : accr);
+            acci = mfma(a.y, b.y, first ? zero : acci);
+            t3 = mfma(a.x + a.y, b.x + b.y, first ? zero : t3);
           }
         }
+    } else {
+      accr = zero;
+      acci = zero;
+      t3 = zero;
     }
     __syncthreads();
     Z.r[0][0] = accr - acci;
@@ -52,15 +59,19 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
     for (int K = 0; K < T; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (16 * K + 4 * r < d) {
+        const bool first = K == 0 && r == 0;
+        if (first || 16 * K + 4 * r < d) {
           const double2 a = xbuf[((0 * NT + K * T + I) * 4 + r) * 64 + (lane ^ 17)];
           const double2 b = xbuf[((1 * NT + K * T + J) * 4 + r) * 64 + lane];
-          accr = mfma(a.x, b.x, accr);
-          acci = mfma(a.x, b.y, acci);
+          accr = mfma(a.x, b.x, first ? zero : accr);
+          acci = mfma(a.x, b.y, first ? zero : acci);
           accr = mfma(-a.y, b.y, accr);
           acci = mfma(a.y, b.x, acci);
         }
       }
+  } else {
+    accr = zero;
+    acci = zero;
   }
   __syncthreads();
   Z.r[0][0] = accr;

@@ -65,38 +65,33 @@ __device__ __forceinline__ double pick(const d4& v, int r) {
 #define GBS_GAUSS_KMAX kMaxK
 #endif
 
-// Z = X Y (Z may alias X or Y).
+// Z = X Y (Z may alias X or Y). Every k-step runs: entries beyond d are zero, so the padded steps
+// add nothing, and starting each accumulator from the first product lets that MFMA take a zero
+// accumulator operand instead of registers cleared beforehand.
 template <int T, bool G>
 __device__ __forceinline__ void cmul_mat(const CMat<T>& X, const CMat<T>& Y, CMat<T>& Z, int d) {
+  (void)d;
+  const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
   if constexpr (G) {
     d4 t1[T][T], t2[T][T], t3[T][T];
-#pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-      for (int J = 0; J < T; ++J) {
-        t1[I][J] = d4{0.0, 0.0, 0.0, 0.0};
-        t2[I][J] = d4{0.0, 0.0, 0.0, 0.0};
-        t3[I][J] = d4{0.0, 0.0, 0.0, 0.0};
-      }
 #pragma unroll
     for (int K = 0; K < T; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (16 * K + 4 * r < d) {
-          double bs[T];
+        double bs[T];
 #pragma unroll
-          for (int J = 0; J < T; ++J) bs[J] = Y.r[K][J][r] + Y.i[K][J][r];
+        for (int J = 0; J < T; ++J) bs[J] = Y.r[K][J][r] + Y.i[K][J][r];
 #pragma unroll
-          for (int I = 0; I < T; ++I) {
-            const double ar = swap17(X.r[K][I][r]);
-            const double ai = swap17(X.i[K][I][r]);
-            const double as = ar + ai;
+        for (int I = 0; I < T; ++I) {
+          const double ar = swap17(X.r[K][I][r]);
+          const double ai = swap17(X.i[K][I][r]);
+          const double as = ar + ai;
+          const bool first = K == 0 && r == 0;
 #pragma unroll
-            for (int J = 0; J < T; ++J) {
-              t1[I][J] = mfma(ar, Y.r[K][J][r], t1[I][J]);
-              t2[I][J] = mfma(ai, Y.i[K][J][r], t2[I][J]);
-              t3[I][J] = mfma(as, bs[J], t3[I][J]);
-            }
+          for (int J = 0; J < T; ++J) {
+            t1[I][J] = mfma(ar, Y.r[K][J][r], first ? zero : t1[I][J]);
+            t2[I][J] = mfma(ai, Y.i[K][J][r], first ? zero : t2[I][J]);
+            t3[I][J] = mfma(as, bs[J], first ? zero : t3[I][J]);
           }
         }
       }
@@ -111,30 +106,22 @@ __device__ __forceinline__ void cmul_mat(const CMat<T>& X, const CMat<T>& Y, CMa
   }
   CMat<T> acc;
 #pragma unroll
-  for (int I = 0; I < T; ++I)
-#pragma unroll
-    for (int J = 0; J < T; ++J) {
-      acc.r[I][J] = d4{0.0, 0.0, 0.0, 0.0};
-      acc.i[I][J] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-#pragma unroll
   for (int K = 0; K < T; ++K)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (16 * K + 4 * r < d) {  // register r of tile row K holds rows 16K + 4r .. 16K + 4r + 3
+    for (int r = 0; r < 4; ++r) {  // register r of tile row K holds rows 16K + 4r .. 16K + 4r + 3
 #pragma unroll
-        for (int I = 0; I < T; ++I) {
-          const double ar = swap17(X.r[K][I][r]);
-          const double ai = swap17(X.i[K][I][r]);
+      for (int I = 0; I < T; ++I) {
+        const double ar = swap17(X.r[K][I][r]);
+        const double ai = swap17(X.i[K][I][r]);
+        const bool first = K == 0 && r == 0;
 #pragma unroll
-          for (int J = 0; J < T; ++J) {
-            const double br = Y.r[K][J][r];
-            const double bi = Y.i[K][J][r];
-            acc.r[I][J] = mfma(ar, br, acc.r[I][J]);
-            acc.i[I][J] = mfma(ar, bi, acc.i[I][J]);
-            acc.r[I][J] = mfma(-ai, bi, acc.r[I][J]);
-            acc.i[I][J] = mfma(ai, br, acc.i[I][J]);
-          }
+        for (int J = 0; J < T; ++J) {
+          const double br = Y.r[K][J][r];
+          const double bi = Y.i[K][J][r];
+          acc.r[I][J] = mfma(ar, br, first ? zero : acc.r[I][J]);
+          acc.i[I][J] = mfma(ar, bi, first ? zero : acc.i[I][J]);
+          acc.r[I][J] = mfma(-ai, bi, acc.r[I][J]);
+          acc.i[I][J] = mfma(ai, br, acc.i[I][J]);
         }
       }
     }
@@ -448,7 +435,8 @@ __host__ __device__ inline WaveLds wave_lds_layout(int nmax, int kmax, int stage
 }
 
 template <int K>
-__global__ __launch_bounds__(kThreads) void wave_engine_kernel(EngineArgs args) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 12 ? 3 : 2, 8))) void wave_engine_kernel(
+    EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
   double2* Alds = reinterpret_cast<double2*>(smem + L.A);
