@@ -16,7 +16,8 @@ INCLUDE = ROOT / "include"
 OUT = PKG / "libgbs.so"
 
 SOURCES = ["gbs_kernels.hip", "gbs_runtime.cpp"]
-HEADERS = ["gbs_internal.h", "gbs_wave_engine.h", "gbs_quad_engine.h", "gbs_tile_engine.h", "gbs_chain_table.h"]
+HEADERS = ["gbs_internal.h", "gbs_wave_engine.h", "gbs_quad_engine.h", "gbs_tile_engine.h", "gbs_qtile_engine.h",
+           "gbs_strip_engine.h", "gbs_chain_table.h"]
 
 ARCH = "gfx950"
 COMMON = [

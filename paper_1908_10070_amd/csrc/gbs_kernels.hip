@@ -158,32 +158,45 @@ int upload_tables(const ConstTables& t) {
 #include "gbs_wave_engine.h"
 #include "gbs_quad_engine.h"
 #include "gbs_tile_engine.h"
+#include "gbs_qtile_engine.h"
+#include "gbs_strip_engine.h"
 
 namespace gbs {
 
 // Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
 //   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS, k = 1..23
 //   classes 23..41  register engine (one subset per wave, one 16x16 tile), kQuadMaxS < |Z| <= 8, k = 5..23
-//   classes 42..56  tile engine T = 2 (2x2 tiles, 4 waves), 9 <= |Z| <= 16, k = 9..23
-//   classes 57..63  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
+//   classes 42..49  strip engine (one subset per wave, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 9..16
+//   classes 50..56  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
+//   classes 57..67  tile engine T = 2 (2x2 tiles, 4 waves), 13 <= |Z| <= 16, k = 13..23
+//   classes 68..74  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
+// For 9 <= |Z| <= 12 the strip engine measured faster up to k = 16 (n = 24: 1.4x the quad-tile
+// engine's throughput on those subsets); from k = 17 its registers spill and the quad-tile engine,
+// at one wave per SIMD with no spills, is faster. For |Z| = 7, 8 the register engine beat the
+// strip engine.
+enum EngineKind { kQuadKind, kWaveKind, kQtileKind, kTileKind };
+
 struct EngineVariant {
   void (*fn)(EngineArgs);
   int threads;
+  int kind;
   int tiles;
 };
 
 template <int C>
 static EngineVariant variant_c() {
-  if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, 1};
-  else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, 1};
-  else if constexpr (C < 57) return {tile_engine_kernel<2, C - 42 + 9>, 256, 2};
-  else return {tile_engine_kernel<3, C - 57 + 17>, 576, 3};
+  if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 1};
+  else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
+  else if constexpr (C < 50) return {strip_engine_kernel<C - 42 + 9, 5, 6>, kThreads, kWaveKind, 1};
+  else if constexpr (C < 57) return {qtile_engine_kernel<C - 50 + 17>, kThreads, kQtileKind, 1};
+  else if constexpr (C < 68) return {tile_engine_kernel<2, C - 57 + 13>, 256, kTileKind, 2};
+  else return {tile_engine_kernel<3, C - 68 + 17>, 576, kTileKind, 3};
 }
 
 template <int... C>
 static EngineVariant variant_table(int cls, std::integer_sequence<int, C...>) {
   static const EngineVariant tab[] = {variant_c<C>()...};
-  return (cls >= 0 && cls < (int)sizeof...(C)) ? tab[cls] : EngineVariant{nullptr, 0, 0};
+  return (cls >= 0 && cls < (int)sizeof...(C)) ? tab[cls] : EngineVariant{nullptr, 0, 0, 0};
 }
 
 static EngineVariant variant(int cls) {
@@ -194,14 +207,16 @@ int engine_class(int s, int k) {
   static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 6, "register-engine variants start at k = 5");
   if (s <= kQuadMaxS) return k - 1;
   if (s <= 8) return 23 + (k - 5);
-  if (s <= 16) return 42 + (k - 9);
-  return 57 + (k - 17);
+  if (s <= 12) return k <= 16 ? 42 + (k - 9) : 50 + (k - 17);
+  if (s <= 16) return 57 + (k - 13);
+  return 68 + (k - 17);
 }
 
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   const EngineVariant v = variant(cls);
-  if (v.tiles == 1) return wave_lds_layout(nmax, kmax, stage_A).total;
-  return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
+  if (v.kind == kQtileKind) return qtile_lds_layout(nmax, kmax, stage_A).total;
+  if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
+  return wave_lds_layout(nmax, kmax, stage_A).total;
 }
 
 static void allow_lds(int cls) {

@@ -221,79 +221,18 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 }  // namespace
 
 template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= GBS_QUAD_WAVES2_KMAX ? 2 : 1, 8))) void quad_engine_kernel(EngineArgs args) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= GBS_QUAD_WAVES2_KMAX ? 2 : 1, 8))) void
+quad_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
-  double2* Alds = reinterpret_cast<double2*>(smem + L.A);
-  int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  int32_t* pl4 = reinterpret_cast<int32_t*>(smem + L.pl) + wave * 4 * kMaxK;
-  double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
-  int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
-  double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-  double* part = reinterpret_cast<double*>(smem + L.part);
-  int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
-
-  int it = args.persistent ? 0 : (int)blockIdx.x;
-  for (;;) {
-    if (args.persistent) {
-      __syncthreads();
-      if (tid == 0) item_sh[0] = atomicAdd(args.counter, 1);
-      __syncthreads();
-      it = item_sh[0];
-    }
-    if (it >= args.n_items) break;
-    const WorkItem item = args.items[it];
-    const PatternDesc pd = args.pats[item.pattern];
-    const int n = pd.n, k = n >> 1;
-    const bool prob = args.modes != nullptr;
-    if (prob && tid < n) mlds[tid] = args.modes[pd.src + tid];
-    __syncthreads();
-    const bool staged = args.stage_A && n <= 32;
-    if (staged) {
-      for (int e = tid; e < n * n; e += kThreads) {
-        const int i = e / n, j = e - (e / n) * n;
-        Alds[e] = prob ? args.A[(int64_t)mlds[i] * args.m + mlds[j]] : args.A[pd.src + e];
-      }
-    }
-    __syncthreads();
-    PatternView P;
-    P.lds = staged ? Alds : nullptr;
-    P.A = args.A;
-    P.modes = prob ? mlds : nullptr;
-    P.src = pd.src;
-    P.n = n;
-    P.m = args.m;
-    const int64_t len = item.hi - item.lo;
-    const int64_t q = (len + 3) / 4;
-    const int64_t lo = item.lo + q * wave < item.hi ? item.lo + q * wave : item.hi;
-    const int64_t hi = lo + q < item.hi ? lo + q : item.hi;
-    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    if (lo < hi && k == K) quad_range<K>(P, lo, hi, pl4, trw, sz, terms, lane, sr, si, cr, ci);
-    if (lane == 0) {
-      part[wave * 4 + 0] = sr;
-      part[wave * 4 + 1] = si;
-      part[wave * 4 + 2] = cr;
-      part[wave * 4 + 3] = ci;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double r0 = part[0], i0 = part[1], c0 = part[2], d0 = part[3];
-      for (int w = 1; w < 4; ++w) {
-        neumaier(r0, c0, part[w * 4 + 0]);
-        neumaier(i0, d0, part[w * 4 + 1]);
-        c0 += part[w * 4 + 2];
-        d0 += part[w * 4 + 3];
-      }
-      gbs_partial p;
-      p.s_re = r0;
-      p.s_im = i0;
-      p.c_re = c0;
-      p.c_im = d0;
-      args.partials[item.partial] = p;
-    }
-    if (!args.persistent) break;
-  }
+  wave_items<K>(args, smem, [&](const PatternView& P, int64_t lo, int64_t hi, int wave, int lane, double& sr,
+                                double& si, double& cr, double& ci) {
+    int32_t* pl4 = reinterpret_cast<int32_t*>(smem + L.pl) + wave * 4 * kMaxK;
+    double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
+    int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
+    double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
+    quad_range<K>(P, lo, hi, pl4, trw, sz, terms, lane, sr, si, cr, ci);
+  });
 }
 
 }  // namespace gbs

@@ -434,20 +434,18 @@ __host__ __device__ inline WaveLds wave_lds_layout(int nmax, int kmax, int stage
   return L;
 }
 
-template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 12 ? 3 : 2, 8))) void wave_engine_kernel(
-    EngineArgs args) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// Persistent item loop of the engines that give each wave its own subsets: stage the pattern
+// matrix (n <= 32) and mode list in LDS, give each of the four waves a contiguous quarter of the
+// item, and combine the four wave partials in wave order, so an item's partial depends only on its
+// range. range(P, lo, hi, wave, lane, sr, si, cr, ci) evaluates the wave's quarter.
+template <int K, typename Range>
+__device__ __forceinline__ void wave_items(const EngineArgs& args, unsigned char* smem, Range range) {
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
   double2* Alds = reinterpret_cast<double2*>(smem + L.A);
   int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  int32_t* pl = reinterpret_cast<int32_t*>(smem + L.pl) + wave * kMaxK;
-  double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
-  int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
-  double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
   double* part = reinterpret_cast<double*>(smem + L.part);
   int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
   int it = args.persistent ? 0 : (int)blockIdx.x;
   for (;;) {
@@ -486,7 +484,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 1
     const int64_t lo = item.lo + q * wave < item.hi ? item.lo + q * wave : item.hi;
     const int64_t hi = lo + q < item.hi ? lo + q : item.hi;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    if (lo < hi && k == K) wave_range<K, 1>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);
+    if (lo < hi && k == K) range(P, lo, hi, wave, lane, sr, si, cr, ci);
     if (lane == 0) {
       part[wave * 4 + 0] = sr;
       part[wave * 4 + 1] = si;
@@ -511,6 +509,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 1
     }
     if (!args.persistent) break;
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 12 ? 3 : 2, 8))) void wave_engine_kernel(
+    EngineArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
+  wave_items<K>(args, smem, [&](const PatternView& P, int64_t lo, int64_t hi, int wave, int lane, double& sr,
+                                double& si, double& cr, double& ci) {
+    int32_t* pl = reinterpret_cast<int32_t*>(smem + L.pl) + wave * kMaxK;
+    double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
+    int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
+    double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
+    wave_range<K, 1>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);
+  });
 }
 
 }  // namespace gbs
