@@ -166,15 +166,17 @@ namespace gbs {
 // Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
 //   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS, k = 1..23
 //   classes 23..41  register engine (one subset per wave, one 16x16 tile), kQuadMaxS < |Z| <= 8, k = 5..23
-//   classes 42..49  strip engine (one subset per wave, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 9..16
-//   classes 50..56  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
-//   classes 57..67  tile engine T = 2 (2x2 tiles, 4 waves), 13 <= |Z| <= 16, k = 13..23
-//   classes 68..74  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
+//   classes 42..49  strip engine, 5 tile rows (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
+//   classes 50..55  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16
+//   classes 56..62  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
+//   classes 63..73  tile engine T = 2 (2x2 tiles, 4 waves), 13 <= |Z| <= 16, k = 13..23
+//   classes 74..80  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
 // For 9 <= |Z| <= 12 the strip engine measured faster up to k = 16 (n = 24: 1.4x the quad-tile
 // engine's throughput on those subsets); from k = 17 its registers spill and the quad-tile engine,
 // at one wave per SIMD with no spills, is faster. For |Z| = 7, 8 the register engine beat the
-// strip engine.
-enum EngineKind { kQuadKind, kWaveKind, kQtileKind, kTileKind };
+// strip engine. The strip engine has one kernel per tile-row count so that the common 5-row case
+// is not sized for 6 rows.
+enum EngineKind { kQuadKind, kWaveKind, kStripKind, kQtileKind, kTileKind };
 
 struct EngineVariant {
   void (*fn)(EngineArgs);
@@ -187,10 +189,11 @@ template <int C>
 static EngineVariant variant_c() {
   if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 1};
   else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
-  else if constexpr (C < 50) return {strip_engine_kernel<C - 42 + 9, 5, 6>, kThreads, kWaveKind, 1};
-  else if constexpr (C < 57) return {qtile_engine_kernel<C - 50 + 17>, kThreads, kQtileKind, 1};
-  else if constexpr (C < 68) return {tile_engine_kernel<2, C - 57 + 13>, 256, kTileKind, 2};
-  else return {tile_engine_kernel<3, C - 68 + 17>, 576, kTileKind, 3};
+  else if constexpr (C < 50) return {strip_engine_kernel<C - 42 + 9, 5, 5>, kThreads, kStripKind, 1};
+  else if constexpr (C < 56) return {strip_engine_kernel<C - 50 + 11, 6, 6>, kThreads, kStripKind, 1};
+  else if constexpr (C < 63) return {qtile_engine_kernel<C - 56 + 17>, kThreads, kQtileKind, 1};
+  else if constexpr (C < 74) return {tile_engine_kernel<2, C - 63 + 13>, 256, kTileKind, 2};
+  else return {tile_engine_kernel<3, C - 74 + 17>, 576, kTileKind, 3};
 }
 
 template <int... C>
@@ -207,14 +210,17 @@ int engine_class(int s, int k) {
   static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 6, "register-engine variants start at k = 5");
   if (s <= kQuadMaxS) return k - 1;
   if (s <= 8) return 23 + (k - 5);
-  if (s <= 12) return k <= 16 ? 42 + (k - 9) : 50 + (k - 17);
-  if (s <= 16) return 57 + (k - 13);
-  return 68 + (k - 17);
+  if (s <= 12 && k >= 17) return 56 + (k - 17);
+  if (s <= 10) return 42 + (k - 9);
+  if (s <= 12) return 50 + (k - 11);
+  if (s <= 16) return 63 + (k - 13);
+  return 74 + (k - 17);
 }
 
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   const EngineVariant v = variant(cls);
   if (v.kind == kQtileKind) return qtile_lds_layout(nmax, kmax, stage_A).total;
+  if (v.kind == kStripKind) return strip_lds_bytes(nmax, kmax, stage_A);
   if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
   return wave_lds_layout(nmax, kmax, stage_A).total;
 }

@@ -102,8 +102,11 @@ __device__ __forceinline__ double2 strip_pair(const SMat<T4>& X, const SMat<T4>&
   return t;
 }
 
+// Runs the chain program; trace t_j's per-lane partial, folded over lane bit 5, is parked in LDS at
+// park[(j - 1) * 64 + lane] until the chain is done (it would otherwise hold k registers while the
+// powers are live).
 template <int K, int T4, int OI, int NS>
-__device__ __forceinline__ void run_ops_strip(SMat<T4> (&S)[NS], double (&w)[K], const int (&addr)[4], int T4d,
+__device__ __forceinline__ void run_ops_strip(SMat<T4> (&S)[NS], double* park, const int (&addr)[4], int T4d,
                                               int lane) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
@@ -114,50 +117,54 @@ __device__ __forceinline__ void run_ops_strip(SMat<T4> (&S)[NS], double (&w)[K],
         strip_mul<T4>(S[op.a], S[op.b], S[op.x], addr, T4d);
     } else if constexpr (op.type == OP_TDIAG) {
       const double2 p = strip_diag<T4>(S[op.a], lane);
-      w[op.x - 1] = fold32(p.x, p.y);
+      park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
     } else {
       const double2 p = strip_pair<T4>(S[op.a], S[op.b]);
-      w[op.x - 1] = fold32(p.x, p.y);
+      park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
     }
-    run_ops_strip<K, T4, OI + 1, NS>(S, w, addr, T4d, lane);
+    run_ops_strip<K, T4, OI + 1, NS>(S, park, addr, T4d, lane);
   }
 }
 
 // One subset with d <= 4 T4: build M_Z, run the chain program, reduce the traces into slot u.
 template <int K, int T4>
 __device__ __forceinline__ void eval_strip(const PatternView& P, const int32_t* pl, int d, double* trw, int u,
-                                           int lane) {
+                                           double* park, int lane) {
   constexpr int NS = kChainTable[K].nslots;
   constexpr int NR = SMat<T4>::NR;
   const int x = lane & 3, b = (lane >> 2) & 3, y = lane >> 4;
   int addr[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) addr[c] = (y + 4 * c + 16 * x) * 4;
-  SMat<T4> S[NS];
+  {
+    SMat<T4> S[NS];
 #pragma unroll
-  for (int I = 0; I < T4; ++I)
+    for (int I = 0; I < T4; ++I)
 #pragma unroll
-    for (int R = 0; R < NR; ++R) {
-      const int a = 4 * I + y, c = 4 * (4 * R + b) + x;
-      double vr = 0.0, vi = 0.0;
-      if (a < d && c < d) {
-        const int bb = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
-        const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
-        vr = e.x;
-        vi = e.y;
+      for (int R = 0; R < NR; ++R) {
+        const int a = 4 * I + y, c = 4 * (4 * R + b) + x;
+        double vr = 0.0, vi = 0.0;
+        if (a < d && c < d) {
+          const int bb = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
+          const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
+          vr = e.x;
+          vi = e.y;
+        }
+        S[0].r[I][R] = vr;
+        S[0].i[I][R] = vi;
       }
-      S[0].r[I][R] = vr;
-      S[0].i[I][R] = vi;
-    }
+    run_ops_strip<K, T4, 0, NS>(S, park, addr, (d + 3) >> 2, lane);
+  }
   double w[K];
-  run_ops_strip<K, T4, 0, NS>(S, w, addr, (d + 3) >> 2, lane);
+#pragma unroll
+  for (int j = 0; j < K; ++j) w[j] = park[j * 64 + lane];  // each lane reads only what it wrote
   reduce_folded<K>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
 }
 
 // The subsets [lo, hi) of one pattern on one wave; each subset uses the tile-row count TL or TH.
 template <int K, int TL, int TH>
 __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double* trw, int32_t* sz,
-                            double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
+                            double2* terms, double* park, int lane, double& sr, double& si, double& cr, double& ci) {
   int s = 1;
   uint32_t mask = lo < hi ? unrank(K, lo, &s) : 0u;
   for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
@@ -169,9 +176,9 @@ __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_
       if (lane == 0) sz[u] = s;
       wave_sync();
       if (2 * s <= 4 * TL)
-        eval_strip<K, TL>(P, pl, 2 * s, trw, u, lane);
+        eval_strip<K, TL>(P, pl, 2 * s, trw, u, park, lane);
       else
-        eval_strip<K, TH>(P, pl, 2 * s, trw, u, lane);
+        eval_strip<K, TH>(P, pl, 2 * s, trw, u, park, lane);
     }
     wave_sync();
     combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
@@ -180,6 +187,11 @@ __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_
 }
 
 }  // namespace
+
+// LDS: the register engine's layout, then one trace-parking area of kmax x 64 doubles per wave.
+__host__ __device__ inline size_t strip_lds_bytes(int nmax, int kmax, int stage_A) {
+  return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * kmax * 64;
+}
 
 // Kernels: subsets with 4 (TL - 1) < 2|Z| <= 4 TH, one wave per subset.
 template <int K, int TL, int TH>
@@ -193,7 +205,8 @@ strip_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    strip_range<K, TL, TH>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);
+    double* park = reinterpret_cast<double*>(smem + L.total) + (size_t)wave * args.kmax * 64;
+    strip_range<K, TL, TH>(P, lo, hi, pl, trw, sz, terms, park, lane, sr, si, cr, ci);
   });
 }
 
