@@ -169,6 +169,29 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partia
                  const double* sfact_host, int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev,
                  void* stream);
 
+/* ------------------------------------------- marginal probabilities (sequential sampling) */
+
+#define GBS_MARGINAL_KMAX 20   /* longest prefix */
+#define GBS_MARGINAL_NMAX 4096 /* largest total photon number */
+
+/* Marginal probabilities of photon-position prefixes, Sec. III C-D (Eq. marginal_definition,
+ * Theorem 1), for identical squeezing on every mode. The n photons' positions x = (x_1..x_n) in
+ * [m]^n are distributed as q_n(x) = |Haf(W_x)|^2 / f_n with W = U U^t (the state's U; its squeezing
+ * values do not enter) and f_n = n! C((m+n)/2 - 1, n/2); the marginal of a prefix is q_n summed over
+ * all completions:
+ *   q_out_dev[b] = q_n(x_1..x_k),  x = modes_host[offsets_host[b] .. offsets_host[b+1]),  k <= n.
+ * Evaluated with Theorem 1 (B ranging over mu-subsets of X_k minus a'), regrouped: the hafnians of
+ * W over all 2^(k-1) even-size position subsets of the prefix run on the subset engines, then for
+ * every set A of positions the sums over the 2j-subsets a of the other positions of
+ * Haf(W_a) Haf(W_{rest}) are combined with the weights F and Per(S_{A,B}) (A, B with equal mode
+ * multisets) on the device; about 3^k / 2 products per prefix.
+ * Repeated modes (collisions) are allowed. n must be even (q is defined for even n only);
+ * 0 <= k <= min(n, GBS_MARGINAL_KMAX), modes in [0, m). k = 0 gives 1, k = 1 gives 1/m.
+ * Results are deterministic. Work memory: 16 bytes x 2^k per prefix plus the hafnian plan, in the
+ * context's workspace. Errors as for gbs_prob_batch; nothing is enqueued on a validation failure. */
+int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* state, int32_t n, const int32_t* modes_host,
+                       const int64_t* offsets_host, int64_t batch, double* q_out_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,11 +62,21 @@ def marginal_brute(W: np.ndarray, prefix: Sequence[int], n: int) -> float:
 
 
 def per01(S: np.ndarray) -> int:
-    """Permanent of a small 0/1 matrix, from its definition (sum over permutations)."""
+    """Permanent of a small 0/1 matrix: the sum over permutations, expanded row by row (row i picks
+    an unused column j with S[i, j] = 1), memoised on the set of columns already used."""
     r = S.shape[0]
-    if r == 0:
-        return 1
-    return int(sum(all(S[i, p[i]] for i in range(r)) for p in itertools.permutations(range(r))))
+    rows = [[j for j in range(r) if S[i, j]] for i in range(r)]
+    memo = {}
+
+    def rec(i, used):
+        if i == r:
+            return 1
+        key = (i, used)
+        if key not in memo:
+            memo[key] = sum(rec(i + 1, used | (1 << j)) for j in rows[i] if not used >> j & 1)
+        return memo[key]
+
+    return rec(0, 0)
 
 
 def F_weight(m: int, n: int, k: int, mu: int, j1: int, j2: int) -> float:
@@ -132,15 +142,25 @@ def marginal_thm1(W: np.ndarray, prefix: Sequence[int], n: int, b_excludes: str 
     return float(tot.real)
 
 
-def split_sums(W: np.ndarray, prefix: Sequence[int], C: Sequence[int]) -> dict:
-    """G_j(C) = sum over a subset of C with |a| = 2j of Haf(R_a) Haf(R_{C minus a}), for every j."""
+def split_sums(W: np.ndarray, prefix: Sequence[int], C: Sequence[int], memo: dict | None = None) -> dict:
+    """G_j(C) = sum over a subset of C with |a| = 2j of Haf(R_a) Haf(R_{C minus a}), for every j.
+    ``memo`` caches Haf(R_a) by position tuple (each evaluated once, same value either way)."""
     x = list(prefix)
+
+    def h(pos):
+        if memo is None:
+            return haf_sub(W, [x[i] for i in pos])
+        key = tuple(pos)
+        if key not in memo:
+            memo[key] = haf_sub(W, [x[i] for i in pos])
+        return memo[key]
+
     G = {}
     for j in range(len(C) // 2 + 1):
         g = 0.0j
         for a in itertools.combinations(C, 2 * j):
             e = [i for i in C if i not in a]
-            g += haf_sub(W, [x[i] for i in a]) * haf_sub(W, [x[i] for i in e])
+            g += h(a) * h(e)
         G[j] = g
     return G
 
@@ -152,25 +172,31 @@ def marginal_split(W: np.ndarray, prefix: Sequence[int], n: int) -> float:
     k = len(x)
     X = list(range(k))
     Gs = {}
+    memo: dict = {}
     for r in range(k + 1):
         for A in itertools.combinations(X, r):
             C = tuple(i for i in X if i not in A)
-            Gs[A] = split_sums(W, x, C)
+            Gs[A] = split_sums(W, x, C, memo)
     tot = 0.0 + 0.0j
     for mu in range(k + 1):
+        # Per(S_{A,B}) vanishes unless A and B carry the same multiset of modes (otherwise a mode
+        # has more rows than matching columns), so only pairs within one multiset are formed.
+        by_modes: dict = {}
         for A in itertools.combinations(X, mu):
-            for B in itertools.combinations(X, mu):
-                S = np.array([[int(x[Ai] == x[Bj]) for Bj in B] for Ai in A], dtype=np.int64)
-                per = per01(S.reshape(mu, mu))
-                if per == 0:
-                    continue
-                GA, GB = Gs[A], Gs[B]
-                for j1 in _j_range(k, n):
-                    for j2 in _j_range(k, n):
-                        if mu not in _mu_range(k, n, j1, j2):
-                            continue
-                        F = F_weight(m, n, k, mu, j1, j2)
-                        if F == 0.0 or j1 not in GA or j2 not in GB:
-                            continue
-                        tot += F * per * GA[j1] * np.conj(GB[j2])
+            by_modes.setdefault(tuple(sorted(x[i] for i in A)), []).append(A)
+        pairs = [(A, B) for group in by_modes.values() for A in group for B in group]
+        for A, B in pairs:
+            S = np.array([[int(x[Ai] == x[Bj]) for Bj in B] for Ai in A], dtype=np.int64)
+            per = per01(S.reshape(mu, mu))
+            if per == 0:
+                continue
+            GA, GB = Gs[A], Gs[B]
+            for j1 in _j_range(k, n):
+                for j2 in _j_range(k, n):
+                    if mu not in _mu_range(k, n, j1, j2):
+                        continue
+                    F = F_weight(m, n, k, mu, j1, j2)
+                    if F == 0.0 or j1 not in GA or j2 not in GB:
+                        continue
+                    tot += F * per * GA[j1] * np.conj(GB[j2])
     return float(tot.real)

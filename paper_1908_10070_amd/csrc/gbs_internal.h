@@ -77,7 +77,31 @@ struct FinalizeArgs {
   double* prob_out;           // nullable
   double2* haf_out;           // nullable
   gbs_partial* partial_out;   // nullable: write the combined compensated partial instead
-  const int64_t* out_idx;     // nullable: partial b goes to partial_out[out_idx[b]]
+  const int64_t* out_idx;     // nullable: result b goes to index out_idx[b] of the output it writes
+};
+
+// Marginal probabilities (Theorem 1, regrouped): per prefix p of k positions, hafnians h[mask] of W
+// restricted to every even-size subset of the positions (mask over k bits), and classes of position
+// sets A with the same mode multiset. For class c (all members of size mu):
+//   H_j = sum over members A of sum over 2j-subsets a of C = [k] minus A of h[a] h[C minus a],
+//   v_c = w_c * Re sum_{j1, j2} F[mu][j1][j2] H_{j1} conj(H_{j2}),
+// and q_p = sum of v_c over the prefix's classes in class order.
+struct MargArgs {
+  const double2* h;          // hafnians; prefix p's table starts at h_off[p]
+  const int64_t* h_off;
+  const int32_t* k;          // prefix lengths
+  const double* F;           // per prefix (k + 1) x (kmax/2 + 1)^2 weights, F_off[p]
+  const int64_t* F_off;
+  const int32_t* cls_prefix; // per class: prefix
+  const int64_t* cls_mem;    // per class: members cls_mem[c] .. cls_mem[c + 1] of mem
+  const double* cls_w;       // per class: Per(S_{A,B}) for A, B in the class
+  const uint32_t* mem;       // member masks A
+  int64_t n_classes;
+  double* v;                 // per class value
+  const int64_t* pre_cls;    // per prefix: classes pre_cls[p] .. pre_cls[p + 1]
+  int64_t batch;
+  int32_t jdim;              // kmax / 2 + 1
+  double* q_out;             // per prefix marginal
 };
 
 // Host-side launchers (defined in gbs_kernels.hip).
@@ -88,7 +112,8 @@ int engine_blocks_per_cu(int cls, size_t lds);
 void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream_t s);
 void launch_reset(int32_t* counter, int n, hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
-void launch_state(const double2* U, const double* r, int m, double2* B, double* prefactor, hipStream_t s);
+void launch_state(const double2* U, const double* r, int m, double2* B, double2* W, double* prefactor, hipStream_t s);
+void launch_marginal(const MargArgs& a, hipStream_t s);
 int upload_tables(const ConstTables& t);
 
 }  // namespace gbs

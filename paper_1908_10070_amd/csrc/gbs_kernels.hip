@@ -97,31 +97,132 @@ __global__ void finalize_kernel(FinalizeArgs a) {
       hr = 0.0;
       hi = 0.0;
     }
-    if (a.haf_out) a.haf_out[b] = make_double2(hr, hi);
-    if (a.prob_out) a.prob_out[b] = (*a.prefactor) * (hr * hr + hi * hi) / a.sfact[b];
+    const int64_t o = a.out_idx ? a.out_idx[b] : b;
+    if (a.haf_out) a.haf_out[o] = make_double2(hr, hi);
+    if (a.prob_out) a.prob_out[o] = (*a.prefactor) * (hr * hr + hi * hi) / a.sfact[b];
   }
 }
 
 // ---------------------------------------------------------------- state
 
-// B = U diag(tanh r) U^t (transpose), prefactor = prod_i 1/cosh r_i.
-__global__ void state_kernel(const double2* U, const double* r, int m, double2* B, double* prefactor) {
+// B = U diag(tanh r) U^t (transpose), W = U U^t, prefactor = prod_i 1/cosh r_i.
+__global__ void state_kernel(const double2* U, const double* r, int m, double2* B, double2* W, double* prefactor) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e < (int64_t)m * m) {
     const int i = (int)(e / m), j = (int)(e - (int64_t)(e / m) * m);
-    double br = 0.0, bi = 0.0;
+    double br = 0.0, bi = 0.0, wr = 0.0, wi = 0.0;
     for (int l = 0; l < m; ++l) {
       const double t = tanh(r[l]);
       const double2 p = cmul(U[(int64_t)i * m + l], U[(int64_t)j * m + l]);
       br = fma(t, p.x, br);
       bi = fma(t, p.y, bi);
+      wr += p.x;
+      wi += p.y;
     }
     B[e] = make_double2(br, bi);
+    W[e] = make_double2(wr, wi);
   }
   if (e == 0) {
     double pf = 1.0;
     for (int l = 0; l < m; ++l) pf /= cosh(r[l]);
     *prefactor = pf;
+  }
+}
+
+// ---------------------------------------------------------------- marginals (Theorem 1)
+
+// One wave per class. For each member A (in order) and each j, the 2j-subsets a of C = [k] minus A
+// are split into contiguous colex-rank ranges, one per lane: a lane unranks its first combination of
+// the |C| positions once and steps with Gosper's construction; positions map to prefix bits through
+// C's bit list. Lane sums are combined by a fixed butterfly, so the result does not depend on timing.
+__global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
+  __shared__ int32_t bitpos[32];
+  __shared__ double2 H[kMaxK + 1];
+  const int lane = threadIdx.x;
+  for (int64_t c = blockIdx.x; c < a.n_classes; c += gridDim.x) {
+    const int p = a.cls_prefix[c];
+    const int k = a.k[p];
+    const uint32_t full = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
+    const double2* h = a.h + a.h_off[p];
+    const uint32_t A0 = a.mem[a.cls_mem[c]];
+    const int mu = __popc(A0);
+    const int cs = k - mu;  // |C|, even by construction
+    if (lane <= cs / 2) H[lane] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int64_t q = a.cls_mem[c]; q < a.cls_mem[c + 1]; ++q) {
+      const uint32_t C = full & ~a.mem[q];
+      if (lane == 0) {
+        int t = 0;
+        for (uint32_t r = C; r; r &= r - 1u) bitpos[t++] = __builtin_ctz(r);
+      }
+      __syncthreads();
+      for (int j = 0; 2 * j <= cs; ++j) {
+        const int r = 2 * j;
+        const int64_t total = c_tab.binom[cs][r];
+        const int64_t per = (total + 63) / 64;
+        const int64_t lo = per * lane, hi = lo + per < total ? lo + per : total;
+        double sr = 0.0, si = 0.0;
+        if (lo < hi) {
+          // unrank combination lo (colex) of r positions among cs
+          uint32_t comb = 0;
+          int64_t rem = lo;
+          int top = cs - 1;
+          for (int i = r; i >= 1; --i) {
+            while (c_tab.binom[top][i] > rem) --top;
+            comb |= 1u << top;
+            rem -= c_tab.binom[top][i];
+            --top;
+          }
+          for (int64_t g = lo; g < hi; ++g) {
+            uint32_t sub = 0;
+            for (uint32_t t = comb; t; t &= t - 1u) sub |= 1u << bitpos[__builtin_ctz(t)];
+            const double2 x = h[sub], y = h[C ^ sub];
+            sr = fma(x.x, y.x, sr);
+            sr = fma(-x.y, y.y, sr);
+            si = fma(x.x, y.y, si);
+            si = fma(x.y, y.x, si);
+            if (comb) {  // Gosper: next larger mask with the same popcount
+              const uint32_t low = comb & (0u - comb);
+              const uint32_t ripple = comb + low;
+              comb = (((ripple ^ comb) >> 2) >> __builtin_ctz(comb)) | ripple;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          sr += __shfl_xor(sr, off, 64);
+          si += __shfl_xor(si, off, 64);
+        }
+        if (lane == 0) H[j] = make_double2(H[j].x + sr, H[j].y + si);
+      }
+      __syncthreads();  // bitpos reused by the next member
+    }
+    if (lane == 0) {
+      const double* F = a.F + a.F_off[p] + (int64_t)mu * a.jdim * a.jdim;
+      double v = 0.0;
+      for (int j1 = 0; 2 * j1 <= cs; ++j1)
+        for (int j2 = 0; 2 * j2 <= cs; ++j2) {
+          const double f = F[j1 * a.jdim + j2];
+          if (f != 0.0) v = fma(f, H[j1].x * H[j2].x + H[j1].y * H[j2].y, v);  // Re H_j1 conj(H_j2)
+        }
+      a.v[c] = a.cls_w[c] * v;
+    }
+    __syncthreads();
+  }
+}
+
+// q_p = sum of the prefix's class values, in class order (one wave per prefix, fixed tree).
+__global__ __launch_bounds__(64) void marg_sum_kernel(MargArgs a) {
+  const int lane = threadIdx.x;
+  for (int64_t p = blockIdx.x; p < a.batch; p += gridDim.x) {
+    const int64_t lo = a.pre_cls[p], hi = a.pre_cls[p + 1];
+    const int64_t per = (hi - lo + 63) / 64;
+    const int64_t b0 = lo + per * lane, b1 = b0 + per < hi ? b0 + per : hi;
+    double s = 0.0;
+    for (int64_t c = b0; c < b1; ++c) s += a.v[c];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) a.q_out[p] = s;
   }
 }
 
@@ -143,9 +244,20 @@ void launch_finalize(const FinalizeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 
-void launch_state(const double2* U, const double* r, int m, double2* B, double* prefactor, hipStream_t s) {
+void launch_state(const double2* U, const double* r, int m, double2* B, double2* W, double* prefactor, hipStream_t s) {
   int64_t total = (int64_t)m * m;
-  hipLaunchKernelGGL(state_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U, r, m, B, prefactor);
+  hipLaunchKernelGGL(state_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U, r, m, B, W, prefactor);
+}
+
+void launch_marginal(const MargArgs& a, hipStream_t s) {
+  if (a.n_classes > 0) {
+    const int64_t g = a.n_classes < 65536 ? a.n_classes : 65536;
+    hipLaunchKernelGGL(marg_class_kernel, dim3((unsigned)g), dim3(64), 0, s, a);
+  }
+  if (a.batch > 0) {
+    const int64_t g = a.batch < 65536 ? a.batch : 65536;
+    hipLaunchKernelGGL(marg_sum_kernel, dim3((unsigned)g), dim3(64), 0, s, a);
+  }
 }
 
 int upload_tables(const ConstTables& t) {

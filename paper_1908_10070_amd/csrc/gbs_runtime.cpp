@@ -113,6 +113,7 @@ struct gbs_state {
   int m = 0;
   double2* U = nullptr;
   double2* B = nullptr;
+  double2* W = nullptr;  // U U^t (marginal probabilities)
   double* r = nullptr;
   double* pref = nullptr;
   double pref_host = 0.0;
@@ -473,6 +474,32 @@ int pattern_sfact(gbs_ctx* ctx, const int32_t* modes, int64_t len, int32_t m, do
 
 // =================================================================== C ABI
 
+namespace {
+
+// log of the generalized binomial Gamma(a + 1) / (Gamma(b + 1) Gamma(a - b + 1)) for a + 1 > 0 and
+// b + 1 > 0; -inf when a - b is a negative integer (the binomial is zero there).
+double log_gbinom_pos(double a, double b) {
+  const double d = a - b;
+  if (d < 0 && d == std::floor(d)) return -INFINITY;
+  return std::lgamma(a + 1) - std::lgamma(b + 1) - std::lgamma(d + 1);
+}
+
+// Theorem 1 weight F = (n - k)! / f_n * C((n - k + mu + m)/2 - 1, k - j1 - j2 + m/2 - 1), with
+// f_n = n! C((m + n)/2 - 1, n/2); zero outside the theorem's ranges of j1, j2 and mu.
+double theorem1_weight(int m, int n, int k, int mu, int j1, int j2) {
+  const int jlo = std::max(0, k - n / 2);
+  if (j1 < jlo || j2 < jlo || 2 * j1 > k || 2 * j2 > k) return 0.0;
+  const int mu_lo = std::max(0, 3 * k - 2 * (j1 + j2) - n), mu_hi = k - 2 * std::max(j1, j2);
+  if (mu < mu_lo || mu > mu_hi || ((mu - k) & 1)) return 0.0;
+  const double lf = std::lgamma(n + 1.0) + log_gbinom_pos((m + n) / 2.0 - 1.0, n / 2.0);
+  const double lc = log_gbinom_pos((n - k + mu + m) / 2.0 - 1.0, k - j1 - j2 + m / 2.0 - 1.0);
+  if (std::isinf(lc)) return 0.0;
+  return std::exp(std::lgamma(n - k + 1.0) - lf + lc);
+}
+
+}  // namespace
+
+
 extern "C" {
 
 const char* gbs_status_str(int status) {
@@ -636,6 +663,7 @@ int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const doubl
   st->m = m;
   const size_t mm = (size_t)m * m;
   if (hipMalloc(&st->U, sizeof(double2) * mm) != hipSuccess || hipMalloc(&st->B, sizeof(double2) * mm) != hipSuccess ||
+      hipMalloc(&st->W, sizeof(double2) * mm) != hipSuccess ||
       hipMalloc(&st->r, sizeof(double) * m) != hipSuccess || hipMalloc(&st->pref, sizeof(double)) != hipSuccess ||
       hipEventCreateWithFlags(&st->ready, hipEventDisableTiming) != hipSuccess) {
     gbs_state_destroy(st);
@@ -644,7 +672,7 @@ int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const doubl
   hipError_t e = hipMemcpyAsync(st->U, U_dev, sizeof(double2) * mm, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(st->r, r_host, sizeof(double) * m, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
-    launch_state(st->U, st->r, m, st->B, st->pref, s);
+    launch_state(st->U, st->r, m, st->B, st->W, st->pref, s);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&st->pref_host, st->pref, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -663,6 +691,7 @@ int gbs_state_destroy(gbs_state* st) {
   if (st->ready) (void)hipEventSynchronize(st->ready);
   if (st->U) (void)hipFree(st->U);
   if (st->B) (void)hipFree(st->B);
+  if (st->W) (void)hipFree(st->W);
   if (st->r) (void)hipFree(st->r);
   if (st->pref) (void)hipFree(st->pref);
   if (st->ready) (void)hipEventDestroy(st->ready);
@@ -820,6 +849,199 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_
   fa.prob_out = prob_out_dev;
   fa.haf_out = reinterpret_cast<double2*>(haf_out_dev);
   launch_finalize(fa, s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
+  ctx->done_recorded = true;
+  return GBS_OK;
+}
+
+
+int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t* modes_host,
+                                  const int64_t* offsets_host, int64_t batch, double* q_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (batch == 0) return GBS_OK;
+  if (!st || !offsets_host || !q_out_dev) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (st->device != ctx->device) return fail(ctx, GBS_EINVAL, "state and context are on different devices");
+  if (n < 0 || (n & 1) || n > GBS_MARGINAL_NMAX)
+    return fail(ctx, GBS_ERANGE, "n = %d must be even and in [0, %d]", n, GBS_MARGINAL_NMAX);
+  if (batch > (int64_t)1 << 24) return fail(ctx, GBS_ERANGE, "batch too large");
+  if (offsets_host[0] != 0) return fail(ctx, GBS_EINVAL, "offsets[0] must be 0");
+  const int m = st->m;
+  int kmax = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    const int64_t len = offsets_host[b + 1] - offsets_host[b];
+    if (len < 0) return fail(ctx, GBS_EINVAL, "offsets must be non-decreasing");
+    if (len > n) return fail(ctx, GBS_ERANGE, "prefix %lld has %lld > n positions", (long long)b, (long long)len);
+    if (len > GBS_MARGINAL_KMAX)
+      return fail(ctx, GBS_ERANGE, "prefix %lld has %lld > %d positions", (long long)b, (long long)len,
+                  GBS_MARGINAL_KMAX);
+    for (int64_t i = offsets_host[b]; i < offsets_host[b + 1]; ++i)
+      if (!modes_host || modes_host[i] < 0 || modes_host[i] >= m)
+        return fail(ctx, GBS_ERANGE, "mode out of [0, %d) in prefix %lld", m, (long long)b);
+    kmax = std::max(kmax, (int)len);
+  }
+  const Tables& T = tables();
+  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
+
+  // 1. hafnians of W over every even-size subset of every prefix, scattered to h[h_off[p] + mask]
+  Plan pl;
+  ItemLists lists;
+  std::vector<int32_t> pmodes;
+  std::vector<int64_t> h_off(batch + 1, 0);
+  pl.part_off.push_back(0);
+  for (int64_t b = 0; b < batch; ++b) {
+    const int k = (int)(offsets_host[b + 1] - offsets_host[b]);
+    const int32_t* x = modes_host + offsets_host[b];
+    for (uint32_t mask = 0; mask < (1u << k); ++mask) {
+      const int c = __builtin_popcount(mask);
+      if (c & 1) continue;
+      const int64_t src = (int64_t)pmodes.size();
+      for (uint32_t r = mask; r; r &= r - 1u) pmodes.push_back(x[__builtin_ctz(r)]);
+      const int pi = (int)pl.pats.size();
+      pl.pats.push_back(PatternDesc{src, c, 0});
+      pl.nvec.push_back(c);
+      pl.sfact.push_back(1.0);
+      pl.out_idx.push_back(h_off[b] + mask);
+      plan_range(ctx, T.host, pl, lists, pi, c, 0, subset_count(c));
+      pl.part_off.push_back(pl.n_partials);
+    }
+    h_off[b + 1] = h_off[b] + ((int64_t)1 << k);
+  }
+  order_items(pl, lists);
+
+  // 2. classes of position sets A (|A| = k mod 2) with equal mode multisets; Per(S_{A,B}) = prod c_t!
+  std::vector<int32_t> k_vec(batch), cls_prefix;
+  std::vector<int64_t> cls_mem{0}, pre_cls{0}, F_off(batch);
+  std::vector<double> cls_w, Ftab;
+  std::vector<uint32_t> mem;
+  const int jdim = kmax / 2 + 1;
+  for (int64_t b = 0; b < batch; ++b) {
+    const int k = (int)(offsets_host[b + 1] - offsets_host[b]);
+    const int32_t* x = modes_host + offsets_host[b];
+    k_vec[b] = k;
+    std::vector<int> code(k);
+    std::vector<int32_t> distinct;
+    for (int i = 0; i < k; ++i) {
+      auto it = std::find(distinct.begin(), distinct.end(), x[i]);
+      code[i] = (int)(it - distinct.begin());
+      if (it == distinct.end()) distinct.push_back(x[i]);
+    }
+    const bool collision_free = (int)distinct.size() == k;
+    std::map<std::vector<uint8_t>, int64_t> index;
+    std::vector<std::vector<uint32_t>> members;
+    std::vector<double> weights;
+    for (uint32_t A = 0; A < (1u << k); ++A) {
+      if ((__builtin_popcount(A) ^ k) & 1) continue;
+      if (collision_free) {
+        members.push_back({A});
+        weights.push_back(1.0);
+        continue;
+      }
+      std::vector<uint8_t> cnt(distinct.size(), 0);
+      for (uint32_t r = A; r; r &= r - 1u) ++cnt[code[__builtin_ctz(r)]];
+      auto it = index.find(cnt);
+      if (it == index.end()) {
+        double w = 1.0;
+        for (uint8_t c : cnt)
+          for (int f = 2; f <= c; ++f) w *= f;
+        index.emplace(cnt, (int64_t)members.size());
+        members.push_back({A});
+        weights.push_back(w);
+      } else {
+        members[it->second].push_back(A);
+      }
+    }
+    for (size_t c = 0; c < members.size(); ++c) {
+      cls_prefix.push_back((int32_t)b);
+      mem.insert(mem.end(), members[c].begin(), members[c].end());
+      cls_mem.push_back((int64_t)mem.size());
+      cls_w.push_back(weights[c]);
+    }
+    pre_cls.push_back((int64_t)cls_prefix.size());
+    F_off[b] = (int64_t)Ftab.size();
+    for (int mu = 0; mu <= k; ++mu)
+      for (int j1 = 0; j1 < jdim; ++j1)
+        for (int j2 = 0; j2 < jdim; ++j2) Ftab.push_back(theorem1_weight(m, n, k, mu, j1, j2));
+  }
+  const int64_t ncls = (int64_t)cls_prefix.size();
+
+  // 3. device layout: the hafnian plan, then h, then the staged class data, then the class values
+  DeviceGuard dg(ctx->device);
+  const Layout L = layout_for(pl, pmodes.size());
+  size_t off = al(L.total);
+  const size_t o_h = off;
+  off += al(sizeof(double2) * (size_t)h_off[batch]);
+  const size_t o_stage = off;
+  const size_t o_hoff = off;
+  off += al(sizeof(int64_t) * h_off.size());
+  const size_t o_k = off;
+  off += al(sizeof(int32_t) * k_vec.size());
+  const size_t o_F = off;
+  off += al(sizeof(double) * Ftab.size());
+  const size_t o_Foff = off;
+  off += al(sizeof(int64_t) * F_off.size());
+  const size_t o_cp = off;
+  off += al(sizeof(int32_t) * cls_prefix.size());
+  const size_t o_cm = off;
+  off += al(sizeof(int64_t) * cls_mem.size());
+  const size_t o_cw = off;
+  off += al(sizeof(double) * cls_w.size());
+  const size_t o_mem = off;
+  off += al(sizeof(uint32_t) * mem.size());
+  const size_t o_pre = off;
+  off += al(sizeof(int64_t) * pre_cls.size());
+  const size_t stage_bytes = off - o_stage;
+  const size_t o_v = off;
+  off += al(sizeof(double) * (size_t)std::max<int64_t>(ncls, 1));
+  int rc = ensure_ws(ctx, off);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = run_plan(ctx, pl, pmodes.data(), pmodes.size(), st->W, m, st->pref, nullptr,
+                reinterpret_cast<double2*>(static_cast<unsigned char*>(ctx->ws) + o_h), nullptr, s);
+  if (rc) return rc;
+
+  const int pi = ctx->pin_idx;
+  ctx->pin_idx ^= 1;
+  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
+  rc = ensure_pinned(ctx, pi, stage_bytes);
+  if (rc) return rc;
+  unsigned char* hp = static_cast<unsigned char*>(ctx->pinned[pi]);
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(hp + (o - o_stage), src, bytes);
+  };
+  put(o_hoff, h_off.data(), sizeof(int64_t) * h_off.size());
+  put(o_k, k_vec.data(), sizeof(int32_t) * k_vec.size());
+  put(o_F, Ftab.data(), sizeof(double) * Ftab.size());
+  put(o_Foff, F_off.data(), sizeof(int64_t) * F_off.size());
+  put(o_cp, cls_prefix.data(), sizeof(int32_t) * cls_prefix.size());
+  put(o_cm, cls_mem.data(), sizeof(int64_t) * cls_mem.size());
+  put(o_cw, cls_w.data(), sizeof(double) * cls_w.size());
+  put(o_mem, mem.data(), sizeof(uint32_t) * mem.size());
+  put(o_pre, pre_cls.data(), sizeof(int64_t) * pre_cls.size());
+  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  HIPCHK(ctx, hipMemcpyAsync(ws + o_stage, hp, stage_bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], s));
+  ctx->pinned_used[pi] = true;
+
+  MargArgs ma{};
+  ma.h = reinterpret_cast<const double2*>(ws + o_h);
+  ma.h_off = reinterpret_cast<const int64_t*>(ws + o_hoff);
+  ma.k = reinterpret_cast<const int32_t*>(ws + o_k);
+  ma.F = reinterpret_cast<const double*>(ws + o_F);
+  ma.F_off = reinterpret_cast<const int64_t*>(ws + o_Foff);
+  ma.cls_prefix = reinterpret_cast<const int32_t*>(ws + o_cp);
+  ma.cls_mem = reinterpret_cast<const int64_t*>(ws + o_cm);
+  ma.cls_w = reinterpret_cast<const double*>(ws + o_cw);
+  ma.mem = reinterpret_cast<const uint32_t*>(ws + o_mem);
+  ma.n_classes = ncls;
+  ma.v = reinterpret_cast<double*>(ws + o_v);
+  ma.pre_cls = reinterpret_cast<const int64_t*>(ws + o_pre);
+  ma.batch = batch;
+  ma.jdim = jdim;
+  ma.q_out = q_out_dev;
+  launch_marginal(ma, s);
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
   ctx->done_recorded = true;

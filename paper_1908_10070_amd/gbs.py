@@ -20,6 +20,7 @@ LIB_PATH = pathlib.Path(os.environ.get("GBS_LIB") or (_HERE / "libgbs.so"))
 
 GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6)
 GBS_N_MAX = 46
+GBS_MARGINAL_KMAX = 20
 
 # Every function declared in include/gbs.h.
 EXPORTS = [
@@ -27,7 +28,7 @@ EXPORTS = [
     "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops", "haf_batch", "haf_batch_varlen",
     "gbs_state_create", "gbs_state_destroy", "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch",
     "gbs_subset_count",
-    "gbs_prob_slices", "gbs_finalize",
+    "gbs_prob_slices", "gbs_finalize", "gbs_marginal_batch",
 ]
 
 _lib = None
@@ -72,6 +73,7 @@ def lib() -> ctypes.CDLL:
         "gbs_subset_count": (i64, [i32]),
         "gbs_prob_slices": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, dp, vp]),
         "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, dp, i64, dp, dp, vp]),
+        "gbs_marginal_batch": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -266,6 +268,17 @@ class Context:
         self._check(lib().gbs_prob_batch(self.handle, state.handle, _np_ptr(modes), _np_ptr(offsets), b,
                                          _t_ptr(prob_out), _t_ptr(haf_out), _stream_ptr(stream)))
         return (prob_out, haf_out) if want_haf else prob_out
+
+    def marginal_batch(self, state: State, n: int, prefixes, q_out=None, stream=None):
+        """Marginal probabilities q_n(x_1..x_k) of position prefixes for n photons (Theorem 1)."""
+        import torch
+        modes, offsets = pack_patterns(prefixes)
+        b = len(offsets) - 1
+        if q_out is None:
+            q_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
+        self._check(lib().gbs_marginal_batch(self.handle, state.handle, int(n), _np_ptr(modes), _np_ptr(offsets), b,
+                                             _t_ptr(q_out), _stream_ptr(stream)))
+        return q_out
 
     def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, out_idx=None, stream=None):
         """Compensated partial sums over subset ranges [lo, hi) -> float64 tensor of (s_re, s_im, c_re, c_im)

@@ -1,0 +1,108 @@
+"""Marginal probabilities of photon-position prefixes on the GPU (gbs_marginal_batch, Theorem 1)
+against the oracle, and their closed forms and consistency at sizes the oracle does not reach."""
+import numpy as np
+import pytest
+
+from oracle import marginal as M
+from paper_1908_10070_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10  # relative; FP64 hafnians (about 1e-13) combined by about 3^k / 2 products
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_10070_amd import gbs
+    ctx = gbs.Context(0)
+    dev = torch.device("cuda", 0)
+    out = {}
+    for m in (5, 8, 16, 36):
+        U = inputs.haar_unitary(m, np.random.default_rng(700 + m))
+        st = ctx.state(torch.from_numpy(U).to(dev), np.full(m, 0.5))
+        out[m] = (st, U @ U.T)
+    return ctx, out
+
+
+def run(ctx, st, n, prefixes):
+    return ctx.marginal_batch(st, n, prefixes).cpu().numpy()
+
+
+def test_small_cases_vs_oracle(env):
+    ctx, states = env
+    rng = np.random.default_rng(91)
+    for m, n, ks in [(5, 6, range(0, 7)), (8, 8, range(0, 9)), (16, 10, range(0, 9)), (36, 12, range(0, 9))]:
+        st, W = states[m]
+        prefixes = [[int(v) for v in rng.integers(0, m, size=k)] for k in ks for _ in range(2)]
+        got = run(ctx, st, n, prefixes)
+        for p, g in zip(prefixes, got):
+            ref = M.marginal_split(W, p, n)
+            assert abs(g - ref) <= TOL * ref, (m, n, p, g, ref)
+            if m ** (n - len(p)) <= 4000:
+                b = M.marginal_brute(W, p, n)
+                assert abs(g - b) <= TOL * b
+
+
+def test_collision_free_and_colliding_k10_k12_vs_oracle(env):
+    ctx, states = env
+    st, W = states[16]
+    prefixes = [[0, 2, 4, 6, 8, 10, 12, 14, 1, 3], [0, 2, 4, 6, 8, 10, 12, 14, 1, 3, 5, 7],
+                [0, 2, 2, 6, 8, 8, 12, 14, 1, 3, 2, 7], [5, 5, 5, 5, 1, 1, 9, 9, 9, 0]]
+    got = run(ctx, st, 16, prefixes)
+    for p, g in zip(prefixes, got):
+        ref = M.marginal_split(W, p, 16)
+        assert abs(g - ref) <= TOL * ref, (p, g, ref)
+
+
+def test_closed_forms(env):
+    ctx, states = env
+    for m in (5, 16, 36):
+        st, _ = states[m]
+        got = run(ctx, st, 12, [[], [0], [m - 1], [m // 2]])
+        assert abs(got[0] - 1.0) < 1e-12
+        assert np.all(np.abs(got[1:] - 1.0 / m) < 1e-12 / m * 10)
+
+
+def test_chain_consistency_large_k(env):
+    """sum over x_k of q(x_1..x_k) = q(x_1..x_{k-1}) at k the oracle cannot reach quickly."""
+    ctx, states = env
+    rng = np.random.default_rng(92)
+    for m, k, n in [(16, 14, 20), (8, 16, 20), (8, 18, 24)]:
+        st, _ = states[m]
+        pre = [int(v) for v in rng.integers(0, m, size=k - 1)]
+        parent = run(ctx, st, n, [pre])[0]
+        kids = run(ctx, st, n, [pre + [l] for l in range(m)])
+        assert abs(kids.sum() - parent) <= 1e-9 * parent, (m, k, kids.sum(), parent)
+        assert np.all(kids > 0)
+
+
+def test_full_prefix_is_sequence_probability(env):
+    ctx, states = env
+    st, W = states[8]
+    x = [3, 0, 7, 0, 1, 2, 5, 5]
+    got = run(ctx, st, 8, [x])[0]
+    ref = M.q_sequence(W, x)
+    assert abs(got - ref) <= TOL * ref
+
+
+def test_deterministic_and_batch_invariant(env):
+    ctx, states = env
+    st, _ = states[16]
+    rng = np.random.default_rng(93)
+    prefixes = [[int(v) for v in rng.integers(0, 16, size=k)] for k in (3, 7, 10, 12, 5)]
+    a = run(ctx, st, 14, prefixes)
+    b = run(ctx, st, 14, prefixes)
+    c = np.array([run(ctx, st, 14, [p])[0] for p in prefixes])
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_invalid_inputs_raise(env):
+    from paper_1908_10070_amd import gbs
+    ctx, states = env
+    st, _ = states[8]
+    for n, pre in [(7, [[0]]), (4, [[0, 1, 2, 3, 4]]), (40, [list(range(8)) * 3]), (8, [[8]]), (8, [[-1]])]:
+        with pytest.raises(gbs.GBSError):
+            run(ctx, st, n, pre)

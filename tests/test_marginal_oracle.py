@@ -87,3 +87,15 @@ def test_planted_mistakes_break_the_brute_force_pin(monkeypatch):
         assert abs(M.marginal_thm1(W, prefix, n) - b) > 1e-3 * b
     finally:
         monkeypatch.setattr(M.np, "conj", conj)
+
+
+def test_per01_is_the_permutation_sum():
+    import itertools
+    rng = np.random.default_rng(0)
+    for r in range(0, 7):
+        for _ in range(10):
+            S = (rng.random((r, r)) < 0.6).astype(int)
+            brute = sum(all(S[i, p[i]] for i in range(r)) for p in itertools.permutations(range(r)))
+            assert M.per01(S) == brute
+    # all-ones block of size c has permanent c!
+    assert M.per01(np.ones((5, 5), dtype=int)) == 120
