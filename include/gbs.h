@@ -192,6 +192,23 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partia
 int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* state, int32_t n, const int32_t* modes_host,
                        const int64_t* offsets_host, int64_t batch, double* q_out_dev, void* stream);
 
+/* ------------------------------------------- sampling (Sec. III A-C, Alg. 1) */
+
+/* Step 1: P_n = C((m+n)/2 - 1, n/2) tanh^n r / cosh^m r for n = 0..nmax (0 for odd n), identical
+ * squeezing r >= 0 on m modes (Eq. Eqdistribution); host only. The caller truncates and
+ * renormalises as the paper does. Returns GBS_EINVAL for m <= 0, nmax < 0, r < 0 or NULL. */
+int gbs_photon_number_pmf(int32_t m, double r, int32_t nmax, double* pmf_host);
+
+/* One step of the chain rule (Eq. ConPro): for each prefix b (k - 1 < n positions) the weights
+ * w[b][l] = q_n(x_1..x_{k-1}, l), l in [0, m), are the marginals of gbs_marginal_batch, and
+ * next_dev[b] = the smallest l with w[b][0] + .. + w[b][l] >= uniforms_dev[b] * sum_l w[b][l]
+ * (inverse CDF; uniforms in [0, 1) are the caller's random numbers, so a draw is reproducible).
+ * weights_dev (nullable, batch x m doubles) receives the weights. Limits and errors as for
+ * gbs_marginal_batch with k = prefix length + 1; batch x m <= 2^24. */
+int gbs_sample_step(gbs_ctx* ctx, const gbs_state* state, int32_t n, const int32_t* modes_host,
+                    const int64_t* offsets_host, int64_t batch, const double* uniforms_dev,
+                    double* weights_dev, int32_t* next_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,6 +114,8 @@ void launch_reset(int32_t* counter, int n, hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
 void launch_state(const double2* U, const double* r, int m, double2* B, double2* W, double* prefactor, hipStream_t s);
 void launch_marginal(const MargArgs& a, hipStream_t s);
+// next[b] = smallest l in [0, m) with w[b][0] + ... + w[b][l] >= u[b] * (w[b][0] + ... + w[b][m-1])
+void launch_draw(const double* w, int64_t batch, int m, const double* u, int32_t* next, hipStream_t s);
 int upload_tables(const ConstTables& t);
 
 }  // namespace gbs

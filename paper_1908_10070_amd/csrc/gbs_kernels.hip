@@ -249,6 +249,31 @@ void launch_state(const double2* U, const double* r, int m, double2* B, double2*
   hipLaunchKernelGGL(state_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U, r, m, B, W, prefactor);
 }
 
+// Inverse-CDF draw from unnormalised weights, one thread per row, sums in index order.
+__global__ void draw_kernel(const double* w, int64_t batch, int m, const double* u, int32_t* next) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double* row = w + b * m;
+  double tot = 0.0;
+  for (int l = 0; l < m; ++l) tot += row[l];
+  const double t = u[b] * tot;
+  double acc = 0.0;
+  int pick = m - 1;
+  for (int l = 0; l < m; ++l) {
+    acc += row[l];
+    if (acc >= t && row[l] > 0.0) {
+      pick = l;
+      break;
+    }
+  }
+  next[b] = pick;
+}
+
+void launch_draw(const double* w, int64_t batch, int m, const double* u, int32_t* next, hipStream_t s) {
+  if (batch <= 0) return;
+  hipLaunchKernelGGL(draw_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, w, batch, m, u, next);
+}
+
 void launch_marginal(const MargArgs& a, hipStream_t s) {
   if (a.n_classes > 0) {
     const int64_t g = a.n_classes < 65536 ? a.n_classes : 65536;

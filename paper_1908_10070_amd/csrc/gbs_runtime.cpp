@@ -856,13 +856,91 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_
 }
 
 
+namespace {
+
+// Marginals of `batch` prefixes into q_out (device); `extra` bytes of workspace are reserved after
+// the marginal's own layout and returned in *extra_dev (for a caller's follow-up kernels).
+int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t* modes_host,
+                    const int64_t* offsets_host, int64_t batch, double* q_out_dev, size_t extra, void** extra_dev,
+                    hipStream_t s);
+
+}  // namespace
+
 int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t* modes_host,
-                                  const int64_t* offsets_host, int64_t batch, double* q_out_dev, void* stream) {
+                       const int64_t* offsets_host, int64_t batch, double* q_out_dev, void* stream) {
   if (!ctx) return GBS_EINVAL;
   ctx->last_error.clear();
   if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
   if (batch == 0) return GBS_OK;
   if (!st || !offsets_host || !q_out_dev) return fail(ctx, GBS_EINVAL, "null pointer");
+  return marginal_common(ctx, st, n, modes_host, offsets_host, batch, q_out_dev, 0, nullptr,
+                         static_cast<hipStream_t>(stream));
+}
+
+int gbs_photon_number_pmf(int32_t m, double r, int32_t nmax, double* pmf_host) {
+  if (m <= 0 || nmax < 0 || !pmf_host || !std::isfinite(r) || r < 0) return GBS_EINVAL;
+  for (int n = 0; n <= nmax; ++n) {
+    if (n & 1) {
+      pmf_host[n] = 0.0;
+      continue;
+    }
+    if (r == 0.0) {
+      pmf_host[n] = n == 0 ? 1.0 : 0.0;
+      continue;
+    }
+    // P_n = C((m + n)/2 - 1, n/2) tanh^n r / cosh^m r, the binomial in Gamma form
+    const double lb = n == 0 ? 0.0 : log_gbinom_pos((m + n) / 2.0 - 1.0, n / 2.0);
+    pmf_host[n] = std::exp(lb + n * std::log(std::tanh(r)) - m * std::log(std::cosh(r)));
+  }
+  return GBS_OK;
+}
+
+int gbs_sample_step(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t* modes_host,
+                    const int64_t* offsets_host, int64_t batch, const double* uniforms_dev, double* weights_dev,
+                    int32_t* next_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (batch == 0) return GBS_OK;
+  if (!st || !offsets_host || !uniforms_dev || !next_dev) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (offsets_host[0] != 0) return fail(ctx, GBS_EINVAL, "offsets[0] must be 0");
+  const int m = st->m;
+  if ((int64_t)batch * m > (int64_t)1 << 24) return fail(ctx, GBS_ERANGE, "batch x m too large");
+  // candidate prefixes: prefix b followed by each mode l
+  std::vector<int32_t> cm;
+  std::vector<int64_t> co{0};
+  for (int64_t b = 0; b < batch; ++b) {
+    const int64_t len = offsets_host[b + 1] - offsets_host[b];
+    if (len < 0) return fail(ctx, GBS_EINVAL, "offsets must be non-decreasing");
+    if (len >= n) return fail(ctx, GBS_ERANGE, "prefix %lld already has n positions", (long long)b);
+    if (len > 0 && !modes_host) return fail(ctx, GBS_EINVAL, "null modes");
+    for (int l = 0; l < m; ++l) {
+      cm.insert(cm.end(), modes_host + offsets_host[b], modes_host + offsets_host[b + 1]);
+      cm.push_back(l);
+      co.push_back((int64_t)cm.size());
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* scratch = nullptr;
+  const size_t wbytes = sizeof(double) * (size_t)batch * m;
+  int rc = marginal_common(ctx, st, n, cm.data(), co.data(), batch * m, weights_dev, weights_dev ? 0 : wbytes,
+                           &scratch, s);
+  if (rc) return rc;
+  const double* w = weights_dev ? weights_dev : static_cast<const double*>(scratch);
+  DeviceGuard dg(ctx->device);
+  launch_draw(w, batch, m, uniforms_dev, next_dev, s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
+  ctx->done_recorded = true;
+  return GBS_OK;
+}
+
+namespace {
+
+int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t* modes_host,
+                    const int64_t* offsets_host, int64_t batch, double* q_out_dev, size_t extra, void** extra_dev,
+                    hipStream_t s) {
+  if (!q_out_dev && !extra_dev) return fail(ctx, GBS_EINVAL, "null q_out");
   if (st->device != ctx->device) return fail(ctx, GBS_EINVAL, "state and context are on different devices");
   if (n < 0 || (n & 1) || n > GBS_MARGINAL_NMAX)
     return fail(ctx, GBS_ERANGE, "n = %d must be even and in [0, %d]", n, GBS_MARGINAL_NMAX);
@@ -995,9 +1073,12 @@ int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32
   const size_t stage_bytes = off - o_stage;
   const size_t o_v = off;
   off += al(sizeof(double) * (size_t)std::max<int64_t>(ncls, 1));
+  const size_t o_extra = off;
+  off += al(extra);
   int rc = ensure_ws(ctx, off);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (extra_dev) *extra_dev = static_cast<unsigned char*>(ctx->ws) + o_extra;
+  if (!q_out_dev) q_out_dev = reinterpret_cast<double*>(static_cast<unsigned char*>(ctx->ws) + o_extra);
   rc = run_plan(ctx, pl, pmodes.data(), pmodes.size(), st->W, m, st->pref, nullptr,
                 reinterpret_cast<double2*>(static_cast<unsigned char*>(ctx->ws) + o_h), nullptr, s);
   if (rc) return rc;
@@ -1047,5 +1128,7 @@ int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32
   ctx->done_recorded = true;
   return GBS_OK;
 }
+
+}  // namespace
 
 }  // extern "C"

@@ -28,7 +28,7 @@ EXPORTS = [
     "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops", "haf_batch", "haf_batch_varlen",
     "gbs_state_create", "gbs_state_destroy", "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch",
     "gbs_subset_count",
-    "gbs_prob_slices", "gbs_finalize", "gbs_marginal_batch",
+    "gbs_prob_slices", "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step",
 ]
 
 _lib = None
@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
         "gbs_prob_slices": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, dp, vp]),
         "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, dp, i64, dp, dp, vp]),
         "gbs_marginal_batch": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, vp]),
+        "gbs_photon_number_pmf": (ctypes.c_int, [i32, ctypes.c_double, i32, dp]),
+        "gbs_sample_step": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -280,6 +282,23 @@ class Context:
                                              _t_ptr(q_out), _stream_ptr(stream)))
         return q_out
 
+    def sample_step(self, state: State, n: int, prefixes, uniforms, weights_out=None, stream=None):
+        """One chain-rule step: the next position of every prefix, drawn by inverse CDF with the given
+        uniforms (a CUDA float64 tensor, one per prefix) -> int32 tensor; optionally the weights."""
+        import torch
+        modes, offsets = pack_patterns(prefixes)
+        b = len(offsets) - 1
+        if uniforms.dtype != torch.float64 or not uniforms.is_cuda or uniforms.numel() != b:
+            raise ValueError("uniforms must be a CUDA float64 tensor with one value per prefix")
+        nxt = torch.empty(b, dtype=torch.int32, device=self.torch_device)
+        u = uniforms.contiguous()
+        if weights_out is not None and (weights_out.dtype != torch.float64 or not weights_out.is_contiguous()
+                                        or weights_out.numel() != b * state.m):
+            raise ValueError("weights_out must be a contiguous float64 tensor of prefixes x m")
+        self._check(lib().gbs_sample_step(self.handle, state.handle, int(n), _np_ptr(modes), _np_ptr(offsets), b,
+                                          _t_ptr(u), _t_ptr(weights_out), _t_ptr(nxt), _stream_ptr(stream)))
+        return nxt
+
     def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, out_idx=None, stream=None):
         """Compensated partial sums over subset ranges [lo, hi) -> float64 tensor of (s_re, s_im, c_re, c_im)
         rows; slice b goes to row out_idx[b] (default b)."""
@@ -322,6 +341,15 @@ class Context:
                                        _t_ptr(prob_out) if want_prob else None, _t_ptr(haf_out),
                                        _stream_ptr(stream)))
         return (prob_out if want_prob else None), haf_out
+
+
+def photon_number_pmf(m: int, r: float, nmax: int) -> np.ndarray:
+    """P_n for n = 0..nmax (Step 1), computed by the library on the host."""
+    out = np.zeros(nmax + 1, dtype=np.float64)
+    rc = lib().gbs_photon_number_pmf(int(m), float(r), int(nmax), _np_ptr(out))
+    if rc:
+        raise GBSError(rc, "gbs_photon_number_pmf failed")
+    return out
 
 
 def sfact_of(modes: Sequence[int]) -> float:

@@ -74,3 +74,14 @@ def test_pack_patterns():
     modes, off = gbs.pack_patterns(np.array([[0, 1], [2, 3]]))
     assert off.tolist() == [0, 2, 4]
     assert gbs.sfact_of([1, 1, 2, 2, 2, 5]) == 2 * 6
+
+
+def test_photon_number_pmf_matches_oracle():
+    """Step 1's table is host code in the library: P_n against the oracle's closed form."""
+    import oracle
+    from paper_1908_10070_amd import gbs
+    for m, r in [(16, 0.5), (36, 0.3423), (5, 0.8814)]:
+        p = gbs.photon_number_pmf(m, r, 60)
+        for n in range(61):
+            assert abs(p[n] - oracle.photon_number_prob(m, n, r)) <= 1e-12 * max(p[n], 1e-300) + 1e-300
+    assert abs(gbs.photon_number_pmf(36, 0.3423, 400).sum() - 1.0) < 1e-12
