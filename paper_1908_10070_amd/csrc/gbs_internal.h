@@ -80,25 +80,32 @@ struct FinalizeArgs {
   const int64_t* out_idx;     // nullable: result b goes to index out_idx[b] of the output it writes
 };
 
-// Marginal probabilities (Theorem 1, regrouped): per prefix p of k positions, hafnians h[mask] of W
-// restricted to every even-size subset of the positions (mask over k bits), and classes of position
-// sets A with the same mode multiset. For class c (all members of size mu):
+// Marginal probabilities (Theorem 1, regrouped). Per prefix p of k positions (modes x), h[mask] is
+// the hafnian of W restricted to the positions in mask (every even-size mask over k bits), built
+// size by size from h(S) = sum_{j in S, j > i0} W(x_i0, x_j) h(S minus {i0, j}), i0 = lowest of S.
+// Position sets A with the same mode multiset form a class; for class c (all members of size mu)
 //   H_j = sum over members A of sum over 2j-subsets a of C = [k] minus A of h[a] h[C minus a],
 //   v_c = w_c * Re sum_{j1, j2} F[mu][j1][j2] H_{j1} conj(H_{j2}),
-// and q_p = sum of v_c over the prefix's classes in class order.
+// and q_p = sum of v_c over the prefix's classes in class order. A collision-free prefix has one
+// class per A with |A| = k mod 2, numbered implicitly (class i <-> A = 2i + parity bit, w = 1);
+// other prefixes list their classes explicitly.
 struct MargArgs {
-  const double2* h;          // hafnians; prefix p's table starts at h_off[p]
+  const double2* W;          // m x m, row-major
+  int32_t m;
+  const int32_t* x;          // prefix modes, prefix p at x_off[p]
+  const int64_t* x_off;
+  double2* h;                // hafnian tables; prefix p's starts at h_off[p] (2^k entries)
   const int64_t* h_off;
   const int32_t* k;          // prefix lengths
-  const double* F;           // per prefix (k + 1) x (kmax/2 + 1)^2 weights, F_off[p]
+  const double* F;           // per prefix (k + 1) x jdim x jdim weights at F_off[p]
   const int64_t* F_off;
-  const int32_t* cls_prefix; // per class: prefix
-  const int64_t* cls_mem;    // per class: members cls_mem[c] .. cls_mem[c + 1] of mem
-  const double* cls_w;       // per class: Per(S_{A,B}) for A, B in the class
+  const int64_t* pre_cls;    // per prefix: classes pre_cls[p] .. pre_cls[p + 1] (global numbering)
+  const int64_t* ex_base;    // per prefix: first explicit class, or -1 if the prefix is collision-free
+  const int64_t* cls_mem;    // explicit class e: members cls_mem[e] .. cls_mem[e + 1] of mem
+  const double* cls_w;       // explicit class e: Per(S_{A,B}) for A, B in the class
   const uint32_t* mem;       // member masks A
-  int64_t n_classes;
+  int64_t n_classes;         // total (implicit + explicit)
   double* v;                 // per class value
-  const int64_t* pre_cls;    // per prefix: classes pre_cls[p] .. pre_cls[p + 1]
   int64_t batch;
   int32_t jdim;              // kmax / 2 + 1
   double* q_out;             // per prefix marginal
@@ -113,7 +120,7 @@ void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream
 void launch_reset(int32_t* counter, int n, hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
 void launch_state(const double2* U, const double* r, int m, double2* B, double2* W, double* prefactor, hipStream_t s);
-void launch_marginal(const MargArgs& a, hipStream_t s);
+void launch_marginal(const MargArgs& a, int kmax, int64_t h_total, hipStream_t s);
 // next[b] = smallest l in [0, m) with w[b][0] + ... + w[b][l] >= u[b] * (w[b][0] + ... + w[b][m-1])
 void launch_draw(const double* w, int64_t batch, int m, const double* u, int32_t* next, hipStream_t s);
 int upload_tables(const ConstTables& t);

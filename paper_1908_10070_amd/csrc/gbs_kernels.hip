@@ -18,6 +18,7 @@
 //     item order, so the result depends only on n and the chunking, never on the batch around it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "gbs_internal.h"
@@ -131,6 +132,49 @@ __global__ void state_kernel(const double2* U, const double* r, int m, double2* 
 
 // ---------------------------------------------------------------- marginals (Theorem 1)
 
+// Prefix holding global index t of a table with per-prefix starts off[0..batch] (binary search).
+__device__ __forceinline__ int64_t owner(const int64_t* off, int64_t batch, int64_t t) {
+  int64_t lo = 0, hi = batch;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Subset hafnians of size `level` (even) for every prefix: the expansion of the matching sum along
+// the lowest position of S (Eq. HafMatch), from the tables of size level - 2.
+__global__ void subset_haf_kernel(MargArgs a, int level) {
+  const int64_t total = a.h_off[a.batch];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = owner(a.h_off, a.batch, t);
+    const uint32_t S = (uint32_t)(t - a.h_off[p]);
+    if (__popc(S) != level) continue;
+    double2* h = a.h + a.h_off[p];
+    if (level == 0) {
+      h[0] = make_double2(1.0, 0.0);
+      continue;
+    }
+    const int32_t* x = a.x + a.x_off[p];
+    const int i0 = __builtin_ctz(S);
+    const uint32_t R = S & (S - 1u);
+    const double2* Wrow = a.W + (int64_t)x[i0] * a.m;
+    double sr = 0.0, si = 0.0;
+    for (uint32_t r = R; r; r &= r - 1u) {
+      const int j = __builtin_ctz(r);
+      const double2 w = Wrow[x[j]];
+      const double2 g = h[R ^ (1u << j)];
+      sr = fma(w.x, g.x, sr);
+      sr = fma(-w.y, g.y, sr);
+      si = fma(w.x, g.y, si);
+      si = fma(w.y, g.x, si);
+    }
+    h[S] = make_double2(sr, si);
+  }
+}
+
 // One wave per class. For each member A (in order) and each j, the 2j-subsets a of C = [k] minus A
 // are split into contiguous colex-rank ranges, one per lane: a lane unranks its first combination of
 // the |C| positions once and steps with Gosper's construction; positions map to prefix bits through
@@ -140,17 +184,30 @@ __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
   __shared__ double2 H[kMaxK + 1];
   const int lane = threadIdx.x;
   for (int64_t c = blockIdx.x; c < a.n_classes; c += gridDim.x) {
-    const int p = a.cls_prefix[c];
+    const int64_t p = owner(a.pre_cls, a.batch, c);
     const int k = a.k[p];
     const uint32_t full = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
     const double2* h = a.h + a.h_off[p];
-    const uint32_t A0 = a.mem[a.cls_mem[c]];
+    const int64_t eb = a.ex_base[p];
+    int64_t m_lo = 0, m_hi = 1;
+    uint32_t A_impl = 0;
+    double w = 1.0;
+    if (eb < 0) {  // collision-free: class i is the single set A = 2i + parity bit
+      const uint32_t i = (uint32_t)(c - a.pre_cls[p]);
+      A_impl = (i << 1) | ((uint32_t)(__popc(i) + k) & 1u);
+    } else {
+      const int64_t e = eb + (c - a.pre_cls[p]);
+      m_lo = a.cls_mem[e];
+      m_hi = a.cls_mem[e + 1];
+      w = a.cls_w[e];
+    }
+    const uint32_t A0 = eb < 0 ? A_impl : a.mem[m_lo];
     const int mu = __popc(A0);
     const int cs = k - mu;  // |C|, even by construction
     if (lane <= cs / 2) H[lane] = make_double2(0.0, 0.0);
     __syncthreads();
-    for (int64_t q = a.cls_mem[c]; q < a.cls_mem[c + 1]; ++q) {
-      const uint32_t C = full & ~a.mem[q];
+    for (int64_t q = m_lo; q < m_hi; ++q) {
+      const uint32_t C = full & ~(eb < 0 ? A_impl : a.mem[q]);
       if (lane == 0) {
         int t = 0;
         for (uint32_t r = C; r; r &= r - 1u) bitpos[t++] = __builtin_ctz(r);
@@ -205,7 +262,7 @@ __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
           const double f = F[j1 * a.jdim + j2];
           if (f != 0.0) v = fma(f, H[j1].x * H[j2].x + H[j1].y * H[j2].y, v);  // Re H_j1 conj(H_j2)
         }
-      a.v[c] = a.cls_w[c] * v;
+      a.v[c] = w * v;
     }
     __syncthreads();
   }
@@ -274,15 +331,18 @@ void launch_draw(const double* w, int64_t batch, int m, const double* u, int32_t
   hipLaunchKernelGGL(draw_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, w, batch, m, u, next);
 }
 
-void launch_marginal(const MargArgs& a, hipStream_t s) {
+void launch_marginal(const MargArgs& a, int kmax, int64_t h_total, hipStream_t s) {
+  if (a.batch <= 0) return;
+  // hafnian tables, size by size (each level reads the previous one)
+  const int64_t blocks = std::min<int64_t>(4096, (h_total + 255) / 256);
+  for (int level = 0; level <= kmax; level += 2)
+    hipLaunchKernelGGL(subset_haf_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, level);
   if (a.n_classes > 0) {
     const int64_t g = a.n_classes < 65536 ? a.n_classes : 65536;
     hipLaunchKernelGGL(marg_class_kernel, dim3((unsigned)g), dim3(64), 0, s, a);
   }
-  if (a.batch > 0) {
-    const int64_t g = a.batch < 65536 ? a.batch : 65536;
-    hipLaunchKernelGGL(marg_sum_kernel, dim3((unsigned)g), dim3(64), 0, s, a);
-  }
+  const int64_t g = a.batch < 65536 ? a.batch : 65536;
+  hipLaunchKernelGGL(marg_sum_kernel, dim3((unsigned)g), dim3(64), 0, s, a);
 }
 
 int upload_tables(const ConstTables& t) {

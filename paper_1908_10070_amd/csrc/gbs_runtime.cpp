@@ -771,6 +771,10 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
       if (out_idx_host[b] < 0) return fail(ctx, GBS_EINVAL, "negative output index");
     pl.out_idx.assign(out_idx_host, out_idx_host + batch);
   }
+  {
+    DeviceGuard dg(ctx->device);
+    if (hipStreamWaitEvent(stream, st->ready, 0) != hipSuccess) return fail(ctx, GBS_EHIP, "state not ready");
+  }
   return run_plan(ctx, pl, modes_host, (size_t)total, st->B, st->m, st->pref, prob_out, haf_out, partial_out, stream);
 }
 
@@ -963,95 +967,102 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
   const Tables& T = tables();
   if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
 
-  // 1. hafnians of W over every even-size subset of every prefix, scattered to h[h_off[p] + mask]
-  Plan pl;
-  ItemLists lists;
-  std::vector<int32_t> pmodes;
-  std::vector<int64_t> h_off(batch + 1, 0);
-  pl.part_off.push_back(0);
-  for (int64_t b = 0; b < batch; ++b) {
-    const int k = (int)(offsets_host[b + 1] - offsets_host[b]);
-    const int32_t* x = modes_host + offsets_host[b];
-    for (uint32_t mask = 0; mask < (1u << k); ++mask) {
-      const int c = __builtin_popcount(mask);
-      if (c & 1) continue;
-      const int64_t src = (int64_t)pmodes.size();
-      for (uint32_t r = mask; r; r &= r - 1u) pmodes.push_back(x[__builtin_ctz(r)]);
-      const int pi = (int)pl.pats.size();
-      pl.pats.push_back(PatternDesc{src, c, 0});
-      pl.nvec.push_back(c);
-      pl.sfact.push_back(1.0);
-      pl.out_idx.push_back(h_off[b] + mask);
-      plan_range(ctx, T.host, pl, lists, pi, c, 0, subset_count(c));
-      pl.part_off.push_back(pl.n_partials);
-    }
-    h_off[b + 1] = h_off[b] + ((int64_t)1 << k);
-  }
-  order_items(pl, lists);
-
-  // 2. classes of position sets A (|A| = k mod 2) with equal mode multisets; Per(S_{A,B}) = prod c_t!
-  std::vector<int32_t> k_vec(batch), cls_prefix;
-  std::vector<int64_t> cls_mem{0}, pre_cls{0}, F_off(batch);
+  // per-prefix tables: hafnian table offsets, weights F, classes (explicit ones only where modes
+  // repeat; a collision-free prefix's 2^(k-1) classes are implicit)
+  const int jdim = kmax / 2 + 1;
+  std::vector<int64_t> h_off(batch + 1, 0), pre_cls(batch + 1, 0), ex_base(batch, -1), F_off(batch);
+  std::vector<int32_t> k_vec(batch);
+  std::vector<int64_t> cls_mem{0};
   std::vector<double> cls_w, Ftab;
   std::vector<uint32_t> mem;
-  const int jdim = kmax / 2 + 1;
+  std::map<int, int64_t> F_of_k;  // one weight table per distinct prefix length
   for (int64_t b = 0; b < batch; ++b) {
     const int k = (int)(offsets_host[b + 1] - offsets_host[b]);
     const int32_t* x = modes_host + offsets_host[b];
     k_vec[b] = k;
+    h_off[b + 1] = h_off[b] + ((int64_t)1 << k);
+    // distinct modes with their multiplicities; code[i] = index of x[i]'s mode
     std::vector<int> code(k);
     std::vector<int32_t> distinct;
+    std::vector<int> mult;
     for (int i = 0; i < k; ++i) {
       auto it = std::find(distinct.begin(), distinct.end(), x[i]);
       code[i] = (int)(it - distinct.begin());
-      if (it == distinct.end()) distinct.push_back(x[i]);
-    }
-    const bool collision_free = (int)distinct.size() == k;
-    std::map<std::vector<uint8_t>, int64_t> index;
-    std::vector<std::vector<uint32_t>> members;
-    std::vector<double> weights;
-    for (uint32_t A = 0; A < (1u << k); ++A) {
-      if ((__builtin_popcount(A) ^ k) & 1) continue;
-      if (collision_free) {
-        members.push_back({A});
-        weights.push_back(1.0);
-        continue;
+      if (it == distinct.end()) {
+        distinct.push_back(x[i]);
+        mult.push_back(0);
       }
-      std::vector<uint8_t> cnt(distinct.size(), 0);
-      for (uint32_t r = A; r; r &= r - 1u) ++cnt[code[__builtin_ctz(r)]];
-      auto it = index.find(cnt);
-      if (it == index.end()) {
+      ++mult[code[i]];
+    }
+    if ((int)distinct.size() == k) {
+      pre_cls[b + 1] = pre_cls[b] + (k == 0 ? 1 : ((int64_t)1 << (k - 1)));
+    } else {
+      // A with |A| = k mod 2 grouped by its mode counts, encoded in mixed radix (radix mult + 1 per
+      // mode, at most 2^k keys); classes in order of their smallest member, members ascending
+      std::vector<int64_t> place(distinct.size());
+      int64_t nkeys = 1;
+      for (size_t t = 0; t < distinct.size(); ++t) {
+        place[t] = nkeys;
+        nkeys *= mult[t] + 1;
+      }
+      std::vector<int64_t> bit_key(k);
+      for (int i = 0; i < k; ++i) bit_key[i] = place[code[i]];
+      std::vector<int64_t> cls_of_key(nkeys, -1), count;
+      std::vector<uint32_t> keyed;  // (A in ascending order, its class)
+      std::vector<int64_t> key_cls;
+      for (uint32_t A = 0; A < (1u << k); ++A) {
+        if ((__builtin_popcount(A) ^ k) & 1) continue;
+        int64_t key = 0;
+        for (uint32_t r = A; r; r &= r - 1u) key += bit_key[__builtin_ctz(r)];
+        if (cls_of_key[key] < 0) {
+          cls_of_key[key] = (int64_t)count.size();
+          count.push_back(0);
+        }
+        ++count[cls_of_key[key]];
+        keyed.push_back(A);
+        key_cls.push_back(cls_of_key[key]);
+      }
+      const int64_t nc = (int64_t)count.size();
+      const int64_t base_mem = (int64_t)mem.size();
+      std::vector<int64_t> start(nc + 1, 0);
+      for (int64_t c = 0; c < nc; ++c) start[c + 1] = start[c] + count[c];
+      mem.resize(base_mem + (int64_t)keyed.size());
+      std::vector<int64_t> fill(start.begin(), start.end() - 1);
+      for (size_t q = 0; q < keyed.size(); ++q) mem[base_mem + fill[key_cls[q]]++] = keyed[q];
+      ex_base[b] = (int64_t)cls_w.size();
+      for (int64_t c = 0; c < nc; ++c) {
+        cls_mem.push_back(base_mem + start[c + 1]);
+        // Per(S_{A,B}) = prod over modes of (count of that mode in A)!
+        const uint32_t A = mem[base_mem + start[c]];
+        std::vector<int> cnt(distinct.size(), 0);
+        for (uint32_t r = A; r; r &= r - 1u) ++cnt[code[__builtin_ctz(r)]];
         double w = 1.0;
-        for (uint8_t c : cnt)
-          for (int f = 2; f <= c; ++f) w *= f;
-        index.emplace(cnt, (int64_t)members.size());
-        members.push_back({A});
-        weights.push_back(w);
-      } else {
-        members[it->second].push_back(A);
+        for (int cv : cnt)
+          for (int f = 2; f <= cv; ++f) w *= f;
+        cls_w.push_back(w);
       }
+      pre_cls[b + 1] = pre_cls[b] + nc;
     }
-    for (size_t c = 0; c < members.size(); ++c) {
-      cls_prefix.push_back((int32_t)b);
-      mem.insert(mem.end(), members[c].begin(), members[c].end());
-      cls_mem.push_back((int64_t)mem.size());
-      cls_w.push_back(weights[c]);
+    auto fk = F_of_k.find(k);
+    if (fk == F_of_k.end()) {
+      fk = F_of_k.emplace(k, (int64_t)Ftab.size()).first;
+      for (int mu = 0; mu <= k; ++mu)
+        for (int j1 = 0; j1 < jdim; ++j1)
+          for (int j2 = 0; j2 < jdim; ++j2) Ftab.push_back(theorem1_weight(m, n, k, mu, j1, j2));
     }
-    pre_cls.push_back((int64_t)cls_prefix.size());
-    F_off[b] = (int64_t)Ftab.size();
-    for (int mu = 0; mu <= k; ++mu)
-      for (int j1 = 0; j1 < jdim; ++j1)
-        for (int j2 = 0; j2 < jdim; ++j2) Ftab.push_back(theorem1_weight(m, n, k, mu, j1, j2));
+    F_off[b] = fk->second;
   }
-  const int64_t ncls = (int64_t)cls_prefix.size();
+  const int64_t ncls = pre_cls[batch];
+  const int64_t nx = offsets_host[batch];
 
-  // 3. device layout: the hafnian plan, then h, then the staged class data, then the class values
+  // device layout in the workspace: staged tables, then the hafnian tables, class values, extra
   DeviceGuard dg(ctx->device);
-  const Layout L = layout_for(pl, pmodes.size());
-  size_t off = al(L.total);
-  const size_t o_h = off;
-  off += al(sizeof(double2) * (size_t)h_off[batch]);
+  size_t off = 0;
   const size_t o_stage = off;
+  const size_t o_x = off;
+  off += al(sizeof(int32_t) * (size_t)std::max<int64_t>(nx, 1));
+  const size_t o_xoff = off;
+  off += al(sizeof(int64_t) * (batch + 1));
   const size_t o_hoff = off;
   off += al(sizeof(int64_t) * h_off.size());
   const size_t o_k = off;
@@ -1060,28 +1071,28 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
   off += al(sizeof(double) * Ftab.size());
   const size_t o_Foff = off;
   off += al(sizeof(int64_t) * F_off.size());
-  const size_t o_cp = off;
-  off += al(sizeof(int32_t) * cls_prefix.size());
+  const size_t o_pre = off;
+  off += al(sizeof(int64_t) * pre_cls.size());
+  const size_t o_exb = off;
+  off += al(sizeof(int64_t) * ex_base.size());
   const size_t o_cm = off;
   off += al(sizeof(int64_t) * cls_mem.size());
   const size_t o_cw = off;
-  off += al(sizeof(double) * cls_w.size());
+  off += al(sizeof(double) * std::max<size_t>(cls_w.size(), 1));
   const size_t o_mem = off;
-  off += al(sizeof(uint32_t) * mem.size());
-  const size_t o_pre = off;
-  off += al(sizeof(int64_t) * pre_cls.size());
+  off += al(sizeof(uint32_t) * std::max<size_t>(mem.size(), 1));
   const size_t stage_bytes = off - o_stage;
+  const size_t o_h = off;
+  off += al(sizeof(double2) * (size_t)h_off[batch]);
   const size_t o_v = off;
   off += al(sizeof(double) * (size_t)std::max<int64_t>(ncls, 1));
   const size_t o_extra = off;
   off += al(extra);
   int rc = ensure_ws(ctx, off);
   if (rc) return rc;
-  if (extra_dev) *extra_dev = static_cast<unsigned char*>(ctx->ws) + o_extra;
-  if (!q_out_dev) q_out_dev = reinterpret_cast<double*>(static_cast<unsigned char*>(ctx->ws) + o_extra);
-  rc = run_plan(ctx, pl, pmodes.data(), pmodes.size(), st->W, m, st->pref, nullptr,
-                reinterpret_cast<double2*>(static_cast<unsigned char*>(ctx->ws) + o_h), nullptr, s);
-  if (rc) return rc;
+  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  if (extra_dev) *extra_dev = ws + o_extra;
+  if (!q_out_dev) q_out_dev = reinterpret_cast<double*>(ws + o_extra);
 
   const int pi = ctx->pin_idx;
   ctx->pin_idx ^= 1;
@@ -1092,37 +1103,44 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
   auto put = [&](size_t o, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hp + (o - o_stage), src, bytes);
   };
+  put(o_x, modes_host, sizeof(int32_t) * (size_t)nx);
+  put(o_xoff, offsets_host, sizeof(int64_t) * (batch + 1));
   put(o_hoff, h_off.data(), sizeof(int64_t) * h_off.size());
   put(o_k, k_vec.data(), sizeof(int32_t) * k_vec.size());
   put(o_F, Ftab.data(), sizeof(double) * Ftab.size());
   put(o_Foff, F_off.data(), sizeof(int64_t) * F_off.size());
-  put(o_cp, cls_prefix.data(), sizeof(int32_t) * cls_prefix.size());
+  put(o_pre, pre_cls.data(), sizeof(int64_t) * pre_cls.size());
+  put(o_exb, ex_base.data(), sizeof(int64_t) * ex_base.size());
   put(o_cm, cls_mem.data(), sizeof(int64_t) * cls_mem.size());
   put(o_cw, cls_w.data(), sizeof(double) * cls_w.size());
   put(o_mem, mem.data(), sizeof(uint32_t) * mem.size());
-  put(o_pre, pre_cls.data(), sizeof(int64_t) * pre_cls.size());
-  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->done_ev, 0));
+  if (hipStreamWaitEvent(s, st->ready, 0) != hipSuccess) return fail(ctx, GBS_EHIP, "state not ready");
   HIPCHK(ctx, hipMemcpyAsync(ws + o_stage, hp, stage_bytes, hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], s));
   ctx->pinned_used[pi] = true;
 
   MargArgs ma{};
-  ma.h = reinterpret_cast<const double2*>(ws + o_h);
+  ma.W = st->W;
+  ma.m = m;
+  ma.x = reinterpret_cast<const int32_t*>(ws + o_x);
+  ma.x_off = reinterpret_cast<const int64_t*>(ws + o_xoff);
+  ma.h = reinterpret_cast<double2*>(ws + o_h);
   ma.h_off = reinterpret_cast<const int64_t*>(ws + o_hoff);
   ma.k = reinterpret_cast<const int32_t*>(ws + o_k);
   ma.F = reinterpret_cast<const double*>(ws + o_F);
   ma.F_off = reinterpret_cast<const int64_t*>(ws + o_Foff);
-  ma.cls_prefix = reinterpret_cast<const int32_t*>(ws + o_cp);
+  ma.pre_cls = reinterpret_cast<const int64_t*>(ws + o_pre);
+  ma.ex_base = reinterpret_cast<const int64_t*>(ws + o_exb);
   ma.cls_mem = reinterpret_cast<const int64_t*>(ws + o_cm);
   ma.cls_w = reinterpret_cast<const double*>(ws + o_cw);
   ma.mem = reinterpret_cast<const uint32_t*>(ws + o_mem);
   ma.n_classes = ncls;
   ma.v = reinterpret_cast<double*>(ws + o_v);
-  ma.pre_cls = reinterpret_cast<const int64_t*>(ws + o_pre);
   ma.batch = batch;
   ma.jdim = jdim;
   ma.q_out = q_out_dev;
-  launch_marginal(ma, s);
+  launch_marginal(ma, kmax, h_off[batch], s);
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
   ctx->done_recorded = true;
