@@ -136,6 +136,25 @@ def extras(gbs, torch, dev, args):
                                  "mean_ms": float(lat_f.mean()), "throughput_req_s": fifo.stats()["throughput_req_s"]},
         }
     out["config4_serving"] = srv_out
+    # chain-rule sampler (Theorem-1 marginals) at the paper's mode count m = n^2, r = 0.88
+    from paper_1908_10070_amd import sampler
+    smp_out = {}
+    for n_ph, count in ((12, 8), (16, 2), (18, 1)):
+        m_s = n_ph * n_ph
+        U_s = inputs.haar_unitary(m_s, np.random.default_rng(4000 + n_ph))
+        st_s = ctx.state(torch.from_numpy(U_s).to(dev), np.full(m_s, 0.88))
+        smp = sampler.Sampler(ctx, st_s, m_s, 0.88)
+        srng = np.random.default_rng(5)
+        smp.positions(min(n_ph, 8), 1, srng)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.positions(n_ph, count, srng)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        smp_out[f"n{n_ph}_m{m_s}"] = {"seconds_per_sample": dt / count, "samples": count}
+    smp_out["context"] = ("paper (CPU, other hardware): 18 photons about 20 h on a laptop; 20 photons about "
+                          "36 h on a 256-core server")
+    out["sampler"] = smp_out
     return out
 
 
