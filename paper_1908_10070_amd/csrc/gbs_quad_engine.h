@@ -19,6 +19,10 @@ namespace {
 #define GBS_QUAD_MAX_S 6
 #endif
 constexpr int kQuadMaxS = GBS_QUAD_MAX_S;
+// up to this k the quad engine multiplies with three real products per step (see cmul_mat)
+#ifndef GBS_QUAD_GAUSS_KMAX
+#define GBS_QUAD_GAUSS_KMAX kMaxK
+#endif
 // up to this k the quad kernels fit two waves per SIMD without spilling
 #ifndef GBS_QUAD_WAVES2_KMAX
 #define GBS_QUAD_WAVES2_KMAX 12
@@ -34,16 +38,36 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int T4>
+// Z = X Y; three real products per step (see cmul_mat) when G.
+template <int T4, bool G>
 __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<T4>& Z) {
-  QMat<T4> acc;
+  if constexpr (G) {
+    double t1[T4][T4], t2[T4][T4], t3[T4][T4];
 #pragma unroll
-  for (int I = 0; I < T4; ++I)
+    for (int K = 0; K < T4; ++K) {
 #pragma unroll
-    for (int J = 0; J < T4; ++J) {
-      acc.r[I][J] = 0.0;
-      acc.i[I][J] = 0.0;
+      for (int I = 0; I < T4; ++I) {
+        const double ar = swap17(X.r[K][I]);
+        const double ai = swap17(X.i[K][I]);
+        const double as = ar + ai;
+#pragma unroll
+        for (int J = 0; J < T4; ++J) {
+          t1[I][J] = mfma4(ar, Y.r[K][J], K == 0 ? 0.0 : t1[I][J]);
+          t2[I][J] = mfma4(ai, Y.i[K][J], K == 0 ? 0.0 : t2[I][J]);
+          t3[I][J] = mfma4(as, Y.r[K][J] + Y.i[K][J], K == 0 ? 0.0 : t3[I][J]);
+        }
+      }
     }
+#pragma unroll
+    for (int I = 0; I < T4; ++I)
+#pragma unroll
+      for (int J = 0; J < T4; ++J) {
+        Z.r[I][J] = t1[I][J] - t2[I][J];
+        Z.i[I][J] = t3[I][J] - t1[I][J] - t2[I][J];
+      }
+    return;
+  }
+  QMat<T4> acc;
 #pragma unroll
   for (int K = 0; K < T4; ++K)
 #pragma unroll
@@ -52,8 +76,8 @@ __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<
       const double ai = swap17(X.i[K][I]);
 #pragma unroll
       for (int J = 0; J < T4; ++J) {
-        acc.r[I][J] = mfma4(ar, Y.r[K][J], acc.r[I][J]);
-        acc.i[I][J] = mfma4(ar, Y.i[K][J], acc.i[I][J]);
+        acc.r[I][J] = mfma4(ar, Y.r[K][J], K == 0 ? 0.0 : acc.r[I][J]);
+        acc.i[I][J] = mfma4(ar, Y.i[K][J], K == 0 ? 0.0 : acc.i[I][J]);
         acc.r[I][J] = mfma4(-ai, Y.i[K][J], acc.r[I][J]);
         acc.i[I][J] = mfma4(ai, Y.r[K][J], acc.i[I][J]);
       }
@@ -96,7 +120,7 @@ __device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], 
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      qmul<T4>(S[op.a], S[op.b], S[op.x]);
+      qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x]);
     } else if constexpr (op.type == OP_TDIAG) {
       const double2 p = qdiag<T4>(S[op.a], lane);
       w[op.x - 1] = fold32(p.x, p.y);

@@ -161,6 +161,205 @@ __device__ __forceinline__ void eval_strip(const PatternView& P, const int32_t* 
   reduce_folded<K>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
 }
 
+// Five tile rows (16 < d <= 20) without the padded second register per row: main register I
+// holds tiles (I, 0..3) in blocks 0..3 as above; side register g holds column tile 4 of rows
+// 4g + b in block b (side register 1 has only row 4, its blocks 1..3 stay zero). For Z = X Y:
+//  * A operands use the pair symmetry: X's tile (I, K) by rows is X's tile (K, I) read at
+//    (x^1, y^1), broadcast from the block that holds it (main register K for I < 4, side register
+//    K / 4 for I = 4) -- one ds_swizzle per 32-bit half, within each 32-lane half of the wave;
+//  * side outputs, rows 0..3: block b needs X's tile (b, K) by rows, which is main register K read
+//    at lane l ^ 17 (no broadcast); B is Y's tile (K, 4), broadcast from its side register; row 4
+//    as for the main outputs, masked to block 0.
+// 105 instead of 150 MFMAs per product and 7 instead of 10 registers per component.
+struct S5Mat {
+  double mr[5], mi[5];  // main registers, rows 0..4
+  double sr[2], si[2];  // side registers
+};
+
+// Lane exchanges within each 32-lane half by ds_swizzle (bit mode: source lane bits 0..4 are
+// ((lane & AND) | OR) ^ XOR), no address registers. swz_tr(c, v): the tile in block c read at
+// (x^1, y^1) -- by the pair symmetry of powers, the transposed neighbour tile in A order;
+// swz_bc(c, v): the tile in block c as stored (B order).
+template <int AND, int OR, int XOR>
+__device__ __forceinline__ double swz(double v) {
+  constexpr int pat = AND | (OR << 5) | (XOR << 10);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)b, pat);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), pat);
+  return join((unsigned)lo, (unsigned)hi);
+}
+// c is a constant after unrolling; the switch folds to one exchange
+__device__ __forceinline__ double swz_tr(int c, double v) {
+  switch (c & 3) {
+    case 0: return swz<0x13, 0 << 2, 0x11>(v);
+    case 1: return swz<0x13, 1 << 2, 0x11>(v);
+    case 2: return swz<0x13, 2 << 2, 0x11>(v);
+    default: return swz<0x13, 3 << 2, 0x11>(v);
+  }
+}
+__device__ __forceinline__ double swz_bc(int c, double v) {
+  switch (c & 3) {
+    case 0: return swz<0x13, 0 << 2, 0>(v);
+    case 1: return swz<0x13, 1 << 2, 0>(v);
+    case 2: return swz<0x13, 2 << 2, 0>(v);
+    default: return swz<0x13, 3 << 2, 0>(v);
+  }
+}
+
+__device__ __forceinline__ void strip5_mul(const S5Mat& X, const S5Mat& Y, S5Mat& Z, const int (&addr)[4],
+                                           const int (&baddr)[4], bool block0) {
+  (void)addr;
+  (void)baddr;
+  S5Mat acc;
+#pragma unroll
+  for (int I = 0; I < 5; ++I) {
+    double t1, t2, t3;
+#pragma unroll
+    for (int K = 0; K < 5; ++K) {
+      // X's tile (I, K) by rows = X's tile (K, I) read at (x^1, y^1), broadcast from its block
+      double ar, ai;
+      if (I < 4) {
+        ar = swz_tr(I, X.mr[K]);
+        ai = swz_tr(I, X.mi[K]);
+      } else {
+        ar = swz_tr(K, X.sr[K >> 2]);
+        ai = swz_tr(K, X.si[K >> 2]);
+      }
+      t1 = mfma4(ar, Y.mr[K], K == 0 ? 0.0 : t1);
+      t2 = mfma4(ai, Y.mi[K], K == 0 ? 0.0 : t2);
+      t3 = mfma4(ar + ai, Y.mr[K] + Y.mi[K], K == 0 ? 0.0 : t3);
+    }
+    acc.mr[I] = t1 - t2;
+    acc.mi[I] = t3 - t1 - t2;
+  }
+  double u1[2], u2[2], u3[2];
+#pragma unroll
+  for (int K = 0; K < 5; ++K) {
+    const double br = swz_bc(K, Y.sr[K >> 2]);
+    const double bi = swz_bc(K, Y.si[K >> 2]);
+    const double bs = br + bi;
+    // rows 0..3
+    {
+      const double ar = swz<0x1f, 0, 0x11>(X.mr[K]);
+      const double ai = swz<0x1f, 0, 0x11>(X.mi[K]);
+      u1[0] = mfma4(ar, br, K == 0 ? 0.0 : u1[0]);
+      u2[0] = mfma4(ai, bi, K == 0 ? 0.0 : u2[0]);
+      u3[0] = mfma4(ar + ai, bs, K == 0 ? 0.0 : u3[0]);
+    }
+    // row 4 (block 0 only): X's tile (4, K) by rows = X's tile (K, 4), in side register K / 4
+    {
+      double ar = swz_tr(K, X.sr[K >> 2]);
+      double ai = swz_tr(K, X.si[K >> 2]);
+      ar = block0 ? ar : 0.0;
+      ai = block0 ? ai : 0.0;
+      u1[1] = mfma4(ar, br, K == 0 ? 0.0 : u1[1]);
+      u2[1] = mfma4(ai, bi, K == 0 ? 0.0 : u2[1]);
+      u3[1] = mfma4(ar + ai, bs, K == 0 ? 0.0 : u3[1]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    acc.sr[g] = u1[g] - u2[g];
+    acc.si[g] = u3[g] - u1[g] - u2[g];
+  }
+  Z = acc;
+}
+
+__device__ __forceinline__ double2 strip5_diag(const S5Mat& X, int lane) {
+  double2 t = make_double2(0.0, 0.0);
+  if ((lane & 3) == (lane >> 4)) {
+    const int b = (lane >> 2) & 3;
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+      if (b == I) {
+        t.x += X.mr[I];
+        t.y += X.mi[I];
+      }
+    if (b == 0) {  // tile (4, 4)
+      t.x += X.sr[1];
+      t.y += X.si[1];
+    }
+  }
+  return t;
+}
+
+__device__ __forceinline__ double2 strip5_pair(const S5Mat& X, const S5Mat& Y) {
+  double2 t = make_double2(0.0, 0.0);
+  auto acc = [&](double xr, double xi, double yr0, double yi0) {
+    const double yr = swap17(yr0), yi = swap17(yi0);
+    t.x = fma(xr, yr, t.x);
+    t.x = fma(-xi, yi, t.x);
+    t.y = fma(xr, yi, t.y);
+    t.y = fma(xi, yr, t.y);
+  };
+#pragma unroll
+  for (int I = 0; I < 5; ++I) acc(X.mr[I], X.mi[I], Y.mr[I], Y.mi[I]);
+#pragma unroll
+  for (int g = 0; g < 2; ++g) acc(X.sr[g], X.si[g], Y.sr[g], Y.si[g]);
+  return t;
+}
+
+template <int K, int OI, int NS>
+__device__ __forceinline__ void run_ops_strip5(S5Mat (&S)[NS], double* park, const int (&addr)[4],
+                                               const int (&baddr)[4], bool block0, int lane) {
+  if constexpr (OI < kChainTable[K].nops) {
+    constexpr Op op = kChainTable[K].ops[OI];
+    if constexpr (op.type == OP_MUL) {
+      if constexpr (op.x == op.b && op.a != op.b)
+        strip5_mul(S[op.b], S[op.a], S[op.x], addr, baddr, block0);  // powers commute
+      else
+        strip5_mul(S[op.a], S[op.b], S[op.x], addr, baddr, block0);
+    } else if constexpr (op.type == OP_TDIAG) {
+      const double2 p = strip5_diag(S[op.a], lane);
+      park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
+    } else {
+      const double2 p = strip5_pair(S[op.a], S[op.b]);
+      park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
+    }
+    run_ops_strip5<K, OI + 1, NS>(S, park, addr, baddr, block0, lane);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void eval_strip5(const PatternView& P, const int32_t* pl, int d, double* trw, int u,
+                                            double* park, int lane) {
+  constexpr int NS = kChainTable[K].nslots;
+  const int x = lane & 3, b = (lane >> 2) & 3, y = lane >> 4;
+  int addr[4], baddr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    addr[c] = (y + 4 * c + 16 * x) * 4;   // tile in block c, transposed (A order)
+    baddr[c] = (x + 4 * c + 16 * y) * 4;  // tile in block c, as stored (B order)
+  }
+  auto at = [&](int a, int c) -> double2 {
+    if (a < d && c < d) {
+      const int bb = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
+      return P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
+    }
+    return make_double2(0.0, 0.0);
+  };
+  {
+    S5Mat S[NS];
+#pragma unroll
+    for (int I = 0; I < 5; ++I) {
+      const double2 e = at(4 * I + y, 4 * b + x);
+      S[0].mr[I] = e.x;
+      S[0].mi[I] = e.y;
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const double2 e = at(4 * (4 * g + b) + y, 16 + x);
+      S[0].sr[g] = e.x;
+      S[0].si[g] = e.y;
+    }
+    run_ops_strip5<K, 0, NS>(S, park, addr, baddr, b == 0, lane);
+  }
+  double w[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) w[j] = park[j * 64 + lane];  // each lane reads only what it wrote
+  reduce_folded<K>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
+}
+
 // The subsets [lo, hi) of one pattern on one wave; each subset uses the tile-row count TL or TH.
 template <int K, int TL, int TH>
 __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double* trw, int32_t* sz,
@@ -175,7 +374,9 @@ __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_
       if (lane < K && ((mask >> lane) & 1u)) pl[__popc(mask & ((1u << lane) - 1u))] = lane;
       if (lane == 0) sz[u] = s;
       wave_sync();
-      if (2 * s <= 4 * TL)
+      if constexpr (TL == 5 && TH == 5)
+        eval_strip5<K>(P, pl, 2 * s, trw, u, park, lane);
+      else if (2 * s <= 4 * TL)
         eval_strip<K, TL>(P, pl, 2 * s, trw, u, park, lane);
       else
         eval_strip<K, TH>(P, pl, 2 * s, trw, u, park, lane);
