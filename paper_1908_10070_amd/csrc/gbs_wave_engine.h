@@ -42,7 +42,15 @@ struct CMat {
   d4 i[T][T];
 };
 
-__device__ __forceinline__ double swap17(double v) { return __shfl_xor(v, 17, 64); }
+// lane l ^ 17 (x ^ 1, y ^ 1 within a tile): ds_swizzle in bit mode (xor 0x11 inside each 32-lane
+// half), no address register
+__device__ __forceinline__ double swap17(double v) {
+  constexpr int pat = 0x1f | (0 << 5) | (0x11 << 10);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)b, pat);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), pat);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
