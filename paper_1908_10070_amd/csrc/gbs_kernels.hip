@@ -175,13 +175,28 @@ __global__ void subset_haf_kernel(MargArgs a, int level) {
   }
 }
 
-// One wave per class. For each member A (in order) and each j, the 2j-subsets a of C = [k] minus A
-// are split into contiguous colex-rank ranges, one per lane: a lane unranks its first combination of
-// the |C| positions once and steps with Gosper's construction; positions map to prefix bits through
-// C's bit list. Lane sums are combined by a fixed butterfly, so the result does not depend on timing.
+// Deposit the low bits of t onto the set bits of mask, lowest first (bits of t beyond popc(mask)
+// are ignored).
+__device__ __forceinline__ uint32_t deposit(uint32_t t, uint32_t mask) {
+  uint32_t out = 0;
+  for (uint32_t m = mask; m && t; m &= m - 1u, t >>= 1)
+    if (t & 1u) out |= m & (0u - m);
+  return out;
+}
+
+constexpr int kMargLow = 7;                  // positions of C spread over the lanes
+constexpr int kMargHigh = kMaxK - kMargLow;  // at most this many walked in the uniform loop
+
+// One wave per class. For each member A (in order) and C = [k] minus A, the even subsets a of C are
+// split as a = low | high: low ranges over the subsets of C's lowest kMargLow positions -- lane l
+// owns the l-th one of even and the l-th one of odd size, so every lane works on every step -- and
+// high walks all subsets of C's other positions in increasing order, the same for every lane (the
+// wave reads neighbouring table entries). The parity of high picks the lane's even or odd low
+// subset so that |a| is even; partial sums are kept per size of high (a uniform index) and moved to
+// j = |a| / 2 at the end. Lane sums are combined in a fixed order, so results do not depend on timing.
 __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
-  __shared__ int32_t bitpos[32];
-  __shared__ double2 H[kMaxK + 1];
+  __shared__ double2 acc[(kMaxK / 2 + 1) * 64];
+  __shared__ double2 H[kMaxK / 2 + 1];
   const int lane = threadIdx.x;
   for (int64_t c = blockIdx.x; c < a.n_classes; c += gridDim.x) {
     const int64_t p = owner(a.pre_cls, a.batch, c);
@@ -204,61 +219,77 @@ __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
     const uint32_t A0 = eb < 0 ? A_impl : a.mem[m_lo];
     const int mu = __popc(A0);
     const int cs = k - mu;  // |C|, even by construction
-    if (lane <= cs / 2) H[lane] = make_double2(0.0, 0.0);
-    __syncthreads();
+    const int J = cs / 2 + 1;
+    if (lane < J) H[lane] = make_double2(0.0, 0.0);
     for (int64_t q = m_lo; q < m_hi; ++q) {
       const uint32_t C = full & ~(eb < 0 ? A_impl : a.mem[q]);
-      if (lane == 0) {
-        int t = 0;
-        for (uint32_t r = C; r; r &= r - 1u) bitpos[t++] = __builtin_ctz(r);
+      for (int j = 0; j < J; ++j) acc[j * 64 + lane] = make_double2(0.0, 0.0);
+      // low part: C's lowest nl positions; lane's even- and odd-size low subsets
+      const int nl = cs < kMargLow ? cs : kMargLow;
+      uint32_t L = 0;
+      {
+        uint32_t r = C;
+        for (int t = 0; t < nl; ++t, r &= r - 1u) L |= r & (0u - r);
+      }
+      const uint32_t Hh = C & ~L;
+      const int half = nl > 0 ? 1 << (nl - 1) : 1;  // number of even (and of odd) low subsets
+      const uint32_t te = ((uint32_t)lane << 1) | ((uint32_t)__popc((uint32_t)lane) & 1u);
+      const uint32_t to = ((uint32_t)lane << 1) | ((~(uint32_t)__popc((uint32_t)lane)) & 1u);
+      const bool ae = lane < half, ao = nl > 0 && lane < half;
+      const uint32_t le = ae ? deposit(te, L) : 0u, lo = ao ? deposit(to, L) : 0u;
+      const int pe = __popc(le), po = __popc(lo);
+      double sr[kMargHigh + 1], si[kMargHigh + 1];
+#pragma unroll
+      for (int t = 0; t <= kMargHigh; ++t) sr[t] = si[t] = 0.0;
+      uint32_t hm = 0;
+      do {
+        const int ph = __popc(hm);  // uniform
+        const bool even = (ph & 1) == 0;
+        if (even ? ae : ao) {
+          const uint32_t sub = (even ? le : lo) | hm;
+          const double2 x = h[sub], y = h[C ^ sub];
+          const double pr = fma(x.x, y.x, -x.y * y.y), pi = fma(x.x, y.y, x.y * y.x);
+          switch (ph) {  // uniform index into registers
+#define GBS_MARG_ACC(T) \
+            case T:                \
+              sr[T] += pr;         \
+              si[T] += pi;         \
+              break;
+            GBS_MARG_ACC(0) GBS_MARG_ACC(1) GBS_MARG_ACC(2) GBS_MARG_ACC(3) GBS_MARG_ACC(4) GBS_MARG_ACC(5)
+            GBS_MARG_ACC(6) GBS_MARG_ACC(7) GBS_MARG_ACC(8) GBS_MARG_ACC(9) GBS_MARG_ACC(10) GBS_MARG_ACC(11)
+            GBS_MARG_ACC(12) GBS_MARG_ACC(13) GBS_MARG_ACC(14) GBS_MARG_ACC(15) GBS_MARG_ACC(16)
+#undef GBS_MARG_ACC
+            default: break;
+          }
+        }
+        hm = (hm - Hh) & Hh;  // next subset of Hh in increasing order
+      } while (hm != 0);
+      // |a| = |low| + |high|: move each partial to j = |a| / 2 (one lane writes only its own slots)
+#pragma unroll
+      for (int t = 0; t <= kMargHigh; ++t) {
+        if (t <= cs - nl) {
+          const int pl = (t & 1) ? po : pe;
+          const int j = (pl + t) >> 1;
+          if ((t & 1) ? ao : ae) acc[j * 64 + lane] = make_double2(acc[j * 64 + lane].x + sr[t], acc[j * 64 + lane].y + si[t]);
+        }
       }
       __syncthreads();
-      for (int j = 0; 2 * j <= cs; ++j) {
-        const int r = 2 * j;
-        const int64_t total = c_tab.binom[cs][r];
-        const int64_t per = (total + 63) / 64;
-        const int64_t lo = per * lane, hi = lo + per < total ? lo + per : total;
-        double sr = 0.0, si = 0.0;
-        if (lo < hi) {
-          // unrank combination lo (colex) of r positions among cs
-          uint32_t comb = 0;
-          int64_t rem = lo;
-          int top = cs - 1;
-          for (int i = r; i >= 1; --i) {
-            while (c_tab.binom[top][i] > rem) --top;
-            comb |= 1u << top;
-            rem -= c_tab.binom[top][i];
-            --top;
-          }
-          for (int64_t g = lo; g < hi; ++g) {
-            uint32_t sub = 0;
-            for (uint32_t t = comb; t; t &= t - 1u) sub |= 1u << bitpos[__builtin_ctz(t)];
-            const double2 x = h[sub], y = h[C ^ sub];
-            sr = fma(x.x, y.x, sr);
-            sr = fma(-x.y, y.y, sr);
-            si = fma(x.x, y.y, si);
-            si = fma(x.y, y.x, si);
-            if (comb) {  // Gosper: next larger mask with the same popcount
-              const uint32_t low = comb & (0u - comb);
-              const uint32_t ripple = comb + low;
-              comb = (((ripple ^ comb) >> 2) >> __builtin_ctz(comb)) | ripple;
-            }
-          }
+      // fixed-order sum over lanes for each j (lane j adds column j; J <= 12 lanes busy)
+      if (lane < J) {
+        double xr = 0.0, xi = 0.0;
+        for (int l = 0; l < 64; ++l) {
+          xr += acc[lane * 64 + l].x;
+          xi += acc[lane * 64 + l].y;
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          sr += __shfl_xor(sr, off, 64);
-          si += __shfl_xor(si, off, 64);
-        }
-        if (lane == 0) H[j] = make_double2(H[j].x + sr, H[j].y + si);
+        H[lane] = make_double2(H[lane].x + xr, H[lane].y + xi);
       }
-      __syncthreads();  // bitpos reused by the next member
+      __syncthreads();
     }
     if (lane == 0) {
       const double* F = a.F + a.F_off[p] + (int64_t)mu * a.jdim * a.jdim;
       double v = 0.0;
-      for (int j1 = 0; 2 * j1 <= cs; ++j1)
-        for (int j2 = 0; 2 * j2 <= cs; ++j2) {
+      for (int j1 = 0; j1 < J; ++j1)
+        for (int j2 = 0; j2 < J; ++j2) {
           const double f = F[j1 * a.jdim + j2];
           if (f != 0.0) v = fma(f, H[j1].x * H[j2].x + H[j1].y * H[j2].y, v);  // Re H_j1 conj(H_j2)
         }

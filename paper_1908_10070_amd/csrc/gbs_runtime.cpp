@@ -976,6 +976,8 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
   std::vector<double> cls_w, Ftab;
   std::vector<uint32_t> mem;
   std::map<int, int64_t> F_of_k;  // one weight table per distinct prefix length
+  // explicit class lists depend only on which positions share a mode: one list per grouping
+  std::map<std::vector<int>, std::pair<int64_t, int64_t>> classes_of_grouping;  // -> (first class, count)
   for (int64_t b = 0; b < batch; ++b) {
     const int k = (int)(offsets_host[b + 1] - offsets_host[b]);
     const int32_t* x = modes_host + offsets_host[b];
@@ -994,54 +996,60 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
       }
       ++mult[code[i]];
     }
+    auto cached = (int)distinct.size() == k ? classes_of_grouping.end() : classes_of_grouping.find(code);
     if ((int)distinct.size() == k) {
       pre_cls[b + 1] = pre_cls[b] + (k == 0 ? 1 : ((int64_t)1 << (k - 1)));
+    } else if (cached != classes_of_grouping.end()) {
+      ex_base[b] = cached->second.first;
+      pre_cls[b + 1] = pre_cls[b] + cached->second.second;
     } else {
-      // A with |A| = k mod 2 grouped by its mode counts, encoded in mixed radix (radix mult + 1 per
-      // mode, at most 2^k keys); classes in order of their smallest member, members ascending
-      std::vector<int64_t> place(distinct.size());
-      int64_t nkeys = 1;
-      for (size_t t = 0; t < distinct.size(); ++t) {
-        place[t] = nkeys;
-        nkeys *= mult[t] + 1;
-      }
-      std::vector<int64_t> bit_key(k);
-      for (int i = 0; i < k; ++i) bit_key[i] = place[code[i]];
-      std::vector<int64_t> cls_of_key(nkeys, -1), count;
-      std::vector<uint32_t> keyed;  // (A in ascending order, its class)
-      std::vector<int64_t> key_cls;
-      for (uint32_t A = 0; A < (1u << k); ++A) {
-        if ((__builtin_popcount(A) ^ k) & 1) continue;
-        int64_t key = 0;
-        for (uint32_t r = A; r; r &= r - 1u) key += bit_key[__builtin_ctz(r)];
-        if (cls_of_key[key] < 0) {
-          cls_of_key[key] = (int64_t)count.size();
-          count.push_back(0);
+      // classes = count vectors (c_t <= multiplicity of mode t, sum = k mod 2); members = every
+      // choice of c_t of mode t's positions, for all t; Per(S_{A,B}) = prod c_t!
+      const int ng = (int)distinct.size();
+      std::vector<std::vector<std::vector<uint32_t>>> combos(ng);  // [t][c] -> position masks
+      for (int t = 0; t < ng; ++t) {
+        std::vector<int> pos;
+        for (int i = 0; i < k; ++i)
+          if (code[i] == t) pos.push_back(i);
+        combos[t].resize(pos.size() + 1);
+        for (uint32_t sm = 0; sm < (1u << pos.size()); ++sm) {
+          uint32_t mask = 0;
+          for (size_t q = 0; q < pos.size(); ++q)
+            if (sm >> q & 1u) mask |= 1u << pos[q];
+          combos[t][__builtin_popcount(sm)].push_back(mask);
         }
-        ++count[cls_of_key[key]];
-        keyed.push_back(A);
-        key_cls.push_back(cls_of_key[key]);
       }
-      const int64_t nc = (int64_t)count.size();
-      const int64_t base_mem = (int64_t)mem.size();
-      std::vector<int64_t> start(nc + 1, 0);
-      for (int64_t c = 0; c < nc; ++c) start[c + 1] = start[c] + count[c];
-      mem.resize(base_mem + (int64_t)keyed.size());
-      std::vector<int64_t> fill(start.begin(), start.end() - 1);
-      for (size_t q = 0; q < keyed.size(); ++q) mem[base_mem + fill[key_cls[q]]++] = keyed[q];
       ex_base[b] = (int64_t)cls_w.size();
-      for (int64_t c = 0; c < nc; ++c) {
-        cls_mem.push_back(base_mem + start[c + 1]);
-        // Per(S_{A,B}) = prod over modes of (count of that mode in A)!
-        const uint32_t A = mem[base_mem + start[c]];
-        std::vector<int> cnt(distinct.size(), 0);
-        for (uint32_t r = A; r; r &= r - 1u) ++cnt[code[__builtin_ctz(r)]];
+      int64_t nc = 0;
+      std::vector<int> cnt(ng, 0), idx(ng);
+      for (;;) {
+        int tot = 0;
         double w = 1.0;
-        for (int cv : cnt)
-          for (int f = 2; f <= cv; ++f) w *= f;
-        cls_w.push_back(w);
+        for (int t = 0; t < ng; ++t) {
+          tot += cnt[t];
+          for (int f = 2; f <= cnt[t]; ++f) w *= f;
+        }
+        if (((tot ^ k) & 1) == 0) {
+          // members: the product of the groups' combination lists, first group varying fastest
+          std::fill(idx.begin(), idx.end(), 0);
+          for (;;) {
+            uint32_t A = 0;
+            for (int t = 0; t < ng; ++t) A |= combos[t][cnt[t]][idx[t]];
+            mem.push_back(A);
+            int t = 0;
+            while (t < ng && ++idx[t] == (int)combos[t][cnt[t]].size()) idx[t++] = 0;
+            if (t == ng) break;
+          }
+          cls_mem.push_back((int64_t)mem.size());
+          cls_w.push_back(w);
+          ++nc;
+        }
+        int t = 0;
+        while (t < ng && ++cnt[t] > mult[t]) cnt[t++] = 0;
+        if (t == ng) break;
       }
       pre_cls[b + 1] = pre_cls[b] + nc;
+      classes_of_grouping.emplace(code, std::make_pair(ex_base[b], nc));
     }
     auto fk = F_of_k.find(k);
     if (fk == F_of_k.end()) {
