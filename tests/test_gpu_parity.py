@@ -247,3 +247,42 @@ def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
         print(f"config5 index {g['index']} n={g['n']} rel err vs {'long double' if 'haf_pt_ld' in g else 'double'} "
               f"oracle {err:.2e}")
         assert err < 1e-7
+
+
+def test_config3_full_size_sampled(ctx, torch_dev):
+    """Config 3 as the benchmark runs it (100,000 twenty-photon patterns, m = 50, one batched call):
+    40 outputs spread over the batch against the oracle, and properties of all of them."""
+    st_in, pats = inputs.config3()
+    st = ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    prob = ctx.prob_batch(st, pats).cpu().numpy()
+    assert prob.shape == (len(pats),) and np.all(np.isfinite(prob)) and np.all(prob > 0)
+    # distinct collision-free 20-photon patterns: their total cannot exceed P_20
+    assert prob.sum() <= oracle.photon_number_prob(50, 20, 0.88) * (1 + 1e-12)
+    B = oracle.state_B(st_in.U, st_in.r)
+    pref = float(np.prod(1.0 / np.cosh(st_in.r)))
+    for i in np.linspace(0, len(pats) - 1, 40).astype(int):
+        ref = abs(oracle.haf_enum(oracle.pattern_matrix(B, pats[i]))) ** 2 * pref
+        assert relerr(prob[i], ref) < TOL, (i, prob[i], ref)
+
+
+def test_largest_size_block_diagonal(ctx, torch_dev):
+    """n = 46 (the largest supported size): Haf of a block-diagonal matrix is the product of the
+    blocks' hafnians (no perfect matching crosses the blocks). The blocks are GBS pattern matrices
+    B_S of the config-5 state (m = 60, r = 0.88), sizes 24 and 22. Block-diagonal input is the worst
+    case for the subset sum's cancellation: every term mixing the blocks cancels exactly, so the sum of
+    term magnitudes exceeds |Haf| by ~1e10 here and the FP64 error is ~1e-6 (measured 9.5e-7). The bound
+    is the stated error level, 1e-5, not the 1e-9 of the smaller configurations."""
+    rng = np.random.default_rng(46)
+    st_in, _ = inputs.config5()
+    B = oracle.state_B(st_in.U, st_in.r)
+    modes = rng.permutation(60)
+    A1 = oracle.pattern_matrix(B, sorted(modes[:24]))
+    A2 = oracle.pattern_matrix(B, sorted(modes[24:46]))
+    A = np.zeros((46, 46), dtype=np.complex128)
+    A[:24, :24] = A1
+    A[24:, 24:] = A2
+    h = ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
+    ref = complex(oracle.haf_enum(A1)) * complex(oracle.haf_enum(A2))
+    err = relerr(h, ref)
+    print(f"n=46 block-diagonal rel err {err:.2e}")
+    assert err < 1e-5
