@@ -99,7 +99,9 @@ int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int6
 
 /* Algorithmic FP64 flop count of one hafnian of size n (per-subset matrix products, trace inner
  * products and the coefficient recursion of the power-trace method as the library schedules it;
- * a complex multiply-add counts 8). Padding and bookkeeping are not counted. */
+ * a complex multiply-add counts 8). A subset with 2|Z| < n/2 forms only its first 2|Z| traces and
+ * extends the rest by Newton's identities, which is what is counted for it. Padding and
+ * bookkeeping are not counted. */
 double gbs_haf_flops(int32_t n);
 
 /* ---------------------------------------------------------------- hafnians */

@@ -273,6 +273,7 @@ __global__ __launch_bounds__(kThreads) void qtile_engine_kernel(EngineArgs args)
     P.src = pd.src;
     P.n = n;
     P.m = args.m;
+    P.ld = n;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
     if (k == K) qtile_range<K>(P, item.lo, item.hi, pl4, xq, tred, trw, sz, terms, tid, sr, si, cr, ci);
     if (tid == 0) {

@@ -160,33 +160,60 @@ __device__ __forceinline__ void reduce_folded_quad(const double (&w)[K], int lan
   }
 }
 
-// Four subsets (one per block) with matrices of at most 4*T4 rows.
-template <int K, int T4>
+// Four subsets (one per block) with matrices of at most 4*T4 rows; forms the first KK of the K
+// traces (KK >= 2|Z| for all four, so the combine step extends the rest exactly).
+template <int K, int T4, int KK>
 __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* pl4, int d_b, bool valid_b, double* trw,
                                           int u_b, int lane) {
-  constexpr int NS = kChainTable[K].nslots;
+  static_assert(KK <= K, "trace count");
+  constexpr int NS = kChainTable[KK].nslots;
   const int b = (lane >> 2) & 3;
   const int x = lane & 3, y = lane >> 4;
   const int32_t* pl = pl4 + b * kMaxK;
   QMat<T4> S[NS];
+  if (P.lds) {
+    // staged copy with a zero row and column at index n: padded entries read a zero, no branches
+    lds_d* Al = (lds_d*)P.lds;
+    int roff[T4], cix[T4];
 #pragma unroll
-  for (int I = 0; I < T4; ++I)
+    for (int I = 0; I < T4; ++I) {
+      const int a = 4 * I + y, bb = a ^ 1;
+      const int r = 2 * pl[bb >> 1] + (bb & 1);
+      roff[I] = (valid_b && a < d_b ? r : P.n) * P.ld;
+    }
 #pragma unroll
     for (int J = 0; J < T4; ++J) {
-      const int a = 4 * I + y, c = 4 * J + x;
-      double vr = 0.0, vi = 0.0;
-      if (valid_b && a < d_b && c < d_b) {
-        const int bb = a ^ 1;
-        const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
-        vr = e.x;
-        vi = e.y;
-      }
-      S[0].r[I][J] = vr;
-      S[0].i[I][J] = vi;
+      const int c = 4 * J + x;
+      const int col = 2 * pl[c >> 1] + (c & 1);
+      cix[J] = valid_b && c < d_b ? col : P.n;  // pair lists of blocks past the last subset are stale
     }
-  double w[K];
-  run_ops_quad<K, T4, 0, NS>(S, w, lane);
-  reduce_folded_quad<K>(w, lane, [&](int j, int part, double v) {
+#pragma unroll
+    for (int I = 0; I < T4; ++I)
+#pragma unroll
+      for (int J = 0; J < T4; ++J) {
+        S[0].r[I][J] = Al[2 * (roff[I] + cix[J])];
+        S[0].i[I][J] = Al[2 * (roff[I] + cix[J]) + 1];
+      }
+  } else {
+#pragma unroll
+    for (int I = 0; I < T4; ++I)
+#pragma unroll
+      for (int J = 0; J < T4; ++J) {
+        const int a = 4 * I + y, c = 4 * J + x;
+        double vr = 0.0, vi = 0.0;
+        if (valid_b && a < d_b && c < d_b) {
+          const int bb = a ^ 1;
+          const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
+          vr = e.x;
+          vi = e.y;
+        }
+        S[0].r[I][J] = vr;
+        S[0].i[I][J] = vi;
+      }
+  }
+  double w[KK];
+  run_ops_quad<KK, T4, 0, NS>(S, w, lane);
+  reduce_folded_quad<KK>(w, lane, [&](int j, int part, double v) {
     if (valid_b) trw[j * (2 * kWaveG) + 2 * u_b + part] = 0.5 * v;
   });
 }
@@ -229,15 +256,22 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       const int d_b = 2 * (b == 0 ? s4[0] : (b == 1 ? s4[1] : (b == 2 ? s4[2] : s4[3])));
       const bool valid_b = b < nv;
       const int u_b = u0 + b;
+      // traces formed: min(K, 2 smax), the rest follow from them (extend_traces)
       if (smax <= 2)
-        eval_quad<K, 1>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+      else if (smax <= 3)
+        eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, u_b, lane);
       else if (kQuadMaxS <= 4 || smax <= 4)
-        eval_quad<K, 2>(P, pl4, d_b, valid_b, trw, u_b, lane);
-      else if constexpr (kQuadMaxS > 4)
-        eval_quad<K, 3>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+      else if constexpr (kQuadMaxS > 4) {
+        if (smax <= 5)
+          eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        else
+          eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+      }
     }
     wave_sync();
-    combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    combine_batch<K, (K > 4)>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
     wave_sync();
   }
 }

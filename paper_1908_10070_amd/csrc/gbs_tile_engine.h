@@ -232,6 +232,7 @@ __global__ __launch_bounds__(T * T * 64) void tile_engine_kernel(EngineArgs args
     P.src = pd.src;
     P.n = n;
     P.m = args.m;
+    P.ld = n;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
     if (k == K) tile_range<K, T>(P, item.lo, item.hi, pl, xbuf, tred, trw, sz, terms, tid, sr, si, cr, ci);
     if (tid == 0) {

@@ -32,6 +32,8 @@ namespace gbs {
 
 namespace {
 
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaveG = 32;  // subsets buffered per wave before the coefficient step
@@ -268,26 +270,43 @@ __device__ __forceinline__ void reduce_folded(const double (&w)[K], int lane, St
   }
 }
 
+typedef const __attribute__((address_space(3))) double lds_d;  // LDS-qualified, for direct ds_read
+
 struct PatternView {
-  const double2* lds;     // staged n x n matrix (row-major) or nullptr
+  const double2* lds;     // staged matrix in LDS, row-major with leading dimension ld, or nullptr
   const double2* A;       // global matrix (haf path) or B (prob path)
   const int32_t* modes;   // LDS mode list (prob path) or nullptr
   int64_t src;
   int n, m;
+  int ld;                 // n + 1 where row n and column n of the staged copy are zero, else n
   __device__ __forceinline__ double2 at(int i, int j) const {
-    if (lds) return lds[i * n + j];
+    if (lds) return lds[i * ld + j];
     if (modes) return A[(int64_t)modes[i] * m + modes[j]];
     return A[src + (int64_t)i * n + j];
   }
 };
 
-// One subset: build M_Z, run the chain program, reduce the traces into the wave's buffer slot u.
-template <int K, int T>
+// One subset: build M_Z, run the chain program for the first KK traces (KK >= d or KK = K; the
+// combine step extends the rest), reduce them into the wave's buffer slot u.
+template <int K, int T, int KK = K>
 __device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t* pl, int d, double* trw, int u,
                                             int lane) {
-  constexpr int NS = kChainTable[K].nslots;
+  static_assert(KK <= K, "trace count");
+  constexpr int NS = kChainTable[KK].nslots;
   CMat<T> S[NS];
   const int x = lane & 15, y = lane >> 4;
+  if (T == 1 && P.lds) {
+    // staged copy with a zero row and column at index n: padded entries read a zero, no branches
+    lds_d* Al = (lds_d*)P.lds;
+    const int cix = x < d ? 2 * pl[x >> 1] + (x & 1) : P.n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = y + 4 * r, b = a ^ 1;
+      const int ro = (a < d ? 2 * pl[b >> 1] + (b & 1) : P.n) * P.ld;
+      S[0].r[0][0][r] = Al[2 * (ro + cix)];
+      S[0].i[0][0][r] = Al[2 * (ro + cix) + 1];
+    }
+  } else {
 #pragma unroll
   for (int I = 0; I < T; ++I)
 #pragma unroll
@@ -308,9 +327,10 @@ __device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t*
         S[0].r[I][J][r] = vr;
         S[0].i[I][J][r] = vi;
       }
-  double w[K];
-  run_ops<K, T, 0, NS>(S, w, d, lane);
-  reduce_folded<K>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
+  }
+  double w[KK];
+  run_ops<KK, T, 0, NS>(S, w, d, lane);
+  reduce_folded<KK>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
 }
 
 __device__ __forceinline__ uint32_t unrank(int k, int64_t g, int* s_out) {
@@ -343,11 +363,64 @@ __device__ __forceinline__ uint32_t next_subset(uint32_t mask, int k, int* s) {
   return (1u << *s) - 1u;
 }
 
-// Coefficient recursion for the buffered subsets (one lane each) and the compensated sum.
+// Halved traces t_j = tr(M^j) / 2 for j > d from t_1..t_d, for a d x d matrix M (d = 2|Z| < K),
+// in place in the lane's column of the trace buffer (t_j at tw[j * 2 kWaveG], imaginary part next).
+// The characteristic polynomial of M has degree d, so with a_i = (-1)^(i-1) e_i (e_i the elementary
+// symmetric functions of the eigenvalues, zero for i > d), Newton's identities give
+//   i a_i = 2 (t_i - sum_{j<i} a_{i-j} t_j)   (i <= d)   and   t_q = sum_{i<=d} a_i t_{q-i}   (q > d).
+// Exact in exact arithmetic; an engine may therefore form only the first min(K, d) traces.
 template <int K>
-__device__ __forceinline__ void combine_batch(const double* trw, const int32_t* sz, double2* terms, int cnt, int lane,
+__device__ __forceinline__ void extend_traces(double* tw, int d) {
+  constexpr int S = 2 * kWaveG;
+  double2 a[K];
+#pragma unroll
+  for (int i = 1; i < K; ++i) {
+    double vr = 0.0, vi = 0.0;
+    if (i <= d) {
+      vr = tw[i * S];
+      vi = tw[i * S + 1];
+#pragma unroll
+      for (int j = 1; j < i; ++j) {
+        const double tr = tw[j * S], ti = tw[j * S + 1];
+        vr = fma(-a[i - j].x, tr, vr);
+        vr = fma(a[i - j].y, ti, vr);
+        vi = fma(-a[i - j].x, ti, vi);
+        vi = fma(-a[i - j].y, tr, vi);
+      }
+      const double f = 2.0 / i;  // a constant once the loop is unrolled
+      vr *= f;
+      vi *= f;
+    }
+    a[i] = make_double2(vr, vi);
+  }
+#pragma unroll
+  for (int q = 2; q <= K; ++q) {
+    if (q > d) {
+      double vr = 0.0, vi = 0.0;
+#pragma unroll
+      for (int i = 1; i < q; ++i) {
+        const double tr = tw[(q - i) * S], ti = tw[(q - i) * S + 1];
+        vr = fma(a[i].x, tr, vr);
+        vr = fma(-a[i].y, ti, vr);
+        vi = fma(a[i].x, ti, vi);
+        vi = fma(a[i].y, tr, vi);
+      }
+      tw[q * S] = vr;
+      tw[q * S + 1] = vi;
+    }
+  }
+}
+
+// Coefficient recursion for the buffered subsets (one lane each) and the compensated sum. With
+// EXT, traces beyond 2|Z| (which the engine leaves unformed) are first extended from the first 2|Z|.
+template <int K, bool EXT = false>
+__device__ __forceinline__ void combine_batch(double* trw, const int32_t* sz, double2* terms, int cnt, int lane,
                                               double& sr, double& si, double& cr, double& ci) {
   if (lane < cnt) {
+    if constexpr (EXT) {
+      const int d = 2 * sz[lane];
+      if (d < K) extend_traces<K>(trw + 2 * lane, d);
+    }
     double2 c[K + 1];
     c[0] = make_double2(1.0, 0.0);
 #pragma unroll
@@ -403,10 +476,15 @@ __device__ void wave_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       if (lane < K && ((mask >> lane) & 1u)) pl[__popc(mask & ((1u << lane) - 1u))] = lane;
       if (lane == 0) sz[u] = s;
       wave_sync();
-      eval_subset<K, T>(P, pl, 2 * s, trw, u, lane);
+      if (T == 1 && s == 7 && 14 < K)
+        eval_subset<K, T, cmin(K, 14)>(P, pl, 2 * s, trw, u, lane);
+      else if (T == 1 && s == 8 && 16 < K)
+        eval_subset<K, T, cmin(K, 16)>(P, pl, 2 * s, trw, u, lane);
+      else
+        eval_subset<K, T>(P, pl, 2 * s, trw, u, lane);
     }
     wave_sync();
-    combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    combine_batch<K, (K > 14)>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
     wave_sync();
   }
 }
@@ -423,7 +501,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(int nmax, int kmax, int stage
   WaveLds L;
   size_t off = 0;
   L.A = off;
-  off += stage_A ? wal16(sizeof(double) * 2 * nmax * nmax) : 0;
+  off += stage_A ? wal16(sizeof(double) * 2 * (nmax + 1) * (nmax + 1)) : 0;
   L.modes = off;
   off += wal16(sizeof(int32_t) * GBS_N_MAX);
   L.pl = off;
@@ -471,10 +549,13 @@ __device__ __forceinline__ void wave_items(const EngineArgs& args, unsigned char
     if (prob && tid < n) mlds[tid] = args.modes[pd.src + tid];
     __syncthreads();
     const bool staged = args.stage_A && n <= 32;
+    const int ld = n + 1;  // staged copy: (n + 1) x (n + 1), row n and column n zero
     if (staged) {
-      for (int e = tid; e < n * n; e += kThreads) {
-        const int i = e / n, j = e - (e / n) * n;
-        Alds[e] = prob ? args.A[(int64_t)mlds[i] * args.m + mlds[j]] : args.A[pd.src + e];
+      for (int e = tid; e < ld * ld; e += kThreads) {
+        const int i = e / ld, j = e - (e / ld) * ld;
+        double2 v = make_double2(0.0, 0.0);
+        if (i < n && j < n) v = prob ? args.A[(int64_t)mlds[i] * args.m + mlds[j]] : args.A[pd.src + (int64_t)i * n + j];
+        Alds[e] = v;
       }
     }
     __syncthreads();
@@ -485,6 +566,7 @@ __device__ __forceinline__ void wave_items(const EngineArgs& args, unsigned char
     P.src = pd.src;
     P.n = n;
     P.m = args.m;
+    P.ld = ld;
 
     // this wave's quarter of the item
     const int64_t len = item.hi - item.lo;
