@@ -172,28 +172,21 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
   const int32_t* pl = pl4 + b * kMaxK;
   QMat<T4> S[NS];
   if (P.lds) {
-    // staged copy with a zero row and column at index n: padded entries read a zero, no branches
-    lds_d* Al = (lds_d*)P.lds;
-    int roff[T4], cix[T4];
+    // blocks past the last subset (stale pair lists) gather as d = 0: every entry the zero one
+    const int dv = valid_b ? d_b : 0;
+    int cix[T4];
+#pragma unroll
+    for (int J = 0; J < T4; ++J) cix[J] = mz_col(P, pl, 4 * J + x, dv);
 #pragma unroll
     for (int I = 0; I < T4; ++I) {
-      const int a = 4 * I + y, bb = a ^ 1;
-      const int r = 2 * pl[bb >> 1] + (bb & 1);
-      roff[I] = (valid_b && a < d_b ? r : P.n) * P.ld;
-    }
-#pragma unroll
-    for (int J = 0; J < T4; ++J) {
-      const int c = 4 * J + x;
-      const int col = 2 * pl[c >> 1] + (c & 1);
-      cix[J] = valid_b && c < d_b ? col : P.n;  // pair lists of blocks past the last subset are stale
-    }
-#pragma unroll
-    for (int I = 0; I < T4; ++I)
+      const int ro = mz_row(P, pl, 4 * I + y, dv);
 #pragma unroll
       for (int J = 0; J < T4; ++J) {
-        S[0].r[I][J] = Al[2 * (roff[I] + cix[J])];
-        S[0].i[I][J] = Al[2 * (roff[I] + cix[J]) + 1];
+        const double2 e = mz_at(P, ro + cix[J]);
+        S[0].r[I][J] = e.x;
+        S[0].i[I][J] = e.y;
       }
+    }
   } else {
 #pragma unroll
     for (int I = 0; I < T4; ++I)

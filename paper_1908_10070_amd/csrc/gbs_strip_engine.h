@@ -138,21 +138,37 @@ __device__ __forceinline__ void eval_strip(const PatternView& P, const int32_t* 
   for (int c = 0; c < 4; ++c) addr[c] = (y + 4 * c + 16 * x) * 4;
   {
     SMat<T4> S[NS];
+    if (P.lds) {
+      int cix[NR];
 #pragma unroll
-    for (int I = 0; I < T4; ++I)
+      for (int R = 0; R < NR; ++R) cix[R] = mz_col(P, pl, 4 * (4 * R + b) + x, d);
 #pragma unroll
-      for (int R = 0; R < NR; ++R) {
-        const int a = 4 * I + y, c = 4 * (4 * R + b) + x;
-        double vr = 0.0, vi = 0.0;
-        if (a < d && c < d) {
-          const int bb = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
-          const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
-          vr = e.x;
-          vi = e.y;
+      for (int I = 0; I < T4; ++I) {
+        const int ro = mz_row(P, pl, 4 * I + y, d);
+#pragma unroll
+        for (int R = 0; R < NR; ++R) {
+          const double2 e = mz_at(P, ro + cix[R]);
+          S[0].r[I][R] = e.x;
+          S[0].i[I][R] = e.y;
         }
-        S[0].r[I][R] = vr;
-        S[0].i[I][R] = vi;
       }
+    } else {
+#pragma unroll
+      for (int I = 0; I < T4; ++I)
+#pragma unroll
+        for (int R = 0; R < NR; ++R) {
+          const int a = 4 * I + y, c = 4 * (4 * R + b) + x;
+          double vr = 0.0, vi = 0.0;
+          if (a < d && c < d) {
+            const int bb = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
+            const double2 e = P.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
+            vr = e.x;
+            vi = e.y;
+          }
+          S[0].r[I][R] = vr;
+          S[0].i[I][R] = vi;
+        }
+    }
     run_ops_strip<K, T4, 0, NS>(S, park, addr, (d + 3) >> 2, lane);
   }
   double w[K];
@@ -340,17 +356,33 @@ __device__ __forceinline__ void eval_strip5(const PatternView& P, const int32_t*
   };
   {
     S5Mat S[NS];
+    if (P.lds) {
+      const int cm = mz_col(P, pl, 4 * b + x, d), cs = mz_col(P, pl, 16 + x, d);
 #pragma unroll
-    for (int I = 0; I < 5; ++I) {
-      const double2 e = at(4 * I + y, 4 * b + x);
-      S[0].mr[I] = e.x;
-      S[0].mi[I] = e.y;
-    }
+      for (int I = 0; I < 5; ++I) {
+        const double2 e = mz_at(P, mz_row(P, pl, 4 * I + y, d) + cm);
+        S[0].mr[I] = e.x;
+        S[0].mi[I] = e.y;
+      }
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const double2 e = at(4 * (4 * g + b) + y, 16 + x);
-      S[0].sr[g] = e.x;
-      S[0].si[g] = e.y;
+      for (int g = 0; g < 2; ++g) {
+        const double2 e = mz_at(P, mz_row(P, pl, 4 * (4 * g + b) + y, d) + cs);
+        S[0].sr[g] = e.x;
+        S[0].si[g] = e.y;
+      }
+    } else {
+#pragma unroll
+      for (int I = 0; I < 5; ++I) {
+        const double2 e = at(4 * I + y, 4 * b + x);
+        S[0].mr[I] = e.x;
+        S[0].mi[I] = e.y;
+      }
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const double2 e = at(4 * (4 * g + b) + y, 16 + x);
+        S[0].sr[g] = e.x;
+        S[0].si[g] = e.y;
+      }
     }
     run_ops_strip5<K, 0, NS>(S, park, addr, baddr, b == 0, lane);
   }

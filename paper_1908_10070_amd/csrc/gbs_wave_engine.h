@@ -286,6 +286,21 @@ struct PatternView {
   }
 };
 
+// Gather from the zero-padded staged copy that the item loop below writes (ld = n + 1, row n and
+// column n zero): offset of row a and index of column c of M_Z = X A_Z (d x d) for the pair list
+// pl; rows and columns at or beyond d map to the zero row / column, so every read is unconditional.
+__device__ __forceinline__ int mz_row(const PatternView& P, const int32_t* pl, int a, int d) {
+  const int b = a ^ 1;  // row a of M is row a^1 of A_Z
+  return (a < d ? 2 * pl[b >> 1] + (b & 1) : P.n) * P.ld;
+}
+__device__ __forceinline__ int mz_col(const PatternView& P, const int32_t* pl, int c, int d) {
+  return c < d ? 2 * pl[c >> 1] + (c & 1) : P.n;
+}
+__device__ __forceinline__ double2 mz_at(const PatternView& P, int off) {
+  lds_d* Al = (lds_d*)P.lds;
+  return make_double2(Al[2 * off], Al[2 * off + 1]);
+}
+
 // One subset: build M_Z, run the chain program for the first KK traces (KK >= d or KK = K; the
 // combine step extends the rest), reduce them into the wave's buffer slot u.
 template <int K, int T, int KK = K>
@@ -297,14 +312,12 @@ __device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t*
   const int x = lane & 15, y = lane >> 4;
   if (T == 1 && P.lds) {
     // staged copy with a zero row and column at index n: padded entries read a zero, no branches
-    lds_d* Al = (lds_d*)P.lds;
-    const int cix = x < d ? 2 * pl[x >> 1] + (x & 1) : P.n;
+    const int cix = mz_col(P, pl, x, d);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int a = y + 4 * r, b = a ^ 1;
-      const int ro = (a < d ? 2 * pl[b >> 1] + (b & 1) : P.n) * P.ld;
-      S[0].r[0][0][r] = Al[2 * (ro + cix)];
-      S[0].i[0][0][r] = Al[2 * (ro + cix) + 1];
+      const double2 e = mz_at(P, mz_row(P, pl, y + 4 * r, d) + cix);
+      S[0].r[0][0][r] = e.x;
+      S[0].i[0][0][r] = e.y;
     }
   } else {
 #pragma unroll
