@@ -58,14 +58,6 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ double pick(const d4& v, int r) {
-  double o = v[0];
-  o = r == 1 ? v[1] : o;
-  o = r == 2 ? v[2] : o;
-  o = r == 3 ? v[3] : o;
-  return o;
-}
-
 // Up to this k, complex products use three real products per step (Gauss): with T1 = Xr Yr,
 // T2 = Xi Yi, T3 = (Xr + Xi)(Yr + Yi), Re = T1 - T2 and Im = T3 - T1 - T2. That is 3/4 of the MFMA
 // work for two extra additions per step. The imaginary part's rounding bound is about twice the
@@ -141,16 +133,22 @@ __device__ __forceinline__ void cmul_mat(const CMat<T>& X, const CMat<T>& Y, CMa
 // per-lane partial of tr(X): the diagonal element this lane holds, if any
 template <int T>
 __device__ __forceinline__ double2 tdiag(const CMat<T>& X, int lane) {
-  double2 t = make_double2(0.0, 0.0);
+  // the lane's diagonal element, if it holds one, is register r = (x - y) / 4 of each diagonal
+  // tile; 0/1 weights pick it without a branch (exact for finite entries: the rest adds zeros)
   const int x = lane & 15, y = lane >> 4;
-  if (x >= y && ((x - y) & 3) == 0) {
-    const int r = (x - y) >> 2;
+  const bool on = x >= y && ((x - y) & 3) == 0;
+  const int r = (x - y) >> 2;
+  double wgt[4];
 #pragma unroll
-    for (int I = 0; I < T; ++I) {
-      t.x += pick(X.r[I][I], r);
-      t.y += pick(X.i[I][I], r);
+  for (int q = 0; q < 4; ++q) wgt[q] = on && r == q ? 1.0 : 0.0;
+  double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int I = 0; I < T; ++I)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      t.x = fma(wgt[q], X.r[I][I][q], t.x);
+      t.y = fma(wgt[q], X.i[I][I][q], t.y);
     }
-  }
   return t;
 }
 
