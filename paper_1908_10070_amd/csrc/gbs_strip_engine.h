@@ -262,12 +262,11 @@ __device__ __forceinline__ void strip5_mul(const S5Mat& X, const S5Mat& Y, S5Mat
       u2[0] = mfma4(ai, bi, K == 0 ? 0.0 : u2[0]);
       u3[0] = mfma4(ar + ai, bs, K == 0 ? 0.0 : u3[0]);
     }
-    // row 4 (block 0 only): X's tile (4, K) by rows = X's tile (K, 4), in side register K / 4
+    // row 4 (block 0 only): X's tile (4, K) by rows = X's tile (K, 4), in side register K / 4;
+    // blocks 1..3 compute a product that is discarded below (one select per result register)
     {
-      double ar = swz_tr(K, X.sr[K >> 2]);
-      double ai = swz_tr(K, X.si[K >> 2]);
-      ar = block0 ? ar : 0.0;
-      ai = block0 ? ai : 0.0;
+      const double ar = swz_tr(K, X.sr[K >> 2]);
+      const double ai = swz_tr(K, X.si[K >> 2]);
       u1[1] = mfma4(ar, br, K == 0 ? 0.0 : u1[1]);
       u2[1] = mfma4(ai, bi, K == 0 ? 0.0 : u2[1]);
       u3[1] = mfma4(ar + ai, bs, K == 0 ? 0.0 : u3[1]);
@@ -278,6 +277,8 @@ __device__ __forceinline__ void strip5_mul(const S5Mat& X, const S5Mat& Y, S5Mat
     acc.sr[g] = u1[g] - u2[g];
     acc.si[g] = u3[g] - u1[g] - u2[g];
   }
+  acc.sr[1] = block0 ? acc.sr[1] : 0.0;  // tiles (5..7, 4) do not exist
+  acc.si[1] = block0 ? acc.si[1] : 0.0;
   Z = acc;
 }
 
