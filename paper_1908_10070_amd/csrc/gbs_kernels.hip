@@ -184,16 +184,21 @@ __device__ __forceinline__ uint32_t deposit(uint32_t t, uint32_t mask) {
   return out;
 }
 
+constexpr int kMargUnroll = 4;  // subsets of the high walk whose table reads are in flight together
 constexpr int kMargLow = 7;                  // positions of C spread over the lanes
 constexpr int kMargHigh = kMaxK - kMargLow;  // at most this many walked in the uniform loop
 
 // One wave per class. For each member A (in order) and C = [k] minus A, the even subsets a of C are
 // split as a = low | high: low ranges over the subsets of C's lowest kMargLow positions -- lane l
 // owns the l-th one of even and the l-th one of odd size, so every lane works on every step -- and
-// high walks all subsets of C's other positions in increasing order, the same for every lane (the
+// high walks subsets of C's other positions in increasing order, the same for every lane (the
 // wave reads neighbouring table entries). The parity of high picks the lane's even or odd low
 // subset so that |a| is even; partial sums are kept per size of high (a uniform index) and moved to
-// j = |a| / 2 at the end. Lane sums are combined in a fixed order, so results do not depend on timing.
+// j = |a| / 2 at the end. The product h(a) h(C minus a) is the same for a and its complement, and
+// exactly one of the two holds C's highest position: when that position is a high one, only the
+// subsets a containing it are walked and each product is added to j = |a| / 2 and to
+// j' = |C minus a| / 2 (half the table reads). Lane sums are combined in a fixed order, so results do
+// not depend on timing.
 __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
   __shared__ double2 acc[(kMaxK / 2 + 1) * 64];
   __shared__ double2 H[kMaxK / 2 + 1];
@@ -232,6 +237,9 @@ __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
         for (int t = 0; t < nl; ++t, r &= r - 1u) L |= r & (0u - r);
       }
       const uint32_t Hh = C & ~L;
+      // pairs (a, C minus a) once each: walk only high parts holding C's top position (if it is high)
+      const uint32_t top = Hh ? (0x80000000u >> __clz(Hh)) : 0u;
+      const uint32_t Hw = Hh & ~top;
       const int half = nl > 0 ? 1 << (nl - 1) : 1;  // number of even (and of odd) low subsets
       const uint32_t te = ((uint32_t)lane << 1) | ((uint32_t)__popc((uint32_t)lane) & 1u);
       const uint32_t to = ((uint32_t)lane << 1) | ((~(uint32_t)__popc((uint32_t)lane)) & 1u);
@@ -241,15 +249,43 @@ __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
       double sr[kMargHigh + 1], si[kMargHigh + 1];
 #pragma unroll
       for (int t = 0; t <= kMargHigh; ++t) sr[t] = si[t] = 0.0;
-      uint32_t hm = 0;
-      do {
-        const int ph = __popc(hm);  // uniform
-        const bool even = (ph & 1) == 0;
-        if (even ? ae : ao) {
-          const uint32_t sub = (even ? le : lo) | hm;
-          const double2 x = h[sub], y = h[C ^ sub];
+      // the walk in steps of kMargUnroll consecutive subsets: their table reads are issued together
+      // (independent gathers in flight), then accumulated in walk order
+      uint32_t sw = 0;  // walked subset of Hw; the high part is sw | top
+      bool more = true;
+      while (more) {
+        uint32_t hq[kMargUnroll], sq[kMargUnroll];
+        bool vq[kMargUnroll];  // uniform: the walk has not wrapped around to 0 yet
+        sq[0] = sw;
+        vq[0] = true;
+#pragma unroll
+        for (int u = 1; u < kMargUnroll; ++u) {
+          sq[u] = (sq[u - 1] - Hw) & Hw;  // next subset of Hw in increasing order
+          vq[u] = vq[u - 1] && sq[u] != 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMargUnroll; ++u) hq[u] = sq[u] | top;
+        sw = (sq[kMargUnroll - 1] - Hw) & Hw;
+        more = vq[kMargUnroll - 1] && sw != 0;
+        double2 xs[kMargUnroll], ys[kMargUnroll];
+        bool act[kMargUnroll];
+#pragma unroll
+        for (int u = 0; u < kMargUnroll; ++u) {
+          const bool even = (__popc(hq[u]) & 1) == 0;
+          act[u] = vq[u] && (even ? ae : ao);
+          xs[u] = ys[u] = make_double2(0.0, 0.0);
+          if (act[u]) {
+            const uint32_t sub = (even ? le : lo) | hq[u];
+            xs[u] = h[sub];
+            ys[u] = h[C ^ sub];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kMargUnroll; ++u) {
+          if (!act[u]) continue;
+          const double2 x = xs[u], y = ys[u];
           const double pr = fma(x.x, y.x, -x.y * y.y), pi = fma(x.x, y.y, x.y * y.x);
-          switch (ph) {  // uniform index into registers
+          switch (__popc(hq[u])) {  // uniform index into registers
 #define GBS_MARG_ACC(T) \
             case T:                \
               sr[T] += pr;         \
@@ -262,15 +298,20 @@ __global__ __launch_bounds__(64) void marg_class_kernel(MargArgs a) {
             default: break;
           }
         }
-        hm = (hm - Hh) & Hh;  // next subset of Hh in increasing order
-      } while (hm != 0);
+      }
       // |a| = |low| + |high|: move each partial to j = |a| / 2 (one lane writes only its own slots)
 #pragma unroll
       for (int t = 0; t <= kMargHigh; ++t) {
         if (t <= cs - nl) {
           const int pl = (t & 1) ? po : pe;
           const int j = (pl + t) >> 1;
-          if ((t & 1) ? ao : ae) acc[j * 64 + lane] = make_double2(acc[j * 64 + lane].x + sr[t], acc[j * 64 + lane].y + si[t]);
+          if ((t & 1) ? ao : ae) {
+            acc[j * 64 + lane] = make_double2(acc[j * 64 + lane].x + sr[t], acc[j * 64 + lane].y + si[t]);
+            if (top) {  // the complement's share
+              const int j2 = (cs - pl - t) >> 1;
+              acc[j2 * 64 + lane] = make_double2(acc[j2 * 64 + lane].x + sr[t], acc[j2 * 64 + lane].y + si[t]);
+            }
+          }
         }
       }
       __syncthreads();
