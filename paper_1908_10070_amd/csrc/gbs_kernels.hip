@@ -184,9 +184,9 @@ __device__ __forceinline__ uint32_t deposit(uint32_t t, uint32_t mask) {
   return out;
 }
 
-constexpr int kMargUnroll = 4;  // subsets of the high walk whose table reads are in flight together
 constexpr int kMargLow = 7;                  // positions of C spread over the lanes
 constexpr int kMargHigh = kMaxK - kMargLow;  // at most this many walked in the uniform loop
+constexpr int kMargUnroll = 4;               // walk steps whose table reads are in flight together
 
 // One wave per class. For each member A (in order) and C = [k] minus A, the even subsets a of C are
 // split as a = low | high: low ranges over the subsets of C's lowest kMargLow positions -- lane l

@@ -7,7 +7,8 @@
 // lane x + 4b + 16y -- the instruction's output (and B-operand) layout. As in the register engine,
 // every power Q of M_Z has Q[i][c] = Q[c^1][i^1], so the A operand of a product is the transposed
 // tile read from lane l ^ 17 (block bits untouched), and tr(P Q) pairs each tile with the same tile of
-// Q read from lane l ^ 17. The k traces of the four subsets are reduced over the 16 lanes of each
+// Q read from lane l ^ 17. The same symmetry makes tile (J, I) a lane permutation of tile (I, J), so
+// only the tiles with I <= J are stored and computed (qmul: 6 of 9 tile products at T4 = 3). The k traces of the four subsets are reduced over the 16 lanes of each
 // block with the register engine's VALU lane exchanges (fold over bit 5 per trace, then transposed
 // over bits 4 and 1, plain over bit 0); half the lanes store a share of the results.
 #pragma once
@@ -38,51 +39,85 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// Z = X Y; three real products per step (see cmul_mat) when G.
+// Only the tiles (I, J) with I <= J of a power are stored and computed: every power Q of M_Z has
+// Q[a][c] = Q[c^1][a^1], so tile (J, I) holds at lane (x, y) what tile (I, J) holds at lane
+// (y^1, x^1). Per-lane byte addresses of the two lane permutations used (inside each block):
+//   tr: lane (x, y) <- (y, x)          (tile (I, K) read by rows, as an A operand, from tile (I, K))
+//   tf: lane (x, y) <- (y^1, x^1)      (tile (K, J), K > J, as a B operand, from tile (J, K))
+struct QPerm {
+  int tr, tf;
+};
+
+__device__ __forceinline__ QPerm qperm(int lane) {
+  const int x = lane & 3, b = (lane >> 2) & 3, y = lane >> 4;
+  QPerm q;
+  q.tr = (y + 4 * b + 16 * x) * 4;
+  q.tf = ((y ^ 1) + 4 * b + 16 * (x ^ 1)) * 4;
+  return q;
+}
+
+// Z = X Y on the stored tiles (I <= J); three real products per step (see cmul_mat) when G.
+// The A operand of (I, K) is tile (K, I) read at lane l ^ 17 when K <= I (the symmetry above), else
+// stored tile (I, K) transposed; the B operand of (K, J) is stored when K <= J, else tile (J, K)
+// through tf. Z may alias X or Y: it is written after the last product.
 template <int T4, bool G>
-__device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<T4>& Z) {
-  if constexpr (G) {
-    double t1[T4][T4], t2[T4][T4], t3[T4][T4];
+__device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<T4>& Z, const QPerm& pm) {
+  double t1[T4][T4], t2[T4][T4], t3[T4][T4];
 #pragma unroll
-    for (int K = 0; K < T4; ++K) {
+  for (int K = 0; K < T4; ++K) {
+    double br[T4], bi[T4], bs[T4];
 #pragma unroll
-      for (int I = 0; I < T4; ++I) {
-        const double ar = swap17(X.r[K][I]);
-        const double ai = swap17(X.i[K][I]);
+    for (int J = 0; J < T4; ++J) {
+      if (K <= J) {
+        br[J] = Y.r[K][J];
+        bi[J] = Y.i[K][J];
+      } else {
+        br[J] = bperm(pm.tf, Y.r[J][K]);
+        bi[J] = bperm(pm.tf, Y.i[J][K]);
+      }
+      if constexpr (G) bs[J] = br[J] + bi[J];
+    }
+#pragma unroll
+    for (int I = 0; I < T4; ++I) {
+      double ar, ai;
+      if (K <= I) {
+        ar = swap17(X.r[K][I]);
+        ai = swap17(X.i[K][I]);
+      } else {
+        ar = bperm(pm.tr, X.r[I][K]);
+        ai = bperm(pm.tr, X.i[I][K]);
+      }
+      if constexpr (G) {
         const double as = ar + ai;
 #pragma unroll
-        for (int J = 0; J < T4; ++J) {
-          t1[I][J] = mfma4(ar, Y.r[K][J], K == 0 ? 0.0 : t1[I][J]);
-          t2[I][J] = mfma4(ai, Y.i[K][J], K == 0 ? 0.0 : t2[I][J]);
-          t3[I][J] = mfma4(as, Y.r[K][J] + Y.i[K][J], K == 0 ? 0.0 : t3[I][J]);
+        for (int J = I; J < T4; ++J) {
+          t1[I][J] = mfma4(ar, br[J], K == 0 ? 0.0 : t1[I][J]);
+          t2[I][J] = mfma4(ai, bi[J], K == 0 ? 0.0 : t2[I][J]);
+          t3[I][J] = mfma4(as, bs[J], K == 0 ? 0.0 : t3[I][J]);
+        }
+      } else {
+#pragma unroll
+        for (int J = I; J < T4; ++J) {
+          t1[I][J] = mfma4(ar, br[J], K == 0 ? 0.0 : t1[I][J]);
+          t3[I][J] = mfma4(ar, bi[J], K == 0 ? 0.0 : t3[I][J]);
+          t1[I][J] = mfma4(-ai, bi[J], t1[I][J]);
+          t3[I][J] = mfma4(ai, br[J], t3[I][J]);
         }
       }
     }
+  }
 #pragma unroll
-    for (int I = 0; I < T4; ++I)
+  for (int I = 0; I < T4; ++I)
 #pragma unroll
-      for (int J = 0; J < T4; ++J) {
+    for (int J = I; J < T4; ++J) {
+      if constexpr (G) {
         Z.r[I][J] = t1[I][J] - t2[I][J];
         Z.i[I][J] = t3[I][J] - t1[I][J] - t2[I][J];
-      }
-    return;
-  }
-  QMat<T4> acc;
-#pragma unroll
-  for (int K = 0; K < T4; ++K)
-#pragma unroll
-    for (int I = 0; I < T4; ++I) {
-      const double ar = swap17(X.r[K][I]);
-      const double ai = swap17(X.i[K][I]);
-#pragma unroll
-      for (int J = 0; J < T4; ++J) {
-        acc.r[I][J] = mfma4(ar, Y.r[K][J], K == 0 ? 0.0 : acc.r[I][J]);
-        acc.i[I][J] = mfma4(ar, Y.i[K][J], K == 0 ? 0.0 : acc.i[I][J]);
-        acc.r[I][J] = mfma4(-ai, Y.i[K][J], acc.r[I][J]);
-        acc.i[I][J] = mfma4(ai, Y.r[K][J], acc.i[I][J]);
+      } else {
+        Z.r[I][J] = t1[I][J];
+        Z.i[I][J] = t3[I][J];
       }
     }
-  Z = acc;
 }
 
 template <int T4>
@@ -98,13 +133,17 @@ __device__ __forceinline__ double2 qdiag(const QMat<T4>& X, int lane) {
   return t;
 }
 
+// per-lane partial of tr(X Y) = sum X[i][c] Y[i^1][c^1]: tile (I, C) pairs with itself read at lane
+// l ^ 17, and a tile (C, I) below the diagonal contributes what its mirror (I, C) does (both factors
+// have the symmetry above), so off-diagonal stored tiles count twice
 template <int T4>
 __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
-  double2 t = make_double2(0.0, 0.0);
+  double2 d = make_double2(0.0, 0.0), o = make_double2(0.0, 0.0);
 #pragma unroll
   for (int I = 0; I < T4; ++I)
 #pragma unroll
-    for (int C = 0; C < T4; ++C) {
+    for (int C = I; C < T4; ++C) {
+      double2& t = C == I ? d : o;
       const double yr = swap17(Y.r[I][C]);
       const double yi = swap17(Y.i[I][C]);
       t.x = fma(X.r[I][C], yr, t.x);
@@ -112,15 +151,15 @@ __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
       t.y = fma(X.r[I][C], yi, t.y);
       t.y = fma(X.i[I][C], yr, t.y);
     }
-  return t;
+  return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
 template <int K, int T4, int OI, int NS>
-__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], int lane) {
+__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], int lane, const QPerm& pm) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x]);
+      qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], pm);
     } else if constexpr (op.type == OP_TDIAG) {
       const double2 p = qdiag<T4>(S[op.a], lane);
       w[op.x - 1] = fold32(p.x, p.y);
@@ -128,7 +167,7 @@ __device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], 
       const double2 p = qpair<T4>(S[op.a], S[op.b]);
       w[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops_quad<K, T4, OI + 1, NS>(S, w, lane);
+    run_ops_quad<K, T4, OI + 1, NS>(S, w, lane, pm);
   }
 }
 
@@ -181,7 +220,7 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
     for (int I = 0; I < T4; ++I) {
       const int ro = mz_row(P, pl, 4 * I + y, dv);
 #pragma unroll
-      for (int J = 0; J < T4; ++J) {
+      for (int J = I; J < T4; ++J) {  // stored tiles only
         const double2 e = mz_at(P, ro + cix[J]);
         S[0].r[I][J] = e.x;
         S[0].i[I][J] = e.y;
@@ -191,7 +230,7 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
 #pragma unroll
     for (int I = 0; I < T4; ++I)
 #pragma unroll
-      for (int J = 0; J < T4; ++J) {
+      for (int J = I; J < T4; ++J) {  // stored tiles only
         const int a = 4 * I + y, c = 4 * J + x;
         double vr = 0.0, vi = 0.0;
         if (valid_b && a < d_b && c < d_b) {
@@ -205,7 +244,7 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
       }
   }
   double w[KK];
-  run_ops_quad<KK, T4, 0, NS>(S, w, lane);
+  run_ops_quad<KK, T4, 0, NS>(S, w, lane, qperm(lane));
   reduce_folded_quad<KK>(w, lane, [&](int j, int part, double v) {
     if (valid_b) trw[j * (2 * kWaveG) + 2 * u_b + part] = 0.5 * v;
   });

@@ -27,12 +27,6 @@ struct SMat {
   double i[T4][NR];
 };
 
-__device__ __forceinline__ double bperm(int addr, double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)b);
-  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
-  return join((unsigned)lo, (unsigned)hi);
-}
 
 // Z = X Y. addr[c]: byte address of the lane holding, in block c of a register, the element that
 // lane needs as A operand (row x, column y of that block's tile).

@@ -179,6 +179,14 @@ __device__ __forceinline__ double join(unsigned lo, unsigned hi) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// v from the lane whose byte address is addr (ds_bpermute, one per 32-bit half)
+__device__ __forceinline__ double bperm(int addr, double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
+  return join((unsigned)lo, (unsigned)hi);
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -319,25 +327,25 @@ __device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t*
     }
   } else {
 #pragma unroll
-  for (int I = 0; I < T; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-    for (int J = 0; J < T; ++J)
+      for (int J = 0; J < T; ++J)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = 16 * I + y + 4 * r;  // row of M_Z
-        const int c = 16 * J + x;          // column
-        double vr = 0.0, vi = 0.0;
-        if (a < d && c < d) {
-          const int b = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
-          const int ia = 2 * pl[b >> 1] + (b & 1);
-          const int ic = 2 * pl[c >> 1] + (c & 1);
-          const double2 e = P.at(ia, ic);
-          vr = e.x;
-          vi = e.y;
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * I + y + 4 * r;  // row of M_Z
+          const int c = 16 * J + x;          // column
+          double vr = 0.0, vi = 0.0;
+          if (a < d && c < d) {
+            const int b = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
+            const int ia = 2 * pl[b >> 1] + (b & 1);
+            const int ic = 2 * pl[c >> 1] + (c & 1);
+            const double2 e = P.at(ia, ic);
+            vr = e.x;
+            vi = e.y;
+          }
+          S[0].r[I][J][r] = vr;
+          S[0].i[I][J][r] = vi;
         }
-        S[0].r[I][J][r] = vr;
-        S[0].i[I][J][r] = vi;
-      }
   }
   double w[KK];
   run_ops<KK, T, 0, NS>(S, w, d, lane);
