@@ -433,8 +433,9 @@ int upload_tables(const ConstTables& t) {
 namespace gbs {
 
 // Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
-//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS, k = 1..23
+//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS (8), k = 1..23
 //   classes 23..41  register engine (one subset per wave, one 16x16 tile), kQuadMaxS < |Z| <= 8, k = 5..23
+//                   (selected only in builds with kQuadMaxS = 6)
 //   classes 42..49  strip engine, 5 tile rows (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
 //   classes 50..55  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16
 //   classes 56..62  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
@@ -476,7 +477,7 @@ static EngineVariant variant(int cls) {
 }
 
 int engine_class(int s, int k) {
-  static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 6, "register-engine variants start at k = 5");
+  static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 8, "quad engine sizes");
   if (s <= kQuadMaxS) return k - 1;
   if (s <= 8) return 23 + (k - 5);
   if (s <= 12 && k >= 17) return 56 + (k - 17);

@@ -1,14 +1,15 @@
-// Quad subset engine for small subsets (d = 2|Z| <= 12), gfx950.
+// Quad subset engine for small subsets (d = 2|Z| <= 16), gfx950.
 //
 // v_mfma_f64_4x4x4_4b_f64 computes four independent 4x4x4 products, one per block b = (lane >> 2) & 3.
 // Here each block carries a different subset: a wave evaluates four consecutive subsets of the
-// canonical order at once. A d x d complex matrix is a T4 x T4 grid (T4 = ceil(d/4) <= 3) of 4x4
+// canonical order at once. A d x d complex matrix is a T4 x T4 grid (T4 = ceil(d/4) <= 4) of 4x4
 // tiles; one double register per tile holds, for block b, element (row y, column x) of that tile at
 // lane x + 4b + 16y -- the instruction's output (and B-operand) layout. As in the register engine,
 // every power Q of M_Z has Q[i][c] = Q[c^1][i^1], so the A operand of a product is the transposed
 // tile read from lane l ^ 17 (block bits untouched), and tr(P Q) pairs each tile with the same tile of
 // Q read from lane l ^ 17. The same symmetry makes tile (J, I) a lane permutation of tile (I, J), so
-// only the tiles with I <= J are stored and computed (qmul: 6 of 9 tile products at T4 = 3). The k traces of the four subsets are reduced over the 16 lanes of each
+// only the tiles with I <= J are stored and computed (qmul: 6 of 9 tile products at T4 = 3, 10 of 16
+// at T4 = 4). The k traces of the four subsets are reduced over the 16 lanes of each
 // block with the register engine's VALU lane exchanges (fold over bit 5 per trace, then transposed
 // over bits 4 and 1, plain over bit 0); half the lanes store a share of the results.
 #pragma once
@@ -16,8 +17,10 @@
 namespace gbs {
 namespace {
 
+// largest |Z| on the quad engine (4x4 tiles, T4 = ceil(|Z|/2) <= 4); 6 hands |Z| = 7, 8 to the
+// register engine instead (one 16x16 tile per subset)
 #ifndef GBS_QUAD_MAX_S
-#define GBS_QUAD_MAX_S 6
+#define GBS_QUAD_MAX_S 8
 #endif
 constexpr int kQuadMaxS = GBS_QUAD_MAX_S;
 // up to this k the quad engine multiplies with three real products per step (see cmul_mat)
@@ -296,10 +299,17 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       else if (kQuadMaxS <= 4 || smax <= 4)
         eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, u_b, lane);
       else if constexpr (kQuadMaxS > 4) {
-        if (smax <= 5)
-          eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, u_b, lane);
-        else
-          eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        if (kQuadMaxS <= 6 || smax <= 6) {
+          if (smax <= 5)
+            eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+          else
+            eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        } else if constexpr (kQuadMaxS > 6) {
+          if (smax <= 7)
+            eval_quad<K, 4, cmin(K, 14)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+          else
+            eval_quad<K, 4, cmin(K, 16)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        }
       }
     }
     wave_sync();
