@@ -157,20 +157,26 @@ __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
   return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
+// Traces of the 4x4-tile grid are parked in LDS (park[(j - 1) * 64 + lane]) until the chain ends
+// instead of holding k registers through every product; smaller grids keep them in registers.
+constexpr int kQuadParkT4 = 4;
+constexpr int kQuadParkK = 16;  // traces a parked evaluation forms at most (2 |Z| <= 16)
+
 template <int K, int T4, int OI, int NS>
-__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], int lane, const QPerm& pm) {
+__device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], double* park, int lane,
+                                             const QPerm& pm) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], pm);
-    } else if constexpr (op.type == OP_TDIAG) {
-      const double2 p = qdiag<T4>(S[op.a], lane);
-      w[op.x - 1] = fold32(p.x, p.y);
     } else {
-      const double2 p = qpair<T4>(S[op.a], S[op.b]);
-      w[op.x - 1] = fold32(p.x, p.y);
+      const double2 p = op.type == OP_TDIAG ? qdiag<T4>(S[op.a], lane) : qpair<T4>(S[op.a], S[op.b]);
+      if constexpr (T4 >= kQuadParkT4)
+        park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
+      else
+        w[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops_quad<K, T4, OI + 1, NS>(S, w, lane, pm);
+    run_ops_quad<K, T4, OI + 1, NS>(S, w, park, lane, pm);
   }
 }
 
@@ -206,7 +212,7 @@ __device__ __forceinline__ void reduce_folded_quad(const double (&w)[K], int lan
 // traces (KK >= 2|Z| for all four, so the combine step extends the rest exactly).
 template <int K, int T4, int KK>
 __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* pl4, int d_b, bool valid_b, double* trw,
-                                          int u_b, int lane) {
+                                          double* park, int u_b, int lane) {
   static_assert(KK <= K, "trace count");
   constexpr int NS = kChainTable[KK].nslots;
   const int b = (lane >> 2) & 3;
@@ -247,15 +253,21 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
       }
   }
   double w[KK];
-  run_ops_quad<KK, T4, 0, NS>(S, w, lane, qperm(lane));
+  run_ops_quad<KK, T4, 0, NS>(S, w, park, lane, qperm(lane));
+  if constexpr (T4 >= kQuadParkT4) {
+    static_assert(KK <= kQuadParkK, "park size");
+#pragma unroll
+    for (int j = 0; j < KK; ++j) w[j] = park[j * 64 + lane];  // each lane reads only what it wrote
+  }
   reduce_folded_quad<KK>(w, lane, [&](int j, int part, double v) {
     if (valid_b) trw[j * (2 * kWaveG) + 2 * u_b + part] = 0.5 * v;
   });
 }
 
-// Subsets [lo, hi) of one pattern (all with |Z| <= 6) on one wave, four at a time.
+// Subsets [lo, hi) of one pattern (all with |Z| <= kQuadMaxS) on one wave, four at a time.
 template <int K>
-__device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl4, double* trw, int32_t* sz,
+__device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl4, double* trw, double* park,
+                           int32_t* sz,
                            double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
   const int b = (lane >> 2) & 3;
   int s = 1;
@@ -293,22 +305,22 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       const int u_b = u0 + b;
       // traces formed: min(K, 2 smax), the rest follow from them (extend_traces)
       if (smax <= 2)
-        eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 3)
-        eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (kQuadMaxS <= 4 || smax <= 4)
-        eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+        eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if constexpr (kQuadMaxS > 4) {
         if (kQuadMaxS <= 6 || smax <= 6) {
           if (smax <= 5)
-            eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+            eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
           else
-            eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+            eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
         } else if constexpr (kQuadMaxS > 6) {
           if (smax <= 7)
-            eval_quad<K, 4, cmin(K, 14)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+            eval_quad<K, 4, cmin(K, 14)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
           else
-            eval_quad<K, 4, cmin(K, 16)>(P, pl4, d_b, valid_b, trw, u_b, lane);
+            eval_quad<K, 4, cmin(K, 16)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
         }
       }
     }
@@ -319,6 +331,11 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 }
 
 }  // namespace
+
+// LDS: the register engine's layout, then (4x4-tile grids enabled) one trace-parking area per wave.
+__host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A) {
+  return wave_lds_layout(nmax, kmax, stage_A).total + (kQuadMaxS > 6 ? sizeof(double) * 4 * kQuadParkK * 64 : 0);
+}
 
 template <int K>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= GBS_QUAD_WAVES2_KMAX ? 2 : 1, 8))) void
@@ -331,7 +348,8 @@ quad_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    quad_range<K>(P, lo, hi, pl4, trw, sz, terms, lane, sr, si, cr, ci);
+    double* park = reinterpret_cast<double*>(smem + L.total) + wave * kQuadParkK * 64;
+    quad_range<K>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
   });
 }
 
