@@ -436,7 +436,8 @@ namespace gbs {
 //   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS (8), k = 1..23
 //   classes 23..41  register engine (one subset per wave, one 16x16 tile), kQuadMaxS < |Z| <= 8, k = 5..23
 //                   (selected only in builds with kQuadMaxS = 6)
-//   classes 42..49  strip engine, 5 tile rows (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
+//   classes 42..49  quad engine on a 5x5 tile grid (GBS_QUAD5, default) or strip engine with 5 tile rows
+//                   (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
 //   classes 50..55  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16
 //   classes 56..62  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
 //   classes 63..73  tile engine T = 2 (2x2 tiles, 4 waves), 13 <= |Z| <= 16, k = 13..23
@@ -447,6 +448,12 @@ namespace gbs {
 // strip engine. The strip engine has one kernel per tile-row count so that the common 5-row case
 // is not sized for 6 rows.
 enum EngineKind { kQuadKind, kWaveKind, kStripKind, kQtileKind, kTileKind };
+
+// |Z| = 9, 10 for k <= 16: the quad engine on a 5x5 tile grid (default) or the five-row strip engine
+#ifndef GBS_QUAD5
+#define GBS_QUAD5 1
+#endif
+constexpr bool kQuad5 = GBS_QUAD5 != 0;
 
 struct EngineVariant {
   void (*fn)(EngineArgs);
@@ -459,7 +466,10 @@ template <int C>
 static EngineVariant variant_c() {
   if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 1};
   else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
-  else if constexpr (C < 50) return {strip_engine_kernel<C - 42 + 9, 5, 5>, kThreads, kStripKind, 1};
+  else if constexpr (C < 50) {
+    if constexpr (kQuad5) return {quad5_engine_kernel<C - 42 + 9>, kThreads, kQuadKind, 1};
+    else return {strip_engine_kernel<C - 42 + 9, 5, 5>, kThreads, kStripKind, 1};
+  }
   else if constexpr (C < 56) return {strip_engine_kernel<C - 50 + 11, 6, 6>, kThreads, kStripKind, 1};
   else if constexpr (C < 63) return {qtile_engine_kernel<C - 56 + 17>, kThreads, kQtileKind, 1};
   else if constexpr (C < 74) return {tile_engine_kernel<2, C - 63 + 13>, 256, kTileKind, 2};

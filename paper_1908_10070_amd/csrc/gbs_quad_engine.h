@@ -265,7 +265,7 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
 }
 
 // Subsets [lo, hi) of one pattern (all with |Z| <= kQuadMaxS) on one wave, four at a time.
-template <int K>
+template <int K, int T4F = 0>
 __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl4, double* trw, double* park,
                            int32_t* sz,
                            double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
@@ -304,7 +304,9 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       const bool valid_b = b < nv;
       const int u_b = u0 + b;
       // traces formed: min(K, 2 smax), the rest follow from them (extend_traces)
-      if (smax <= 2)
+      if constexpr (T4F > 0)
+        eval_quad<K, T4F, cmin(K, 4 * T4F)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+      else if (smax <= 2)
         eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 3)
         eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
@@ -334,7 +336,25 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 
 // LDS: the register engine's layout, then (4x4-tile grids enabled) one trace-parking area per wave.
 __host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A) {
-  return wave_lds_layout(nmax, kmax, stage_A).total + (kQuadMaxS > 6 ? sizeof(double) * 4 * kQuadParkK * 64 : 0);
+  return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * kQuadParkK * 64;
+}
+
+// |Z| = 9, 10 (d = 18, 20) on a 5x5 grid of 4x4 tiles: 15 stored tiles per power; a kernel of its
+// own, since those registers (about 300) would cost the smaller grids their second wave per SIMD
+template <int K>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 8))) void
+quad5_engine_kernel(EngineArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
+  wave_items<K>(args, smem, [&](const PatternView& P, int64_t lo, int64_t hi, int wave, int lane, double& sr,
+                                double& si, double& cr, double& ci) {
+    int32_t* pl4 = reinterpret_cast<int32_t*>(smem + L.pl) + wave * 4 * kMaxK;
+    double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
+    int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
+    double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
+    double* park = reinterpret_cast<double*>(smem + L.total) + wave * kQuadParkK * 64;
+    quad_range<K, 5>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
+  });
 }
 
 template <int K>
