@@ -112,7 +112,7 @@ struct MargArgs {
 };
 
 // Host-side launchers (defined in gbs_kernels.hip).
-constexpr int kEngineClasses = 81;  // subset-engine kernel variants (see gbs_kernels.hip)
+constexpr int kEngineClasses = 88;  // subset-engine kernel variants (see gbs_kernels.hip)
 int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);
 int engine_blocks_per_cu(int cls, size_t lds);

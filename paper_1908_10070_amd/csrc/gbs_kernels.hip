@@ -440,13 +440,15 @@ namespace gbs {
 //                   (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
 //   classes 50..55  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16
 //   classes 56..62  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
+//                   (|Z| = 11, 12 only, with GBS_QUAD5)
 //   classes 63..73  tile engine T = 2 (2x2 tiles, 4 waves), 13 <= |Z| <= 16, k = 13..23
 //   classes 74..80  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
-// For 9 <= |Z| <= 12 the strip engine measured faster up to k = 16 (n = 24: 1.4x the quad-tile
-// engine's throughput on those subsets); from k = 17 its registers spill and the quad-tile engine,
-// at one wave per SIMD with no spills, is faster. For |Z| = 7, 8 the register engine beat the
-// strip engine. The strip engine has one kernel per tile-row count so that the common 5-row case
-// is not sized for 6 rows.
+//   classes 81..87  quad engine on a 5x5 tile grid, |Z| = 9, 10, k = 17..23 (GBS_QUAD5)
+// Without the 5x5 quad grid, the strip engine measured faster for 9 <= |Z| <= 12 up to k = 16 (n = 24:
+// 1.4x the quad-tile engine's throughput on those subsets); from k = 17 its registers spill and the
+// quad-tile engine, at one wave per SIMD with no spills, is faster. The strip engine has one kernel
+// per tile-row count so that the common 5-row case is not sized for 6 rows. EngineVariant::tiles is
+// the tile count per side of a tile engine and the largest grid side (4 or 5) of a quad engine.
 enum EngineKind { kQuadKind, kWaveKind, kStripKind, kQtileKind, kTileKind };
 
 // |Z| = 9, 10 for k <= 16: the quad engine on a 5x5 tile grid (default) or the five-row strip engine
@@ -464,10 +466,11 @@ struct EngineVariant {
 
 template <int C>
 static EngineVariant variant_c() {
-  if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 1};
+  if constexpr (C >= 81) return {quad5_engine_kernel<C - 81 + 17>, kThreads, kQuadKind, 5};
+  else if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 4};
   else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
   else if constexpr (C < 50) {
-    if constexpr (kQuad5) return {quad5_engine_kernel<C - 42 + 9>, kThreads, kQuadKind, 1};
+    if constexpr (kQuad5) return {quad5_engine_kernel<C - 42 + 9>, kThreads, kQuadKind, 5};
     else return {strip_engine_kernel<C - 42 + 9, 5, 5>, kThreads, kStripKind, 1};
   }
   else if constexpr (C < 56) return {strip_engine_kernel<C - 50 + 11, 6, 6>, kThreads, kStripKind, 1};
@@ -490,6 +493,7 @@ int engine_class(int s, int k) {
   static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 8, "quad engine sizes");
   if (s <= kQuadMaxS) return k - 1;
   if (s <= 8) return 23 + (k - 5);
+  if (kQuad5 && s <= 10 && k >= 17) return 81 + (k - 17);
   if (s <= 12 && k >= 17) return 56 + (k - 17);
   if (s <= 10) return 42 + (k - 9);
   if (s <= 12) return 50 + (k - 11);
@@ -502,7 +506,7 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   if (v.kind == kQtileKind) return qtile_lds_layout(nmax, kmax, stage_A).total;
   if (v.kind == kStripKind) return strip_lds_bytes(nmax, kmax, stage_A);
   if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
-  if (v.kind == kQuadKind) return quad_lds_bytes(nmax, kmax, stage_A);
+  if (v.kind == kQuadKind) return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));
   return wave_lds_layout(nmax, kmax, stage_A).total;
 }
 

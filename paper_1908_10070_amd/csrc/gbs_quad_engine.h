@@ -160,7 +160,8 @@ __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
 // Traces of the 4x4-tile grid are parked in LDS (park[(j - 1) * 64 + lane]) until the chain ends
 // instead of holding k registers through every product; smaller grids keep them in registers.
 constexpr int kQuadParkT4 = 4;
-constexpr int kQuadParkK = 16;  // traces a parked evaluation forms at most (2 |Z| <= 16)
+// parking rows per wave: a kernel whose grids have at most T4 tiles per side forms min(k, 4 T4) traces
+__host__ __device__ constexpr int quad_park_k(int t4max, int k) { return k < 4 * t4max ? k : 4 * t4max; }
 
 template <int K, int T4, int OI, int NS>
 __device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], double* park, int lane,
@@ -255,7 +256,7 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
   double w[KK];
   run_ops_quad<KK, T4, 0, NS>(S, w, park, lane, qperm(lane));
   if constexpr (T4 >= kQuadParkT4) {
-    static_assert(KK <= kQuadParkK, "park size");
+    static_assert(KK <= quad_park_k(T4, K), "park size");
 #pragma unroll
     for (int j = 0; j < KK; ++j) w[j] = park[j * 64 + lane];  // each lane reads only what it wrote
   }
@@ -335,12 +336,12 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 }  // namespace
 
 // LDS: the register engine's layout, then (4x4-tile grids enabled) one trace-parking area per wave.
-__host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A) {
-  return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * kQuadParkK * 64;
+__host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A, int park_k) {
+  return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * park_k * 64;
 }
 
 // |Z| = 9, 10 (d = 18, 20) on a 5x5 grid of 4x4 tiles: 15 stored tiles per power; a kernel of its
-// own, since those registers (about 300) would cost the smaller grids their second wave per SIMD
+// own, since those registers (300 and more) would cost the smaller grids their second wave per SIMD
 template <int K>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 8))) void
 quad5_engine_kernel(EngineArgs args) {
@@ -352,7 +353,7 @@ quad5_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    double* park = reinterpret_cast<double*>(smem + L.total) + wave * kQuadParkK * 64;
+    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(5, K) * 64;
     quad_range<K, 5>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
   });
 }
@@ -368,7 +369,7 @@ quad_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    double* park = reinterpret_cast<double*>(smem + L.total) + wave * kQuadParkK * 64;
+    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(4, K) * 64;
     quad_range<K>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
   });
 }
