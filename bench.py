@@ -117,7 +117,9 @@ def extras(gbs, torch, dev, args):
     for load in (0.5,):
         rate = load * capacity
         arr, pats = inputs.config4_requests(nreq + warm, rate)
-        be = serve.GpuBackend(ctx, st3, pool_entries=1 << 16)
+        # every step has a new shape, so the server's context captures no graphs (nothing to replay)
+        sctx = gbs.Context(0, use_graph=False)
+        be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16)
         cont = serve.Server(be, pool_entries=1 << 16, step_flops=2e11, max_slice=4096).start()
         serve.replay(cont, arr, pats)
         cont.stop()

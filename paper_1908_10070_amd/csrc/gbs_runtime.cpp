@@ -93,11 +93,19 @@ struct gbs_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
-  void* pinned[2] = {nullptr, nullptr};
-  size_t pinned_bytes[2] = {0, 0};
-  hipEvent_t pinned_ev[2] = {nullptr, nullptr};
-  bool pinned_used[2] = {false, false};
+  // ring of pinned staging buffers: a call waits only for the copy of the call kPinRing calls back,
+  // so a caller keeping two steps of two calls each in flight never blocks on the device here
+  static constexpr int kPinRing = 4;
+  void* pinned[kPinRing] = {};
+  size_t pinned_bytes[kPinRing] = {};
+  hipEvent_t pinned_ev[kPinRing] = {};
+  bool pinned_used[kPinRing] = {};
   int pin_idx = 0;
+  int next_pin() {
+    const int i = pin_idx;
+    pin_idx = (pin_idx + 1) % kPinRing;
+    return i;
+  }
   hipEvent_t done_ev = nullptr;
   bool done_recorded = false;
   hipStream_t cap_stream = nullptr;
@@ -321,8 +329,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   int rc = ensure_ws(ctx, L.total);
   if (rc) return rc;
   // stage into the next pinned buffer (wait until its previous copy has finished)
-  const int pi = ctx->pin_idx;
-  ctx->pin_idx ^= 1;
+  const int pi = ctx->next_pin();
   if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
   rc = ensure_pinned(ctx, pi, L.staged_bytes);
   if (rc) return rc;
@@ -534,8 +541,10 @@ int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_
     return GBS_EHIP;
   }
   c->ncu = p.multiProcessorCount;
-  if (upload_tables(T.host) != 0 || hipEventCreateWithFlags(&c->pinned_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->pinned_ev[1], hipEventDisableTiming) != hipSuccess ||
+  bool ev_ok = true;
+  for (int i = 0; i < gbs_ctx::kPinRing; ++i)
+    ev_ok = ev_ok && hipEventCreateWithFlags(&c->pinned_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (upload_tables(T.host) != 0 || !ev_ok ||
       hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     gbs_ctx_destroy(c);
@@ -555,7 +564,7 @@ int gbs_ctx_destroy(gbs_ctx* c) {
   DeviceGuard dg(c->device);
   (void)hipDeviceSynchronize();
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < gbs_ctx::kPinRing; ++i) {
     if (c->pinned[i]) (void)hipHostFree(c->pinned[i]);
     if (c->pinned_ev[i]) (void)hipEventDestroy(c->pinned_ev[i]);
   }
@@ -833,8 +842,7 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_
   const Layout L = layout_for(pl, 0);
   int rc = ensure_ws(ctx, L.total);
   if (rc) return rc;
-  const int pi = ctx->pin_idx;
-  ctx->pin_idx ^= 1;
+  const int pi = ctx->next_pin();
   if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
   rc = ensure_pinned(ctx, pi, L.staged_bytes);
   if (rc) return rc;
@@ -1109,8 +1117,7 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
   if (extra_dev) *extra_dev = ws + o_extra;
   if (!q_out_dev) q_out_dev = reinterpret_cast<double*>(ws + o_extra);
 
-  const int pi = ctx->pin_idx;
-  ctx->pin_idx ^= 1;
+  const int pi = ctx->next_pin();
   if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
   rc = ensure_pinned(ctx, pi, stage_bytes);
   if (rc) return rc;

@@ -354,7 +354,10 @@ def photon_number_pmf(m: int, r: float, nmax: int) -> np.ndarray:
 
 def sfact_of(modes: Sequence[int]) -> float:
     """prod_j s_j! of a mode list (host-side helper for schedulers)."""
-    _, counts = np.unique(np.asarray(modes, dtype=np.int64), return_counts=True)
+    ml = [int(v) for v in modes]
+    if len(set(ml)) == len(ml):
+        return 1.0  # no mode repeats
+    _, counts = np.unique(np.asarray(ml, dtype=np.int64), return_counts=True)
     f = 1.0
     for c in counts:
         for v in range(2, int(c) + 1):

@@ -50,7 +50,7 @@ def subset_flops(n: int, lo: int, hi: int, haf_flops: Callable[[int], float]) ->
     return haf_flops(n) * (hi - lo) / max(cnt, 1)
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)  # requests are distinct objects: identity equality (cheap list removal)
 class Request:
     rid: int
     modes: np.ndarray
@@ -58,6 +58,8 @@ class Request:
     t_arrival: float
     future: Future
     slices: List[tuple] = dataclasses.field(default_factory=list)
+    work: List[float] = dataclasses.field(default_factory=list)  # modelled flops of each slice
+    remaining: float = 0.0      # modelled flops of the slices not yet issued
     next_slice: int = 0
     pool_off: int = -1          # first partial slot in the device pool
     t_done: float = 0.0
@@ -156,6 +158,7 @@ class Server:
         self._steps: collections.deque = collections.deque()  # (handle, finished requests)
         self._free_pool = [(0, pool_entries)]  # free ranges (offset, length)
         self._rid = 0
+        self._flops_cache: Dict[int, float] = {}
         self._stop = False
         self._thread: Optional[threading.Thread] = None
         self.latencies: List[float] = []
@@ -175,6 +178,8 @@ class Server:
             r = Request(self._rid, m, len(m), time.perf_counter(), f)
             self._rid += 1
             r.slices = slice_plan(r.n, self.max_slice)
+            r.work = [subset_flops(r.n, lo, hi, self._haf_flops) for lo, hi in r.slices]
+            r.remaining = sum(r.work)
             if len(r.slices) > self.pool_entries:
                 self.rejected += 1
                 f.set_exception(MemoryError(f"request needs {len(r.slices)} partial slots, pool has {self.pool_entries}"))
@@ -246,8 +251,12 @@ class Server:
             self._active.append(r)
         self.max_concurrent = max(self.max_concurrent, len(self._active))
 
-    def _remaining(self, r: Request) -> float:
-        return sum(subset_flops(r.n, lo, hi, self.b.haf_flops) for lo, hi in r.slices[r.next_slice:])
+    def _haf_flops(self, n: int) -> float:
+        """The backend's flop model for size n, asked once per n."""
+        v = self._flops_cache.get(n)
+        if v is None:
+            v = self._flops_cache[n] = float(self.b.haf_flops(n))
+        return v
 
     def _build_step(self):
         """Shortest remaining work first (short requests are not held behind long ones), each request at
@@ -256,7 +265,7 @@ class Server:
         jobs, finished = [], []
         budget = self.step_flops
         cap = self.step_flops * self.share
-        order = sorted(self._active, key=lambda r: (self._remaining(r), r.rid))
+        order = sorted(self._active, key=lambda r: (r.remaining, r.rid))
         oldest = min(self._active, key=lambda r: r.rid)
         if order and order[0] is not oldest:
             order.remove(oldest)
@@ -270,17 +279,19 @@ class Server:
             used = 0.0
             while r.next_slice < len(r.slices) and (anti_starve or (budget > 0 and (used < cap or used == 0.0))):
                 lo, hi = r.slices[r.next_slice]
-                w = subset_flops(r.n, lo, hi, self.b.haf_flops)
+                w = r.work[r.next_slice]
                 jobs.append((r.modes, lo, hi, r.pool_off + r.next_slice))
                 r.next_slice += 1
+                r.remaining -= w
                 if anti_starve:
                     break  # one slice outside the budget; the budget goes by remaining work
                 budget -= w
                 used += w
             if r.next_slice == len(r.slices):
                 finished.append(r)
-        for r in finished:
-            self._active.remove(r)
+        if finished:
+            done = {id(r) for r in finished}
+            self._active = [r for r in self._active if id(r) not in done]
         return jobs, finished
 
     def _complete(self, reqs: List[Request], probs: Optional[np.ndarray], err: Optional[BaseException]):
