@@ -97,11 +97,12 @@ int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
 int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chunk_large);
 int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int64_t* chunk_large);
 
-/* Algorithmic FP64 flop count of one hafnian of size n (per-subset matrix products, trace inner
- * products and the coefficient recursion of the power-trace method as the library schedules it;
- * a complex multiply-add counts 8). A subset with 2|Z| < n/2 forms only its first 2|Z| traces and
- * extends the rest by Newton's identities, which is what is counted for it. Padding and
- * bookkeeping are not counted. */
+/* Algorithmic FP64 flop count of one hafnian of size n: the power-trace method as formulated, every
+ * pair subset Z forming all n/2 traces with the library's chain program for n/2 (matrix products,
+ * trace inner products, coefficient recursion; a complex multiply-add counts 8). The kernels do
+ * less arithmetic than this (three-product complex multiplies, only the tiles on and above the
+ * diagonal, short chains for 2|Z| < n/2), so flops/s against this count is throughput in method
+ * flops, not executed hardware work. Padding and bookkeeping are not counted. */
 double gbs_haf_flops(int32_t n);
 
 /* ---------------------------------------------------------------- hafnians */

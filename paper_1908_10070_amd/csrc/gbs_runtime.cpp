@@ -604,14 +604,8 @@ double gbs_haf_flops(int32_t n) {
   if (!T.ok) return 0.0;
   const int k = n / 2;
   double f = 0.0;
-  for (int s = 1; s <= k; ++s) {
-    // a subset with d = 2s < k forms traces 1..d and extends the rest (Newton's identities:
-    // d(d-1)/2 complex multiply-adds for the coefficients, (k-d) d for the extension)
-    const int d = 2 * s, kk = d < k ? d : k;
-    double g = flops_subset(T.host.prog[kk], k, s);
-    if (d < k) g += 8.0 * (d * (d - 1) / 2.0 + double(k - d) * d);
-    f += (double)T.host.binom[k][s] * g;
-  }
+  // the method as formulated: every subset forms all k traces with the chain program for k
+  for (int s = 1; s <= k; ++s) f += (double)T.host.binom[k][s] * flops_subset(T.host.prog[k], k, s);
   return f;
 }
 
