@@ -160,9 +160,10 @@ struct DeviceGuard {
 };
 
 void default_chunks(int n, int64_t* cs, int64_t* cl) {
-  // small-subset items: enough subsets to amortise staging; large-subset items: ~100 us of work
-  *cs = 1024;
-  *cl = n <= 32 ? 32 : (n <= 40 ? 16 : 8);
+  // small-subset items: enough subsets to amortise staging, few enough to balance the quad engine's
+  // larger grids; large-subset items: ~100 us of work (measured: n = 20 prefers 256/64, n = 24 512/64)
+  *cs = n <= 20 ? 256 : 512;
+  *cl = n <= 24 ? 64 : (n <= 32 ? 32 : (n <= 40 ? 16 : 8));
 }
 
 void chunks_for(const gbs_ctx* ctx, int n, int64_t* cs, int64_t* cl) {
