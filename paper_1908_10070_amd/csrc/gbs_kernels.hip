@@ -433,9 +433,9 @@ int upload_tables(const ConstTables& t) {
 namespace gbs {
 
 // Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
-//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= kQuadMaxS (8), k = 1..23
-//   classes 23..41  register engine (one subset per wave, one 16x16 tile), kQuadMaxS < |Z| <= 8, k = 5..23
-//                   (selected only in builds with kQuadMaxS = 6)
+//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= 6, k = 1..23
+//   classes 23..41  |Z| = 7, 8, k = 5..23: quad engine on a 4x4 tile grid (kQuadMaxS = 8, default) or
+//                   register engine (one subset per wave, one 16x16 tile; builds with kQuadMaxS = 6)
 //   classes 42..49  quad engine on a 5x5 tile grid (GBS_QUAD5, default) or strip engine with 5 tile rows
 //                   (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
 //   classes 50..55  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16
@@ -466,11 +466,14 @@ struct EngineVariant {
 
 template <int C>
 static EngineVariant variant_c() {
-  if constexpr (C >= 81) return {quad5_engine_kernel<C - 81 + 17>, kThreads, kQuadKind, 5};
-  else if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 4};
-  else if constexpr (C < 42) return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
+  if constexpr (C >= 81) return {quad_grid_kernel<C - 81 + 17, 5>, kThreads, kQuadKind, 5};
+  else if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 3};
+  else if constexpr (C < 42) {
+    if constexpr (kQuadMaxS > 6) return {quad_grid_kernel<C - 23 + 5, 4>, kThreads, kQuadKind, 4};
+    else return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
+  }
   else if constexpr (C < 50) {
-    if constexpr (kQuad5) return {quad5_engine_kernel<C - 42 + 9>, kThreads, kQuadKind, 5};
+    if constexpr (kQuad5) return {quad_grid_kernel<C - 42 + 9, 5>, kThreads, kQuadKind, 5};
     else return {strip_engine_kernel<C - 42 + 9, 5, 5>, kThreads, kStripKind, 1};
   }
   else if constexpr (C < 56) return {strip_engine_kernel<C - 50 + 11, 6, 6>, kThreads, kStripKind, 1};
@@ -490,8 +493,8 @@ static EngineVariant variant(int cls) {
 }
 
 int engine_class(int s, int k) {
-  static_assert(kQuadMaxS >= 4 && kQuadMaxS <= 8, "quad engine sizes");
-  if (s <= kQuadMaxS) return k - 1;
+  static_assert(kQuadMaxS == 6 || kQuadMaxS == 8, "quad engine sizes");
+  if (s <= 6) return k - 1;
   if (s <= 8) return 23 + (k - 5);
   if (kQuad5 && s <= 10 && k >= 17) return 81 + (k - 17);
   if (s <= 12 && k >= 17) return 56 + (k - 17);

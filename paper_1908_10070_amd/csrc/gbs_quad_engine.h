@@ -27,10 +27,12 @@ constexpr int kQuadMaxS = GBS_QUAD_MAX_S;
 #ifndef GBS_QUAD_GAUSS_KMAX
 #define GBS_QUAD_GAUSS_KMAX kMaxK
 #endif
-// up to this k the quad kernels fit two waves per SIMD without spilling
+// occupancy: the |Z| <= 6 kernels run two waves per SIMD up to k = 20 (one above, where two would
+// spill; three, with spills, measured 1% slower at n = 24); up to GBS_QUAD_WAVES2_KMAX the 4x4-grid
+// kernels run two as well (one above)
 #ifndef GBS_QUAD_WAVES2_KMAX
 #define GBS_QUAD_WAVES2_KMAX 12
-#endif  // largest |Z| on the quad engine (4x4 tiles, T4 = ceil(|Z|/2))
+#endif
 
 template <int T4>
 struct QMat {
@@ -157,9 +159,9 @@ __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
   return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
-// Traces of the 4x4-tile grid are parked in LDS (park[(j - 1) * 64 + lane]) until the chain ends
-// instead of holding k registers through every product; smaller grids keep them in registers.
-constexpr int kQuadParkT4 = 4;
+// Traces of 3x3 and larger tile grids are parked in LDS (park[(j - 1) * 64 + lane]) until the chain
+// ends instead of holding k registers through every product; smaller grids keep them in registers.
+constexpr int kQuadParkT4 = 3;
 // parking rows per wave: a kernel whose grids have at most T4 tiles per side forms min(k, 4 T4) traces
 __host__ __device__ constexpr int quad_park_k(int t4max, int k) { return k < 4 * t4max ? k : 4 * t4max; }
 
@@ -265,7 +267,8 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
   });
 }
 
-// Subsets [lo, hi) of one pattern (all with |Z| <= kQuadMaxS) on one wave, four at a time.
+// Subsets [lo, hi) of one pattern on one wave, four at a time: all with |Z| <= 6 (grids of up to
+// 3x3 tiles), or, with T4F > 0, all with |Z| = 2 T4F - 1 or 2 T4F (a T4F x T4F grid).
 template <int K, int T4F = 0>
 __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl4, double* trw, double* park,
                            int32_t* sz,
@@ -305,26 +308,22 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       const bool valid_b = b < nv;
       const int u_b = u0 + b;
       // traces formed: min(K, 2 smax), the rest follow from them (extend_traces)
-      if constexpr (T4F > 0)
-        eval_quad<K, T4F, cmin(K, 4 * T4F)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-      else if (smax <= 2)
+      if constexpr (T4F > 0) {  // a kernel for one grid size: |Z| = 2 T4F - 1 or 2 T4F
+        if (smax <= 2 * T4F - 1)
+          eval_quad<K, T4F, cmin(K, 4 * T4F - 2)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        else
+          eval_quad<K, T4F, cmin(K, 4 * T4F)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+      } else if (smax <= 2)
         eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 3)
         eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (kQuadMaxS <= 4 || smax <= 4)
         eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if constexpr (kQuadMaxS > 4) {
-        if (kQuadMaxS <= 6 || smax <= 6) {
-          if (smax <= 5)
-            eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-          else
-            eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-        } else if constexpr (kQuadMaxS > 6) {
-          if (smax <= 7)
-            eval_quad<K, 4, cmin(K, 14)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-          else
-            eval_quad<K, 4, cmin(K, 16)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-        }
+        if (smax <= 5)
+          eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        else
+          eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       }
     }
     wave_sync();
@@ -340,11 +339,12 @@ __host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A
   return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * park_k * 64;
 }
 
-// |Z| = 9, 10 (d = 18, 20) on a 5x5 grid of 4x4 tiles: 15 stored tiles per power; a kernel of its
-// own, since those registers (300 and more) would cost the smaller grids their second wave per SIMD
-template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 8))) void
-quad5_engine_kernel(EngineArgs args) {
+// |Z| = 2 T4 - 1, 2 T4 on a T4 x T4 grid of 4x4 tiles, a kernel per grid size so that each runs at the
+// occupancy its registers allow: T4 = 4 (10 stored tiles, two waves per SIMD), T4 = 5 (15 stored
+// tiles, 380-512 VGPRs and AGPRs, one wave per SIMD)
+template <int K, int T4>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(T4 >= 5 || K > GBS_QUAD_WAVES2_KMAX ? 1 : 2, 8))) void
+quad_grid_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
   wave_items<K>(args, smem, [&](const PatternView& P, int64_t lo, int64_t hi, int wave, int lane, double& sr,
@@ -353,13 +353,13 @@ quad5_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(5, K) * 64;
-    quad_range<K, 5>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
+    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(T4, K) * 64;
+    quad_range<K, T4>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
   });
 }
 
 template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= GBS_QUAD_WAVES2_KMAX ? 2 : 1, 8))) void
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 20 ? 2 : 1, 8))) void
 quad_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
@@ -369,7 +369,7 @@ quad_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(4, K) * 64;
+    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(3, K) * 64;
     quad_range<K>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
   });
 }
