@@ -212,8 +212,8 @@ def main():
     elif args.no_tune:
         chunks = ctx.get_tuning(n)
     else:
-        chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(8, 16, 32, 64), cache=None,
-                               log=tune_log)
+        chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(16, 32, 64, 128, 256),
+                               cache=None, log=tune_log)
 
     for _ in range(args.warmup):
         ctx.haf_batch(A, out=out)
