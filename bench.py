@@ -53,25 +53,59 @@ def _oracle_worker(args):
     import oracle
     mats, = args
     t0 = time.perf_counter()
-    for a in mats:
-        oracle.haf_pt(a)
-    return time.perf_counter() - t0
+    vals = [oracle.haf_pt(a) for a in mats]
+    return time.perf_counter() - t0, vals
 
 
-def cpu_baseline(A, n_per_core=12):
-    """The oracle's power-trace hafnian timed on the host cores over a bounded sample."""
+def host_info():
+    """Core count and CPU model of this host (the oracle's baseline runs here)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "host_cores": os.cpu_count() or 1, "usable_cores": usable}
+
+
+def cpu_baseline(A, n_per_core=12, max_cores=16):
+    """The oracle's power-trace hafnian (plain C, -O2, one matrix per call) timed on the host cores over
+    a bounded sample, plus a one-core rate. Returns (record, oracle values of the sample)."""
     import multiprocessing as mp
-    cores = max(1, min(16, os.cpu_count() or 1))
+    info = host_info()
+    # worker processes: all usable cores, at most max_cores (the GPU box grants 16 per GPU)
+    cores = max(1, min(max_cores, info["usable_cores"]))
     sample = A[: cores * n_per_core]
-    chunks = [(sample[i::cores],) for i in range(cores)]
+    idx = [list(range(i, len(sample), cores)) for i in range(cores)]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        pool.map(_oracle_worker, chunks)
+        res = pool.map(_oracle_worker, [(sample[ix],) for ix in idx])
     wall = time.perf_counter() - t0
-    return {"value": len(sample) / wall, "unit": "hafnians/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle haf_pt (FP64 power trace) on the first {len(sample)} of the 4096 matrices, "
-                      f"{cores} worker processes, {wall:.1f} s wall"}
+    vals = np.zeros(len(sample), dtype=np.complex128)
+    for ix, (_, v) in zip(idx, res):
+        vals[ix] = v
+    one_t, _ = _oracle_worker((A[:n_per_core],))
+    rec = {"value": len(sample) / wall, "unit": "hafnians/s", "cores": cores, "kind": "oracle",
+           "one_core_value": n_per_core / one_t,
+           "sample": f"oracle haf_pt (FP64 power trace, plain C at -O2, no SIMD or threads inside) on the first "
+                     f"{len(sample)} of the 4096 matrices, {cores} worker processes, {wall:.1f} s wall; one-core "
+                     f"rate from the first {n_per_core} on one process",
+           **info}
+    return rec, vals
+
+
+def rel_errs(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return np.abs(x - ref) / np.maximum(np.abs(ref), 1e-300)
 
 
 def _timed(fn, reps=3):
@@ -85,8 +119,55 @@ def _timed(fn, reps=3):
     return (time.perf_counter() - t0) / reps
 
 
+def _kappa_bound(n, kappa, double_ref):
+    """n^2 kappa u: the stated FP64 error bound where the subset sum cancels by kappa (doubled when the
+    reference is itself a double-precision power trace)."""
+    return n * n * kappa * 2.0 ** -53 * (2.0 if double_ref else 1.0)
+
+
+def config5_extra(gbs, torch, dev, ctx):
+    """Config 5: 64 B_S matrices of n = 36/40/44 (m = 60, r = 0.88), one gbs_prob_batch call, against the
+    stored oracle values (with kappa) of the ones that have them."""
+    import pathlib
+    from paper_1908_10070_amd import inputs
+    st_in, pats = inputs.config5()
+    st = ctx.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
+    prob = torch.empty(len(pats), dtype=torch.float64, device=dev)
+    haf = torch.empty(len(pats), dtype=torch.complex128, device=dev)
+    ctx.prob_batch(st, pats, prob_out=prob, haf_out=haf)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.prob_batch(st, pats, prob_out=prob, haf_out=haf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flops = sum(gbs.haf_flops(len(p)) for p in pats)
+    out = {"hafnians": len(pats), "seconds": dt, "hafnians_per_s": len(pats) / dt, "tflops": flops / dt / 1e12,
+           "frac_fp64_peak": flops / dt / 1e12 / FP64_PEAK_TFLOPS}
+    gold = ROOT + "/tests/golden/config5_haf.json"
+    try:
+        recs = json.loads(pathlib.Path(gold).read_text())["records"]
+    except (OSError, ValueError):
+        recs = []
+    h = haf.cpu().numpy()
+    rows = []
+    for r in recs:
+        ld = "haf_pt_ld" in r
+        ref = complex(*(r["haf_pt_ld"] if ld else r["haf_pt"]))
+        e = float(rel_errs(h[r["index"]], ref))
+        row = {"index": r["index"], "n": r["n"], "rel_err": e, "ref": "long double" if ld else "double"}
+        if "kappa" in r:
+            row["kappa"] = r["kappa"]
+            row["err_over_kappa_u"] = e / (r["kappa"] * 2.0 ** -53)
+            row["within_n2_kappa_u"] = e <= _kappa_bound(r["n"], r["kappa"], not ld)
+        rows.append(row)
+    out["vs_oracle"] = rows
+    out["max_rel_err"] = max((r["rel_err"] for r in rows), default=None)
+    return out
+
+
 def extras(gbs, torch, dev, args):
-    """Probability throughput (configs 1 and 3) and served-request latency (config 4)."""
+    """Probability throughput (configs 1, 3, 5) with oracle errors, and served-request latency (config 4)."""
+    import oracle
     from paper_1908_10070_amd import inputs, serve
 
     out = {}
@@ -97,68 +178,79 @@ def extras(gbs, torch, dev, args):
     from paper_1908_10070_amd.gbs import pack_patterns
     allp = pack_patterns([[]] + [list(p) for p in pats1])  # the vacuum and every 8-photon pattern
     t = _timed(lambda: ctx.prob_batch(st1, allp))
-    out["config1"] = {"probs_per_s": (len(pats1) + 1) / t, "ms": t * 1e3, "patterns": int(len(pats1) + 1)}
+    p1 = ctx.prob_batch(st1, allp).cpu().numpy()
+    sel = np.linspace(0, len(pats1) - 1, 64).astype(int)
+    ref1 = oracle.prob_ref_patterns(st1_in.U, st1_in.r, pats1[sel])
+    out["config1"] = {"probs_per_s": (len(pats1) + 1) / t, "ms": t * 1e3, "patterns": int(len(pats1) + 1),
+                      "max_rel_err": float(np.max(rel_errs(p1[1 + sel], ref1))), "err_sample": len(sel)}
     # config 3: m = 50, r = 0.88, 100,000 twenty-photon patterns
     st3_in, pats3 = inputs.config3()
     st3 = ctx.state(torch.from_numpy(st3_in.U).to(dev), st3_in.r)
     prob = torch.empty(len(pats3), dtype=torch.float64, device=dev)
     t = _timed(lambda: ctx.prob_batch(st3, pats3, prob_out=prob))
     f20 = gbs.haf_flops(20)
+    sel = np.linspace(0, len(pats3) - 1, 48).astype(int)
+    ref3 = oracle.prob_ref_patterns(st3_in.U, st3_in.r, pats3[sel])
     out["config3"] = {"probs_per_s": len(pats3) / t, "ms": t * 1e3, "patterns": int(len(pats3)),
-                      "tflops": f20 * len(pats3) / t / 1e12, "frac_fp64_peak": f20 * len(pats3) / t / 1e12 / FP64_PEAK_TFLOPS}
+                      "tflops": f20 * len(pats3) / t / 1e12, "frac_fp64_peak": f20 * len(pats3) / t / 1e12 / FP64_PEAK_TFLOPS,
+                      "max_rel_err": float(np.max(rel_errs(prob.cpu().numpy()[sel], ref3))), "err_sample": len(sel)}
+    if not args.no_config5:
+        out["config5"] = config5_extra(gbs, torch, dev, ctx)
     # config 4: served mixed stream on the config-3 state
-    nreq = args.serve_requests
-    warm = max(nreq // 10, 50)
+    nreq, warm = args.serve_requests, args.serve_warmup
     mix_rng = np.random.default_rng(3004)
     mix = [inputs.collision_free_patterns(50, int(2 * mix_rng.integers(4, 17)), 1, mix_rng)[0] for _ in range(2000)]
     t = _timed(lambda: ctx.prob_batch(st3, mix), reps=2)
     capacity = len(mix) / t
-    srv_out = {"batched_capacity_req_s": capacity}
-    for load in (0.5,):
+    srv_out = {"batched_capacity_req_s": capacity,
+               "note": "capacity = 2000 mixed requests in one gbs_prob_batch call; latency = arrival to result on "
+                       "the host; statistics over the requests after the warm-up ones"}
+    for load in args.serve_loads:
         rate = load * capacity
         arr, pats = inputs.config4_requests(nreq + warm, rate)
         # every step has a new shape, so the server's context captures no graphs (nothing to replay)
         sctx = gbs.Context(0, use_graph=False)
         be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16)
-        # steps of 8e11 modelled flops (about 10-15 ms of GPU work): larger steps run the stream at a
-        # higher rate than 2e11 (measured p99 62 vs 150 ms at this load)
-        cont = serve.Server(be, pool_entries=1 << 16, step_flops=8e11, max_slice=4096).start()
+        cont = serve.Server(be, pool_entries=1 << 16, step_flops=args.step_flops, max_slice=4096).start()
         serve.replay(cont, arr, pats)
-        cont.stop()
-        lat_c = np.array(cont.latencies[warm:]) * 1e3
-        pp = gbs.Context(0, use_graph=False, persistent=False)
-        fifo = serve.FifoServer(pp, st3).start()
-        serve.replay(fifo, arr, pats)
-        fifo.stop(timeout=600)
-        lat_f = np.array(fifo.latencies[warm:]) * 1e3
-        srv_out[f"load_{load}"] = {
-            "arrival_rate_req_s": rate, "requests": nreq, "warmup_requests": warm,
-            "continuous": {"p50_ms": float(np.percentile(lat_c, 50)), "p99_ms": float(np.percentile(lat_c, 99)),
-                           "mean_ms": float(lat_c.mean()), "throughput_req_s": cont.stats()["throughput_req_s"],
-                           "steps": cont.steps},
-            "fifo_per_pattern": {"p50_ms": float(np.percentile(lat_f, 50)), "p99_ms": float(np.percentile(lat_f, 99)),
-                                 "mean_ms": float(lat_f.mean()), "throughput_req_s": fifo.stats()["throughput_req_s"]},
-        }
+        cont.stop(timeout=600)
+        lat_c = np.array(cont.latencies_by_rid(warm)) * 1e3
+        span_c = cont.span(warm)
+        res = {"arrival_rate_req_s": rate, "requests": nreq, "warmup_requests": warm,
+               "continuous": {"p50_ms": float(np.percentile(lat_c, 50)), "p99_ms": float(np.percentile(lat_c, 99)),
+                              "mean_ms": float(lat_c.mean()), "throughput_req_s": nreq / span_c,
+                              "steps": cont.steps}}
+        if not args.no_fifo:
+            pp = gbs.Context(0, use_graph=False, persistent=False)
+            fifo = serve.FifoServer(pp, st3).start()
+            serve.replay(fifo, arr, pats)
+            fifo.stop(timeout=900)
+            lat_f = np.array(fifo.latencies_by_rid(warm)) * 1e3
+            res["fifo_per_pattern"] = {"p50_ms": float(np.percentile(lat_f, 50)),
+                                       "p99_ms": float(np.percentile(lat_f, 99)), "mean_ms": float(lat_f.mean()),
+                                       "throughput_req_s": nreq / fifo.span(warm)}
+        srv_out[f"load_{load}"] = res
     out["config4_serving"] = srv_out
-    # chain-rule sampler (Theorem-1 marginals) at the paper's mode count m = n^2, r = 0.88
-    from paper_1908_10070_amd import sampler
-    smp_out = {}
-    for n_ph, count in ((12, 8), (16, 2), (18, 1)):
-        m_s = n_ph * n_ph
-        U_s = inputs.haar_unitary(m_s, np.random.default_rng(4000 + n_ph))
-        st_s = ctx.state(torch.from_numpy(U_s).to(dev), np.full(m_s, 0.88))
-        smp = sampler.Sampler(ctx, st_s, m_s, 0.88)
-        srng = np.random.default_rng(5)
-        smp.positions(min(n_ph, 8), 1, srng)  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        smp.positions(n_ph, count, srng)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        smp_out[f"n{n_ph}_m{m_s}"] = {"seconds_per_sample": dt / count, "samples": count}
-    smp_out["context"] = ("paper (CPU, other hardware): 18 photons about 20 h on a laptop; 20 photons about "
-                          "36 h on a 256-core server")
-    out["sampler"] = smp_out
+    if not args.no_sampler:
+        # chain-rule sampler (Theorem-1 marginals) at the paper's mode count m = n^2, r = 0.88
+        from paper_1908_10070_amd import sampler
+        smp_out = {}
+        for n_ph, count in ((12, 8), (16, 2), (18, 1)):
+            m_s = n_ph * n_ph
+            U_s = inputs.haar_unitary(m_s, np.random.default_rng(4000 + n_ph))
+            st_s = ctx.state(torch.from_numpy(U_s).to(dev), np.full(m_s, 0.88))
+            smp = sampler.Sampler(ctx, st_s, m_s, 0.88)
+            srng = np.random.default_rng(5)
+            smp.positions(min(n_ph, 8), 1, srng)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            smp.positions(n_ph, count, srng)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            smp_out[f"n{n_ph}_m{m_s}"] = {"seconds_per_sample": dt / count, "samples": count}
+        smp_out["context"] = ("paper (CPU, other hardware): 18 photons about 20 h on a laptop; 20 photons about "
+                              "36 h on a 256-core server")
+        out["sampler"] = smp_out
     return out
 
 
@@ -170,7 +262,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-pattern", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the probability and serving measurements")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-warmup", type=int, default=1000)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8],
+                    help="arrival rates as fractions of the measured batched capacity")
+    ap.add_argument("--step-flops", type=float, default=8e11, help="modelled work per server step")
+    ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO per-pattern server")
+    ap.add_argument("--no-config5", action="store_true")
+    ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in chunk sizes")
     ap.add_argument("--chunks", type=str, default="",
                     help="fixed chunk sizes 'small,large' instead of tuning (profiling runs)")
@@ -185,8 +284,9 @@ def main():
 
     n, batch = 24, 4096
     A_host = inputs.config2(batch=batch, n=n)
-    # The CPU leg runs first, in worker processes forked before anything touches the GPU.
-    cpu = None if args.no_cpu else cpu_baseline(A_host)
+    # The CPU leg runs first, in worker processes forked before anything touches the GPU; its oracle
+    # values of the sampled matrices also check the timed run's output.
+    cpu, cpu_vals = (None, None) if args.no_cpu else cpu_baseline(A_host)
 
     import torch
     from paper_1908_10070_amd import gbs
@@ -239,6 +339,13 @@ def main():
     kern_ms = float(np.mean(gpu_ms))
     achieved = flops_per_haf * batch / (kern_ms * 1e-3) / 1e12
 
+    # error of the timed run's output against the oracle (the CPU leg's sample; else a small one)
+    h_timed = out.cpu().numpy()
+    if cpu_vals is None:
+        import oracle
+        cpu_vals = np.array([oracle.haf_pt(a) for a in A_host[:16]])
+    errs = rel_errs(h_timed[: len(cpu_vals)], cpu_vals)
+
     res = {
         "metric": METRIC, "value": value, "unit": "hafnians/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -246,6 +353,9 @@ def main():
         "config": {"workload": "config2: 4096 random complex-symmetric 24x24 matrices (seed 1002), haf_batch, "
                                "persistent launch replayed from a HIP graph", "n": n, "batch": batch,
                    "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1])},
+        "max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),
+        "err_sample": f"timed run's output of the first {len(cpu_vals)} matrices vs the oracle's haf_pt (FP64 power "
+                      f"trace); the stated tolerance is 1e-9",
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms,

@@ -60,22 +60,30 @@ enum {
   GBS_OK = 0,
   GBS_EINVAL = 1,        /* null pointer, negative size, malformed offsets */
   GBS_ERANGE = 2,        /* a mode outside [0, m), n > GBS_N_MAX, subset range outside [0, 2^(n/2)-1] */
-  GBS_ENOMEM = 3,        /* caller workspace too small for the plan, or device allocation failed */
+  GBS_ENOMEM = 3,        /* caller workspace or state memory too small (see gbs_ctx_workspace_needed) */
   GBS_EHIP = 4,          /* a HIP runtime call failed; gbs_last_error() has the text */
   GBS_EUNSUPPORTED = 5   /* device is not gfx950 */
 };
 
 /* ---------------------------------------------------------------- context */
 
-/* Create a context on `device`.
- * workspace_dev/workspace_bytes: optional caller-owned device buffer the library carves its
- *   scratch (plan, staged patterns, partial sums, counters) from. Pass NULL/0 to let the
- *   library allocate (and grow) its own device workspace. With a caller buffer, calls whose
- *   plan does not fit return GBS_ENOMEM and enqueue nothing.
- * The context also holds pinned host staging buffers, the per-size chain programs, the
- * launch-shape table (see gbs_ctx_set_tuning) and cached HIP graphs. */
+/* Device memory. The library never allocates device memory: the caller owns every device buffer
+ * (in the Python binding, PyTorch tensors), including each context's workspace and each state's
+ * memory. Host-side, a context holds pinned staging buffers, the launch-shape table and cached HIP
+ * graphs.
+ *
+ * Create a context on `device`. workspace_dev/workspace_bytes: the caller-owned device buffer the
+ * library carves each call's scratch from (staged plan and patterns, work counters, partial sums,
+ * marginal tables). It may be NULL/0 at creation. A call whose plan does not fit returns GBS_ENOMEM,
+ * enqueues nothing, and records the size it needed (gbs_ctx_workspace_needed); the caller then
+ * installs a larger buffer with gbs_ctx_set_workspace and repeats the call. */
 int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_ctx** out);
 int gbs_ctx_destroy(gbs_ctx* ctx);
+/* Replace the workspace. Waits until the work this context has enqueued is done (the old buffer
+ * may be released afterwards) and drops the cached graphs, which refer to the old buffer. */
+int gbs_ctx_set_workspace(gbs_ctx* ctx, void* workspace_dev, size_t workspace_bytes);
+/* Bytes the last call that returned GBS_ENOMEM on this context needed (0 if none did). */
+size_t gbs_ctx_workspace_needed(const gbs_ctx* ctx);
 
 /* Static description of a status code. */
 const char* gbs_status_str(int status);
@@ -120,13 +128,20 @@ int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_of
 
 /* ------------------------------------------------------------ GBS state */
 
+/* Device bytes a state on m modes needs (B and W, m*m complex128 each, the m squeezing values and
+ * the prefactor, 256-byte aligned); 0 for m outside [1, 4096]. */
+size_t gbs_state_bytes(int32_t m);
 /* Build a resident GBS state from an m x m unitary U (device, row-major complex128) and per-mode
- * squeezing parameters r (host, m doubles). A kernel forms B = U diag(tanh r_i) U^t and the
- * prefactor 1 / prod_i cosh r_i on the device (Sec. II C: W = U U^t; Eq. ProOri). The state owns
- * its device copy of B (m*m complex128) and of U; `U_dev` may be freed once the stream is synced.
- * The state is bound to the context's device and may be used with any context on that device. */
+ * squeezing parameters r (host, m doubles). A kernel forms B = U diag(tanh r_i) U^t, W = U U^t
+ * (the marginal probabilities' matrix) and the prefactor 1 / prod_i cosh r_i on the device
+ * (Sec. II C: W = U U^t; Eq. ProOri) in state_mem_dev, caller-owned device memory of at least
+ * gbs_state_bytes(m) bytes that must stay allocated until gbs_state_destroy. U_dev is read only by
+ * that kernel: it may be freed once the stream has reached it. The state is bound to the context's
+ * device and may be used with any context on that device. Errors: GBS_EINVAL for null pointers or
+ * non-finite r, GBS_ERANGE for m outside [1, 4096], GBS_ENOMEM if state_mem_bytes is too small. */
 int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const double* r_host,
-                     void* stream, gbs_state** out);
+                     void* state_mem_dev, size_t state_mem_bytes, void* stream, gbs_state** out);
+/* Waits for the state's setup, then releases the host object (not state_mem_dev). */
 int gbs_state_destroy(gbs_state* state);
 /* Device pointer to the state's B (m x m row-major complex128), and m / the prefactor (host copy,
  * valid after the creating stream has been synced). */
@@ -164,12 +179,15 @@ int gbs_prob_slices(gbs_ctx* ctx, const gbs_state* state, const int32_t* modes_h
 
 /* Combine partials: pattern b's partials are partials_dev[part_lo_host[b] .. part_hi_host[b]),
  * summed in that order with compensation (ranges may be anywhere in partials_dev and may differ in
- * length). n_host[b] is its photon number, sfact_host[b] its prod_j s_j!.
- * haf_out_dev[b] = sum (1 for n = 0, 0 for odd n); prob_out_dev[b] = prefactor |haf|^2 / sfact
- * (prefactor from `state`). Either output may be NULL; prob_out_dev needs a state and sfact_host. */
+ * length). Pattern b is the mode list modes_host[offsets_host[b] .. offsets_host[b+1]) as in
+ * gbs_prob_batch: its length is the photon number n, and the library derives prod_j s_j! from its
+ * repeated modes (Eq. ProOri). haf_out_dev[b] = sum (1 for n = 0, 0 for odd n);
+ * prob_out_dev[b] = prefactor |haf|^2 / prod_j s_j! (prefactor from `state`). Either output may be
+ * NULL; prob_out_dev needs a state, and then modes must lie in [0, m) (GBS_ERANGE otherwise).
+ * modes_host may be NULL when every pattern is empty. Nothing is enqueued on a validation failure. */
 int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partials_dev,
-                 const int64_t* part_lo_host, const int64_t* part_hi_host, const int32_t* n_host,
-                 const double* sfact_host, int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev,
+                 const int64_t* part_lo_host, const int64_t* part_hi_host, const int32_t* modes_host,
+                 const int64_t* offsets_host, int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev,
                  void* stream);
 
 /* ------------------------------------------- marginal probabilities (sequential sampling) */
@@ -184,7 +202,8 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partia
  * all completions:
  *   q_out_dev[b] = q_n(x_1..x_k),  x = modes_host[offsets_host[b] .. offsets_host[b+1]),  k <= n.
  * Evaluated with Theorem 1 (B ranging over mu-subsets of X_k minus a'), regrouped: the hafnians of
- * W over all 2^(k-1) even-size position subsets of the prefix run on the subset engines, then for
+ * W over all 2^(k-1) even-size position subsets of the prefix are built size by size from the
+ * matching sum expanded along the lowest position (Eq. HafMatch; O(k 2^k) work), then for
  * every set A of positions the sums over the 2j-subsets a of the other positions of
  * Haf(W_a) Haf(W_{rest}) are combined with the weights F and Per(S_{A,B}) (A, B with equal mode
  * multisets) on the device; about 3^k / 2 products per prefix.

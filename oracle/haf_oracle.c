@@ -31,6 +31,7 @@
  * (complex-)symmetric input. Odd n gives 0, n = 0 gives 1.
  */
 #include <complex.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -104,13 +105,24 @@ int orc_haf_enum_batch(const double* A_ri, int n, long batch, double* out_ri) {
 
 /* ---------------------------------------------------------- power trace --- */
 
-/* One definition, instantiated for double and long double. */
-#define DEFINE_HAF_PT(NAME, REAL, CPLX)                                          \
+/* One definition, instantiated for double and long double. NAME_kappa also returns
+   sum_Z |(-1)^(k-|Z|) c_k(X A_Z)| (the sum of the subset terms' magnitudes, so that
+   kappa = that sum / |Haf| measures the cancellation in the subset sum) in *absum. */
+#define DEFINE_HAF_PT(NAME, REAL, CPLX, CABS)                                    \
+  int NAME##_kappa(const double* A_ri, int n, double* out_ri, double* absum);   \
   int NAME(const double* A_ri, int n, double* out_ri) {                         \
+    return NAME##_kappa(A_ri, n, out_ri, NULL);                                 \
+  }                                                                             \
+  int NAME##_kappa(const double* A_ri, int n, double* out_ri, double* absum) {  \
+    if (absum) *absum = 0.0;                                                    \
     if (n < 0 || n > 64) return 1;                                              \
     if (n % 2) { out_ri[0] = 0.0; out_ri[1] = 0.0; return 0; }                  \
     int k = n / 2;                                                              \
-    if (k == 0) { out_ri[0] = 1.0; out_ri[1] = 0.0; return 0; }                 \
+    if (k == 0) {                                                               \
+      out_ri[0] = 1.0; out_ri[1] = 0.0;                                         \
+      if (absum) *absum = 1.0;                                                  \
+      return 0;                                                                 \
+    }                                                                           \
     if (k > 40) return 1;                                                       \
     CPLX* A = (CPLX*)malloc(sizeof(CPLX) * n * n);                              \
     CPLX* M = (CPLX*)malloc(sizeof(CPLX) * n * n);                              \
@@ -126,6 +138,7 @@ int orc_haf_enum_batch(const double* A_ri, int n, long batch, double* out_ri) {
     for (int i = 0; i < n * n; ++i)                                             \
       A[i] = (REAL)A_ri[2 * i] + (REAL)A_ri[2 * i + 1] * (CPLX)I;               \
     CPLX total = 0;                                                             \
+    REAL mag = 0;                                                               \
     for (uint64_t Z = 1; Z < (1ull << k); ++Z) {                                \
       int d = 0;                                                                \
       for (int i = 0; i < k; ++i)                                               \
@@ -158,15 +171,17 @@ int orc_haf_enum_batch(const double* A_ri, int n, long batch, double* out_ri) {
         c[q] = acc / (REAL)q;                                                   \
       }                                                                         \
       if ((k - s) % 2) total -= c[k]; else total += c[k];                       \
+      mag += CABS(c[k]);                                                        \
     }                                                                           \
     out_ri[0] = (double)creall(total);                                          \
     out_ri[1] = (double)cimagl(total);                                          \
+    if (absum) *absum = (double)mag;                                            \
     free(A); free(M); free(P); free(Q); free(t); free(c); free(idx);            \
     return 0;                                                                   \
   }
 
-DEFINE_HAF_PT(orc_haf_pt, double, cplx)
-DEFINE_HAF_PT(orc_haf_pt_ld, long double, lcplx)
+DEFINE_HAF_PT(orc_haf_pt, double, cplx, cabs)
+DEFINE_HAF_PT(orc_haf_pt_ld, long double, lcplx, cabsl)
 
 int orc_haf_pt_batch(const double* A_ri, int n, long batch, double* out_ri) {
   for (long b = 0; b < batch; ++b) {

@@ -48,6 +48,10 @@ def _lib():
             f = getattr(lib, name)
             f.argtypes = [dp, ctypes.c_int, ctypes.c_long, dp]
             f.restype = ctypes.c_int
+        for name in ("orc_haf_pt_kappa", "orc_haf_pt_ld_kappa"):
+            f = getattr(lib, name)
+            f.argtypes = [dp, ctypes.c_int, dp, dp]
+            f.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -105,6 +109,31 @@ def haf_pt(A) -> complex:
 def haf_pt_ld(A) -> complex:
     """Power-trace formula evaluated in long double (64-bit mantissa)."""
     return _call_single("orc_haf_pt_ld", A)
+
+
+def _call_kappa(fname: str, A):
+    A = _as_c128(A)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("square matrix expected")
+    out = np.zeros(2, dtype=np.float64)
+    mag = np.zeros(1, dtype=np.float64)
+    rc = getattr(_lib(), fname)(_ptr(A), n, _ptr(out), _ptr(mag))
+    if rc:
+        raise RuntimeError(f"{fname} failed with code {rc} (n={n})")
+    h = complex(out[0], out[1])
+    return h, float(mag[0]) / abs(h) if h != 0 else float("inf")
+
+
+def haf_pt_kappa(A):
+    """(Haf, kappa) by the power-trace formula in double: kappa = sum_Z |term(Z)| / |Haf|, the
+    cancellation of the subset sum, which sets the size of the rounding error of any FP64 evaluation."""
+    return _call_kappa("orc_haf_pt_kappa", A)
+
+
+def haf_pt_ld_kappa(A):
+    """(Haf, kappa) as haf_pt_kappa, evaluated in long double."""
+    return _call_kappa("orc_haf_pt_ld_kappa", A)
 
 
 def haf_pt_batch(As) -> np.ndarray:
@@ -263,6 +292,7 @@ def multisets(m: int, n: int):
 
 __all__ = [
     "haf_enum", "haf_enum_batch", "haf_pt", "haf_pt_ld", "haf_pt_batch", "haf_pt_ld_batch", "haf_py",
+    "haf_pt_kappa", "haf_pt_ld_kappa",
     "state_B", "occupation", "pattern_matrix", "W_s_paper", "prob_paper", "prob_ref",
     "haf_ref_patterns", "prob_ref_patterns", "gbinom", "smss_prob", "photon_number_prob", "f_n",
     "multisets",

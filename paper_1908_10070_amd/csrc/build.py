@@ -8,6 +8,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = pathlib.Path(__file__).resolve().parent
 PKG = HERE.parent
@@ -15,9 +16,11 @@ ROOT = PKG.parent
 INCLUDE = ROOT / "include"
 OUT = PKG / "libgbs.so"
 
-SOURCES = ["gbs_kernels.hip", "gbs_runtime.cpp"]
-HEADERS = ["gbs_internal.h", "gbs_wave_engine.h", "gbs_quad_engine.h", "gbs_tile_engine.h", "gbs_qtile_engine.h",
-           "gbs_strip_engine.h", "gbs_chain_table.h"]
+# the engine kernels are split over several translation units so that they compile in parallel
+SOURCES = ["gbs_eng_grid5.hip", "gbs_eng_grid4.hip", "gbs_eng_quad.hip", "gbs_eng_tile.hip", "gbs_eng_strip.hip",
+           "gbs_kernels.hip", "gbs_runtime.cpp"]
+HEADERS = ["gbs_internal.h", "gbs_tables.h", "gbs_engine_common.h", "gbs_quad_engine.h", "gbs_tile_engine.h",
+           "gbs_qtile_engine.h", "gbs_strip_engine.h", "gbs_chain_table.h"]
 
 ARCH = "gfx950"
 COMMON = [
@@ -51,14 +54,20 @@ def build(force: bool = True, verbose: bool = False, out: pathlib.Path = None, d
     if not force and out == OUT and not _stale():
         return OUT
     with tempfile.TemporaryDirectory(prefix="gbs_build_") as td:
-        objs = []
-        for src in SOURCES:
+        def compile_one(src):
             obj = pathlib.Path(td) / (src + ".o")
             lang = ["-x", "hip"] if src.endswith(".hip") else []
             cmd = [hipcc(), *COMMON, *["-D" + d for d in defines], *lang, "-c", str(HERE / src), "-o", str(obj)]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)
+            return src, obj, r
+
+        jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as pool:
+            results = list(pool.map(compile_one, SOURCES))
+        objs = []
+        for src, obj, r in results:
             if r.returncode != 0:
                 sys.stderr.write(r.stdout + r.stderr)
                 raise RuntimeError(f"hipcc failed on {src}")

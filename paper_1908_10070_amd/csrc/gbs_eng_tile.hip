@@ -1,0 +1,42 @@
+// Subset-engine kernels for the largest subsets: quad-tile engine for |Z| = 11, 12 at k = 17..23
+// (classes kClsQtile + k - 17), tile engine with 2x2 16x16 tiles for |Z| = 13..16 at k = 13..23
+// (kClsTile2 + k - 13) and with 3x3 tiles for |Z| >= 17 at k = 17..23 (kClsTile3 + k - 17).
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "gbs_engine_common.h"
+#include "gbs_quad_engine.h"
+#include "gbs_qtile_engine.h"
+#include "gbs_tile_engine.h"
+
+namespace gbs {
+
+template <int... I>
+static void fill_qtile(EngineVariant* tab, std::integer_sequence<int, I...>) {
+  ((tab[kClsQtile + I] = EngineVariant{reinterpret_cast<const void*>(&qtile_engine_kernel<I + 17>), kThreads,
+                                       kQtileKind, 1}),
+   ...);
+}
+
+template <int... I>
+static void fill_tile2(EngineVariant* tab, std::integer_sequence<int, I...>) {
+  ((tab[kClsTile2 + I] = EngineVariant{reinterpret_cast<const void*>(&tile_engine_kernel<2, I + 13>), 256,
+                                       kTileKind, 2}),
+   ...);
+}
+
+template <int... I>
+static void fill_tile3(EngineVariant* tab, std::integer_sequence<int, I...>) {
+  ((tab[kClsTile3 + I] = EngineVariant{reinterpret_cast<const void*>(&tile_engine_kernel<3, I + 17>), 576,
+                                       kTileKind, 3}),
+   ...);
+}
+
+void register_tile_engines(EngineVariant* tab) {
+  fill_qtile(tab, std::make_integer_sequence<int, 7>{});
+  fill_tile2(tab, std::make_integer_sequence<int, 11>{});
+  fill_tile3(tab, std::make_integer_sequence<int, 7>{});
+}
+
+}  // namespace gbs

@@ -1,38 +1,48 @@
-// Register-resident subset engine for subsets with d = 2|Z| <= 32 (gfx950).
+// Pieces shared by the subset engines (gfx950): tile layouts of the 16x16x4 FP64 MFMA, lane
+// exchanges, the wave reduction of per-lane trace partials, the gather of M_Z from the staged pattern
+// matrix, subset enumeration, the trace extension by Newton's identities, the coefficient recursion
+// with compensated summation, and the persistent item loop of the engines that give each wave its
+// own subsets.
 //
-// One wave evaluates one subset at a time with no workgroup barriers:
-//   * M_Z = X A_Z is gathered straight into MFMA accumulator layout: a d x d complex matrix is a
-//     T x T grid (T = 1 or 2) of 16x16 FP64 tiles, each tile a pair (re, im) of 4-double registers;
-//     lane l = x + 16 y, register r of a tile holds element (row y + 4 r, column x) -- the output
-//     layout of v_mfma_f64_16x16x4f64. Entries beyond d are zero.
-//   * Every power Q of M_Z satisfies Q^t = X Q X (X swaps the two indices of each pair, and A_Z is
-//     symmetric). So Q[i][c] = Q[c^1][i^1], and the A operand of a product -- which needs Q by rows
-//     where the accumulator layout holds it by columns -- is the same register of the transposed
-//     tile read from lane l ^ 17 (x^1, y^1). The B operand is the accumulator register itself.
-//     A 16x16 complex product is then 4 register steps x 4 MFMAs with no LDS traffic.
-//   * tr(P Q) = sum_{i,c} P[i][c] Q[i^1][c^1] is, per lane, the product of P with Q read from lane
-//     l ^ 17. Each trace's per-lane partial is folded over lane bit 5 (v_permlane32_swap, real part
-//     kept in the low half, imaginary in the high half) as soon as it is formed; the k folded traces
-//     are then reduced together by a transposed butterfly on permlane16 swaps and DPP row moves,
-//     with no LDS traffic.
-//   * The schedule (which powers, which traces) is the compile-time chain table for k, so slots and
-//     traces are plain registers.
-// A workgroup (4 waves) takes one work item -- a range of one pattern's canonical subset order --
-// stages the pattern matrix in LDS once (n <= 32), and gives each wave a contiguous quarter. Traces
-// of 32 subsets are buffered per wave; 32 lanes then run the coefficient recursion and one lane adds
-// the signed terms into a compensated running sum. The four wave partials are combined in wave
-// order, so an item's partial depends only on its range.
+// Conventions used by every engine:
+//   * A d x d complex matrix in the v_mfma_f64_16x16x4f64 layout is a grid of 16x16 FP64 tiles, each
+//     a pair (re, im) of 4-double registers; lane l = x + 16 y, register r of a tile holds element
+//     (row y + 4 r, column x). Entries beyond d are zero.
+//   * Every power Q of M_Z = X A_Z satisfies Q^t = X Q X (X swaps the two indices of each pair, and
+//     A_Z is symmetric), so Q[i][c] = Q[c^1][i^1]: the A operand of a product -- Q by rows where the
+//     output layout holds it by columns -- is the same register of the transposed tile read from
+//     lane l ^ 17 (x^1, y^1), and tr(P Q) = sum_{i,c} P[i][c] Q[i^1][c^1] pairs each register of P
+//     with the same register of Q at lane l ^ 17.
+//   * Each trace's per-lane partial is folded over lane bit 5 (v_permlane32_swap, real part kept in
+//     the low half, imaginary in the high half) as soon as it is formed; the folded traces are then
+//     reduced together by a transposed butterfly on permlane16 swaps and DPP row moves.
+//   * A workgroup of 4 waves takes one work item -- a range of one pattern's canonical subset order
+//     -- stages the pattern matrix in LDS once (n <= 32) and gives each wave a contiguous quarter.
+//     Traces of 32 subsets are buffered per wave; 32 lanes then run the coefficient recursion and one
+//     lane adds the signed terms into a compensated running sum. The four wave partials are combined
+//     in wave order, so an item's partial depends only on its range.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "gbs_chain_table.h"
 #include "gbs_internal.h"
+#include "gbs_tables.h"
 
 namespace gbs {
 
 namespace {
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// s + c += x with Neumaier's compensation (per component, fixed order).
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+  double t = s + x;
+  if (fabs(s) >= fabs(x))
+    c += (s - t) + x;
+  else
+    c += (x - t) + s;
+  s = t;
+}
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -227,25 +237,6 @@ __device__ __forceinline__ double fold_row(double x, double y, bool bit) {
   return keep + dpp<CTRL>(send);
 }
 
-// Run the chain program for k on the slots; trace t_j's per-lane partial is folded over lane
-// bit 5 into w[j - 1] as soon as it is formed (real part in lanes 0..31, imaginary in 32..63).
-template <int K, int T, int OI, int NS>
-__device__ __forceinline__ void run_ops(CMat<T> (&S)[NS], double (&w)[K], int d, int lane) {
-  if constexpr (OI < kChainTable[K].nops) {
-    constexpr Op op = kChainTable[K].ops[OI];
-    if constexpr (op.type == OP_MUL) {
-      cmul_mat<T, (K <= GBS_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], d);
-    } else if constexpr (op.type == OP_TDIAG) {
-      const double2 p = tdiag<T>(S[op.a], lane);
-      w[op.x - 1] = fold32(p.x, p.y);
-    } else {
-      const double2 p = tpair<T>(S[op.a], S[op.b]);
-      w[op.x - 1] = fold32(p.x, p.y);
-    }
-    run_ops<K, T, OI + 1, NS>(S, w, d, lane);
-  }
-}
-
 // Rest of the wave reduction of the folded traces: transposed over lane bits 4 and 3, plain over
 // bits 2..0. Afterwards the lanes with (lane & 7) == 0 call store(j, part, total) for their share
 // of the (trace, real/imaginary part) pairs.
@@ -307,64 +298,19 @@ __device__ __forceinline__ double2 mz_at(const PatternView& P, int off) {
   return make_double2(Al[2 * off], Al[2 * off + 1]);
 }
 
-// One subset: build M_Z, run the chain program for the first KK traces (KK >= d or KK = K; the
-// combine step extends the rest), reduce them into the wave's buffer slot u.
-template <int K, int T, int KK = K>
-__device__ __forceinline__ void eval_subset(const PatternView& P, const int32_t* pl, int d, double* trw, int u,
-                                            int lane) {
-  static_assert(KK <= K, "trace count");
-  constexpr int NS = kChainTable[KK].nslots;
-  CMat<T> S[NS];
-  const int x = lane & 15, y = lane >> 4;
-  if (T == 1 && P.lds) {
-    // staged copy with a zero row and column at index n: padded entries read a zero, no branches
-    const int cix = mz_col(P, pl, x, d);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double2 e = mz_at(P, mz_row(P, pl, y + 4 * r, d) + cix);
-      S[0].r[0][0][r] = e.x;
-      S[0].i[0][0][r] = e.y;
-    }
-  } else {
-#pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-      for (int J = 0; J < T; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int a = 16 * I + y + 4 * r;  // row of M_Z
-          const int c = 16 * J + x;          // column
-          double vr = 0.0, vi = 0.0;
-          if (a < d && c < d) {
-            const int b = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
-            const int ia = 2 * pl[b >> 1] + (b & 1);
-            const int ic = 2 * pl[c >> 1] + (c & 1);
-            const double2 e = P.at(ia, ic);
-            vr = e.x;
-            vi = e.y;
-          }
-          S[0].r[I][J][r] = vr;
-          S[0].i[I][J][r] = vi;
-        }
-  }
-  double w[KK];
-  run_ops<KK, T, 0, NS>(S, w, d, lane);
-  reduce_folded<KK>(w, lane, [&](int j, int part, double v) { trw[j * (2 * kWaveG) + 2 * u + part] = 0.5 * v; });
-}
-
 __device__ __forceinline__ uint32_t unrank(int k, int64_t g, int* s_out) {
   int s = 1;
   uint64_t rem = (uint64_t)g;
-  while (s < k && rem >= c_tab.binom[k][s]) {
-    rem -= c_tab.binom[k][s];
+  while (s < k && rem >= kBinom.v[k][s]) {
+    rem -= kBinom.v[k][s];
     ++s;
   }
   uint32_t mask = 0;
   int c = k - 1;
   for (int i = s; i >= 1; --i) {
-    while (c_tab.binom[c][i] > rem) --c;
+    while (kBinom.v[c][i] > rem) --c;
     mask |= 1u << c;
-    rem -= c_tab.binom[c][i];
+    rem -= kBinom.v[c][i];
     --c;
   }
   *s_out = s;
@@ -454,7 +400,7 @@ __device__ __forceinline__ void combine_batch(double* trw, const int32_t* sz, do
         ai = fma(tr, c[q - j].y, ai);
         ai = fma(ti, c[q - j].x, ai);
       }
-      const double iq = c_tab.inv[q];
+      const double iq = kInv.v[q];
       c[q] = make_double2(ar * iq, ai * iq);
     }
     double2 ck = c[K];
@@ -479,33 +425,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// The subsets [lo, hi) of one pattern, all with the same tile count T, on one wave.
-template <int K, int T>
-__device__ void wave_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double* trw, int32_t* sz,
-                           double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
-  int s = 1;
-  uint32_t mask = lo < hi ? unrank(K, lo, &s) : 0u;
-  for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
-    const int cnt = (int)((hi - g0) < kWaveG ? (hi - g0) : kWaveG);
-    for (int u = 0; u < cnt; ++u) {
-      if (u > 0 || g0 > lo) mask = next_subset(mask, K, &s);
-      wave_sync();  // previous subset's pair list no longer read
-      if (lane < K && ((mask >> lane) & 1u)) pl[__popc(mask & ((1u << lane) - 1u))] = lane;
-      if (lane == 0) sz[u] = s;
-      wave_sync();
-      if (T == 1 && s == 7 && 14 < K)
-        eval_subset<K, T, cmin(K, 14)>(P, pl, 2 * s, trw, u, lane);
-      else if (T == 1 && s == 8 && 16 < K)
-        eval_subset<K, T, cmin(K, 16)>(P, pl, 2 * s, trw, u, lane);
-      else
-        eval_subset<K, T>(P, pl, 2 * s, trw, u, lane);
-    }
-    wave_sync();
-    combine_batch<K, (K > 14)>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
-    wave_sync();
-  }
 }
 
 }  // namespace
@@ -618,21 +537,6 @@ __device__ __forceinline__ void wave_items(const EngineArgs& args, unsigned char
     }
     if (!args.persistent) break;
   }
-}
-
-template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 12 ? 3 : 2, 8))) void wave_engine_kernel(
-    EngineArgs args) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
-  wave_items<K>(args, smem, [&](const PatternView& P, int64_t lo, int64_t hi, int wave, int lane, double& sr,
-                                double& si, double& cr, double& ci) {
-    int32_t* pl = reinterpret_cast<int32_t*>(smem + L.pl) + wave * kMaxK;
-    double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
-    int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
-    double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    wave_range<K, 1>(P, lo, hi, pl, trw, sz, terms, lane, sr, si, cr, ci);
-  });
 }
 
 }  // namespace gbs

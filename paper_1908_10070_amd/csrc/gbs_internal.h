@@ -10,7 +10,7 @@ namespace gbs {
 
 constexpr int kMaxK = GBS_N_MAX / 2;  // largest pair count k = n/2
 constexpr int kMaxOps = 64;           // ops in one chain program
-constexpr int kThreads = 256;         // workgroup size of the register engine (4 waves)
+constexpr int kThreads = 256;         // workgroup size of the engines that give each wave its own subsets
 
 enum OpType : uint8_t { OP_MUL = 1, OP_TDIAG = 2, OP_TPAIR = 3 };
 
@@ -28,12 +28,6 @@ struct ChainProgram {
   int32_t nmul;
   int32_t npair;
   Op ops[kMaxOps];
-};
-
-struct ConstTables {
-  ChainProgram prog[kMaxK + 1];
-  uint64_t binom[kMaxK + 1][kMaxK + 1];  // C(a, b)
-  double inv[kMaxK + 1];                  // 1/q, correctly rounded
 };
 
 // One pattern (a matrix to take the hafnian of).
@@ -111,8 +105,38 @@ struct MargArgs {
   double* q_out;             // per prefix marginal
 };
 
+// Subset-engine kernel variants, one kernel per (engine, k) so each carries only its own k's
+// registers and chain program. Class numbers (k = n/2, s = |Z|):
+//   0..22   quad engine, |Z| <= 6, k = 1..23                        (gbs_eng_quad.hip)
+//   23..41  quad engine on a 4x4 tile grid, |Z| = 7, 8, k = 5..23    (gbs_eng_grid4.hip)
+//   42..56  quad engine on a 5x5 tile grid, |Z| = 9, 10, k = 9..23   (gbs_eng_grid5.hip)
+//   57..62  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16      (gbs_eng_strip.hip)
+//   63..69  quad-tile engine, |Z| = 11, 12, k = 17..23               (gbs_eng_tile.hip)
+//   70..80  tile engine, 2x2 16x16 tiles, |Z| = 13..16, k = 13..23   (gbs_eng_tile.hip)
+//   81..87  tile engine, 3x3 16x16 tiles, |Z| >= 17, k = 17..23      (gbs_eng_tile.hip)
+constexpr int kEngineClasses = 88;
+constexpr int kClsQuad = 0, kClsGrid4 = 23, kClsGrid5 = 42, kClsStrip = 57, kClsQtile = 63, kClsTile2 = 70,
+              kClsTile3 = 81;
+
+enum EngineKind { kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3 };
+
+// One kernel variant: its entry point, workgroup size, engine kind and tile count per side (tile
+// engines) or largest grid side (quad engines).
+struct EngineVariant {
+  const void* fn;
+  int threads;
+  int kind;
+  int tiles;
+};
+
+// Each engine translation unit fills its classes of the variant table.
+void register_quad_engines(EngineVariant* tab);
+void register_grid4_engines(EngineVariant* tab);
+void register_grid5_engines(EngineVariant* tab);
+void register_strip_engines(EngineVariant* tab);
+void register_tile_engines(EngineVariant* tab);
+
 // Host-side launchers (defined in gbs_kernels.hip).
-constexpr int kEngineClasses = 88;  // subset-engine kernel variants (see gbs_kernels.hip)
 int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);
 int engine_blocks_per_cu(int cls, size_t lds);
@@ -123,6 +147,5 @@ void launch_state(const double2* U, const double* r, int m, double2* B, double2*
 void launch_marginal(const MargArgs& a, int kmax, int64_t h_total, hipStream_t s);
 // next[b] = smallest l in [0, m) with w[b][0] + ... + w[b][l] >= u[b] * (w[b][0] + ... + w[b][m-1])
 void launch_draw(const double* w, int64_t batch, int m, const double* u, int32_t* next, hipStream_t s);
-int upload_tables(const ConstTables& t);
 
 }  // namespace gbs

@@ -1,70 +1,32 @@
-// HIP kernels of libgbs for gfx950 (MI355X).
+// HIP kernels of libgbs for gfx950 (MI355X) other than the subset engines, and the dispatch of the
+// engine variants.
 //
 // Hafnian by the power-trace formula the paper cites for its O(n^3 2^(n/2)) cost (Sec. II C):
 // with k = n/2, pairs (2i, 2i+1) and X the within-pair row swap,
 //   Haf(A) = sum_{Z subset [k], Z != {}} (-1)^(k-|Z|) c_k(M_Z),   M_Z = X A_Z,
 //   c_0 = 1,  q c_q = sum_{j=1..q} (tr(M_Z^j) / 2) c_{q-j}        (c_k = [lambda^k] det(I - lambda M_Z)^(-1/2)).
 //
-// Work layout (one workgroup = 4 waves):
-//   * a work item is a range of the canonical subset order of one pattern (by |Z|, then bitmask);
-//   * the pattern matrix (n <= 32) is staged in LDS once per item;
-//   * "small" subsets (d = 2|Z| <= 16) run one per wave, "large" ones (d <= 48) on all four waves;
-//   * per subset, a chain program forms a few powers of M_Z with FP64 MFMA (16x16x4 tiles, operands
-//     read from LDS slots) and takes every t_j = tr(M_Z^j), j <= k, either from a diagonal or as an
-//     inner product tr(M^a M^b);
-//   * traces of 16 subsets are buffered, then 16 lanes run the coefficient recursion at once and
-//     one lane adds the signed terms into a compensated (Neumaier) running sum;
-//   * each item writes one compensated partial; a finalize kernel sums a pattern's partials in
-//     item order, so the result depends only on n and the chunking, never on the batch around it.
+// A call's subsets are cut into work items (ranges of one pattern's canonical subset order: by |Z|,
+// then bitmask). Each item runs on the engine kernel for its subset sizes and k (gbs_eng_*.hip; the
+// class table is in gbs_internal.h) and writes one compensated partial sum; finalize_kernel adds a
+// pattern's partials in item order, so a result depends only on n and the chunk sizes, never on the
+// batch around it. This file also holds the state setup (B, W, prefactor), the Theorem-1 marginal
+// kernels, the inverse-CDF draw of the sampler and the work-counter reset.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <utility>
 
-#include "gbs_internal.h"
+#include "gbs_engine_common.h"
+#include "gbs_quad_engine.h"
+#include "gbs_qtile_engine.h"
+#include "gbs_strip_engine.h"
+#include "gbs_tile_engine.h"
 
 namespace gbs {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__constant__ ConstTables c_tab;
-
-struct __align__(16) C2 {
-  double x, y;
-};
-
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
-  double t = s + x;
-  if (fabs(s) >= fabs(x))
-    c += (s - t) + x;
-  else
-    c += (x - t) + s;
-  s = t;
-}
-
-// Canonical subset order for k pairs: all subsets of size 1, then size 2, ...; within a size,
-// increasing bitmask (colexicographic order of the pair sets).
-__device__ __forceinline__ uint32_t unrank_subset(int k, int64_t g, int* s_out) {
-  int s = 1;
-  uint64_t rem = (uint64_t)g;
-  while (s < k && rem >= c_tab.binom[k][s]) {
-    rem -= c_tab.binom[k][s];
-    ++s;
-  }
-  uint32_t mask = 0;
-  int c = k - 1;
-  for (int i = s; i >= 1; --i) {
-    while (c_tab.binom[c][i] > rem) --c;
-    mask |= 1u << c;
-    rem -= c_tab.binom[c][i];
-    --c;
-  }
-  *s_out = s;
-  return mask;
 }
 
 // ---------------------------------------------------------------- finalize
@@ -417,91 +379,38 @@ void launch_marginal(const MargArgs& a, int kmax, int64_t h_total, hipStream_t s
   hipLaunchKernelGGL(marg_sum_kernel, dim3((unsigned)g), dim3(64), 0, s, a);
 }
 
-int upload_tables(const ConstTables& t) {
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), &t, sizeof(ConstTables)) == hipSuccess ? 0 : 1;
-}
+// ---------------------------------------------------------------- engine dispatch
 
-}  // namespace gbs
-
-// Subset engines (same translation unit: they read c_tab).
-#include "gbs_wave_engine.h"
-#include "gbs_quad_engine.h"
-#include "gbs_tile_engine.h"
-#include "gbs_qtile_engine.h"
-#include "gbs_strip_engine.h"
-
-namespace gbs {
-
-// Engine kernel variants, one per (engine, k) so each carries only its own k's registers:
-//   classes  0..22  quad engine (four subsets per wave, 4x4x4 MFMA), |Z| <= 6, k = 1..23
-//   classes 23..41  |Z| = 7, 8, k = 5..23: quad engine on a 4x4 tile grid (kQuadMaxS = 8, default) or
-//                   register engine (one subset per wave, one 16x16 tile; builds with kQuadMaxS = 6)
-//   classes 42..49  quad engine on a 5x5 tile grid (GBS_QUAD5, default) or strip engine with 5 tile rows
-//                   (one subset per wave, 4x4x4 MFMA), |Z| = 9, 10, k = 9..16
-//   classes 50..55  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16
-//   classes 56..62  quad-tile engine (four subsets per 4 waves, 4x4x4 MFMA), 9 <= |Z| <= 12, k = 17..23
-//                   (|Z| = 11, 12 only, with GBS_QUAD5)
-//   classes 63..73  tile engine T = 2 (2x2 tiles, 4 waves), 13 <= |Z| <= 16, k = 13..23
-//   classes 74..80  tile engine T = 3 (3x3 tiles, 9 waves), |Z| >= 17, k = 17..23
-//   classes 81..87  quad engine on a 5x5 tile grid, |Z| = 9, 10, k = 17..23 (GBS_QUAD5)
-// Without the 5x5 quad grid, the strip engine measured faster for 9 <= |Z| <= 12 up to k = 16 (n = 24:
-// 1.4x the quad-tile engine's throughput on those subsets); from k = 17 its registers spill and the
-// quad-tile engine, at one wave per SIMD with no spills, is faster. The strip engine has one kernel
-// per tile-row count so that the common 5-row case is not sized for 6 rows. EngineVariant::tiles is
-// the tile count per side of a tile engine and the largest grid side (4 or 5) of a quad engine.
-enum EngineKind { kQuadKind, kWaveKind, kStripKind, kQtileKind, kTileKind };
-
-// |Z| = 9, 10 for k <= 16: the quad engine on a 5x5 tile grid (default) or the five-row strip engine
-#ifndef GBS_QUAD5
-#define GBS_QUAD5 1
-#endif
-constexpr bool kQuad5 = GBS_QUAD5 != 0;
-
-struct EngineVariant {
-  void (*fn)(EngineArgs);
-  int threads;
-  int kind;
-  int tiles;
-};
-
-template <int C>
-static EngineVariant variant_c() {
-  if constexpr (C >= 81) return {quad_grid_kernel<C - 81 + 17, 5>, kThreads, kQuadKind, 5};
-  else if constexpr (C < 23) return {quad_engine_kernel<C + 1>, kThreads, kQuadKind, 3};
-  else if constexpr (C < 42) {
-    if constexpr (kQuadMaxS > 6) return {quad_grid_kernel<C - 23 + 5, 4>, kThreads, kQuadKind, 4};
-    else return {wave_engine_kernel<C - 23 + 5>, kThreads, kWaveKind, 1};
-  }
-  else if constexpr (C < 50) {
-    if constexpr (kQuad5) return {quad_grid_kernel<C - 42 + 9, 5>, kThreads, kQuadKind, 5};
-    else return {strip_engine_kernel<C - 42 + 9, 5, 5>, kThreads, kStripKind, 1};
-  }
-  else if constexpr (C < 56) return {strip_engine_kernel<C - 50 + 11, 6, 6>, kThreads, kStripKind, 1};
-  else if constexpr (C < 63) return {qtile_engine_kernel<C - 56 + 17>, kThreads, kQtileKind, 1};
-  else if constexpr (C < 74) return {tile_engine_kernel<2, C - 63 + 13>, 256, kTileKind, 2};
-  else return {tile_engine_kernel<3, C - 74 + 17>, 576, kTileKind, 3};
-}
-
-template <int... C>
-static EngineVariant variant_table(int cls, std::integer_sequence<int, C...>) {
-  static const EngineVariant tab[] = {variant_c<C>()...};
-  return (cls >= 0 && cls < (int)sizeof...(C)) ? tab[cls] : EngineVariant{nullptr, 0, 0, 0};
+static const EngineVariant* variants() {
+  static EngineVariant tab[kEngineClasses] = {};
+  static const bool filled = [] {
+    register_quad_engines(tab);
+    register_grid4_engines(tab);
+    register_grid5_engines(tab);
+    register_strip_engines(tab);
+    register_tile_engines(tab);
+    return true;
+  }();
+  (void)filled;
+  return tab;
 }
 
 static EngineVariant variant(int cls) {
-  return variant_table(cls, std::make_integer_sequence<int, kEngineClasses>{});
+  if (cls < 0 || cls >= kEngineClasses) return EngineVariant{nullptr, 0, 0, 0};
+  return variants()[cls];
 }
 
+// Engine per subset size: the quad engine's grids up to |Z| = 10 (four subsets per wave on the 4x4x4
+// MFMA; only the tiles on and above the diagonal), the strip engine for |Z| = 11, 12 up to k = 16 and
+// the quad-tile engine above (where the strip engine's registers spill), the 16x16 tile engines
+// (2x2 and 3x3 tiles per workgroup) for larger subsets.
 int engine_class(int s, int k) {
-  static_assert(kQuadMaxS == 6 || kQuadMaxS == 8, "quad engine sizes");
-  if (s <= 6) return k - 1;
-  if (s <= 8) return 23 + (k - 5);
-  if (kQuad5 && s <= 10 && k >= 17) return 81 + (k - 17);
-  if (s <= 12 && k >= 17) return 56 + (k - 17);
-  if (s <= 10) return 42 + (k - 9);
-  if (s <= 12) return 50 + (k - 11);
-  if (s <= 16) return 63 + (k - 13);
-  return 74 + (k - 17);
+  if (s <= 6) return kClsQuad + (k - 1);
+  if (s <= 8) return kClsGrid4 + (k - 5);
+  if (s <= 10) return kClsGrid5 + (k - 9);
+  if (s <= 12) return k <= 16 ? kClsStrip + (k - 11) : kClsQtile + (k - 17);
+  if (s <= 16) return kClsTile2 + (k - 13);
+  return kClsTile3 + (k - 17);
 }
 
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
@@ -509,15 +418,13 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   if (v.kind == kQtileKind) return qtile_lds_layout(nmax, kmax, stage_A).total;
   if (v.kind == kStripKind) return strip_lds_bytes(nmax, kmax, stage_A);
   if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
-  if (v.kind == kQuadKind) return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));
-  return wave_lds_layout(nmax, kmax, stage_A).total;
+  return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));
 }
 
 static void allow_lds(int cls) {
   static bool done[kEngineClasses] = {};
   if (cls < 0 || cls >= kEngineClasses || done[cls]) return;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(variant(cls).fn),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute(variant(cls).fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   done[cls] = true;
 }
 
@@ -534,7 +441,9 @@ void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream
   const EngineVariant v = variant(cls);
   if (!v.fn) return;
   allow_lds(cls);
-  hipLaunchKernelGGL(v.fn, dim3(grid), dim3(v.threads), lds, s, a);
+  EngineArgs arg = a;
+  void* kargs[] = {&arg};
+  (void)hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), kargs, lds, s);
 }
 
 }  // namespace gbs

@@ -17,6 +17,8 @@
 // the four waves' values are added in wave order through LDS, and the coefficient recursion and the
 // compensated sum are those of the other engines.
 #pragma once
+#include "gbs_engine_common.h"
+#include "gbs_quad_engine.h"
 
 namespace gbs {
 namespace {

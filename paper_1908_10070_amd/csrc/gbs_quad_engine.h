@@ -1,28 +1,23 @@
-// Quad subset engine for small subsets (d = 2|Z| <= 16), gfx950.
+// Quad subset engine for subsets with d = 2|Z| <= 20, gfx950.
 //
 // v_mfma_f64_4x4x4_4b_f64 computes four independent 4x4x4 products, one per block b = (lane >> 2) & 3.
 // Here each block carries a different subset: a wave evaluates four consecutive subsets of the
-// canonical order at once. A d x d complex matrix is a T4 x T4 grid (T4 = ceil(d/4) <= 4) of 4x4
+// canonical order at once. A d x d complex matrix is a T4 x T4 grid (T4 = ceil(d/4) <= 5) of 4x4
 // tiles; one double register per tile holds, for block b, element (row y, column x) of that tile at
-// lane x + 4b + 16y -- the instruction's output (and B-operand) layout. As in the register engine,
+// lane x + 4b + 16y -- the instruction's output (and B-operand) layout. As in every engine,
 // every power Q of M_Z has Q[i][c] = Q[c^1][i^1], so the A operand of a product is the transposed
 // tile read from lane l ^ 17 (block bits untouched), and tr(P Q) pairs each tile with the same tile of
 // Q read from lane l ^ 17. The same symmetry makes tile (J, I) a lane permutation of tile (I, J), so
 // only the tiles with I <= J are stored and computed (qmul: 6 of 9 tile products at T4 = 3, 10 of 16
 // at T4 = 4). The k traces of the four subsets are reduced over the 16 lanes of each
-// block with the register engine's VALU lane exchanges (fold over bit 5 per trace, then transposed
+// block with the shared VALU lane exchanges (fold over bit 5 per trace, then transposed
 // over bits 4 and 1, plain over bit 0); half the lanes store a share of the results.
 #pragma once
+#include "gbs_engine_common.h"
 
 namespace gbs {
 namespace {
 
-// largest |Z| on the quad engine (4x4 tiles, T4 = ceil(|Z|/2) <= 4); 6 hands |Z| = 7, 8 to the
-// register engine instead (one 16x16 tile per subset)
-#ifndef GBS_QUAD_MAX_S
-#define GBS_QUAD_MAX_S 8
-#endif
-constexpr int kQuadMaxS = GBS_QUAD_MAX_S;
 // up to this k the quad engine multiplies with three real products per step (see cmul_mat)
 #ifndef GBS_QUAD_GAUSS_KMAX
 #define GBS_QUAD_GAUSS_KMAX kMaxK
@@ -317,14 +312,12 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
         eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 3)
         eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-      else if (kQuadMaxS <= 4 || smax <= 4)
+      else if (smax <= 4)
         eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-      else if constexpr (kQuadMaxS > 4) {
-        if (smax <= 5)
-          eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-        else
-          eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
-      }
+      else if (smax <= 5)
+        eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+      else
+        eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
     }
     wave_sync();
     combine_batch<K, (K > 4)>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
@@ -334,7 +327,7 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 
 }  // namespace
 
-// LDS: the register engine's layout, then (4x4-tile grids enabled) one trace-parking area per wave.
+// LDS: the shared item-loop layout (wave_lds_layout), then one trace-parking area per wave.
 __host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A, int park_k) {
   return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * park_k * 64;
 }

@@ -18,41 +18,13 @@
 #include "gbs_internal.h"
 
 #include "gbs_chain_table.h"
+#include "gbs_tables.h"
 
 using namespace gbs;
 
 namespace {
 
 constexpr size_t kLdsBudget = 160 * 1024;
-
-// ------------------------------------------------------------------ tables
-
-struct Tables {
-  bool ok = false;
-  int err = GBS_OK;
-  ConstTables host{};
-};
-
-std::mutex g_tab_mu;
-Tables g_tab;
-
-size_t slot_bytes_large(int n) { return sizeof(double) * 2 * (size_t)n * (n + 1); }
-
-// Chain programs for every k, each the cheapest whose LDS slots fit the engine's budget at d = n.
-const Tables& tables() {
-  std::lock_guard<std::mutex> lk(g_tab_mu);
-  if (g_tab.ok || g_tab.err != GBS_OK) return g_tab;
-  ConstTables& t = g_tab.host;
-  std::memset(&t, 0, sizeof(t));
-  for (int a = 0; a <= kMaxK; ++a) {
-    t.binom[a][0] = 1;
-    for (int b = 1; b <= kMaxK; ++b) t.binom[a][b] = a == 0 ? 0 : t.binom[a - 1][b - 1] + t.binom[a - 1][b];
-  }
-  for (int q = 1; q <= kMaxK; ++q) t.inv[q] = 1.0 / (double)q;
-  for (int k = 0; k <= kMaxK; ++k) t.prog[k] = kChainTable[k];
-  g_tab.ok = true;
-  return g_tab;
-}
 
 // ------------------------------------------------------------------ helpers
 
@@ -62,9 +34,9 @@ int64_t subset_count(int n) {
 }
 
 // first canonical index of subsets with |Z| = s (s >= 1)
-int64_t size_start(const ConstTables& t, int k, int s) {
+int64_t size_start(int k, int s) {
   int64_t g = 0;
-  for (int q = 1; q < s && q <= k; ++q) g += (int64_t)t.binom[k][q];
+  for (int q = 1; q < s && q <= k; ++q) g += (int64_t)kBinom.v[k][q];
   return g;
 }
 
@@ -72,11 +44,6 @@ double flops_subset(const ChainProgram& p, int k, int s) {
   const double d = 2.0 * s;
   return p.nmul * 8.0 * d * d * d + p.npair * 8.0 * d * d + 8.0 * k * (k + 1) / 2.0;
 }
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
 
 }  // namespace
 
@@ -90,9 +57,9 @@ struct GraphKey {
 struct gbs_ctx {
   int device = 0;
   int ncu = 0;
-  void* ws = nullptr;
+  void* ws = nullptr;        // caller-owned workspace
   size_t ws_bytes = 0;
-  bool ws_owned = false;
+  size_t ws_needed = 0;      // what the last call that found it too small needed
   // ring of pinned staging buffers: a call waits only for the copy of the call kPinRing calls back
   // (a ring of four measured 3% slower on the batched n = 24 launch than this one)
   static constexpr int kPinRing = 2;
@@ -116,10 +83,10 @@ struct gbs_ctx {
   std::list<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
 };
 
+// Views into caller-owned state memory (layout: state_layout).
 struct gbs_state {
   int device = 0;
   int m = 0;
-  double2* U = nullptr;
   double2* B = nullptr;
   double2* W = nullptr;  // U U^t (marginal probabilities)
   double* r = nullptr;
@@ -180,7 +147,8 @@ struct Plan {
   std::vector<PatternDesc> pats;
   std::vector<WorkItem> items;  // grouped by engine kernel
   struct Group {
-    int cls;                     // engine kernel variant
+    int cls;                     // engine kernel variant (one k per variant)
+    int n;                       // photon number of every pattern in the group
     int64_t first, count;
   };
   std::vector<Group> groups;
@@ -196,11 +164,9 @@ struct ItemLists {
   std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
 };
 
-// Split [lo, hi) of pattern p into items: ranges of subset sizes that share an engine variant
-// (small |Z| on the quad engine, up to 8 on the one-tile register engine, 9..16 and >= 17 on the 2x2
-// and 3x3 tile engines), cut into chunks.
-void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L, int p, int n, int64_t lo,
-                int64_t hi) {
+// Split [lo, hi) of pattern p into items: runs of subset sizes that share an engine variant
+// (engine_class), cut into chunks of chunk_small subsets (|Z| <= 8) or chunk_large (larger |Z|).
+void plan_range(const gbs_ctx* ctx, Plan& pl, ItemLists& L, int p, int n, int64_t lo, int64_t hi) {
   if (hi <= lo) return;
   const int k = n / 2;
   int64_t cs, cl;
@@ -210,8 +176,8 @@ void plan_range(const gbs_ctx* ctx, const ConstTables& t, Plan& pl, ItemLists& L
     const int cls = engine_class(s_lo, k);
     int s_hi = s_lo;
     while (s_hi + 1 <= k && engine_class(s_hi + 1, k) == cls) ++s_hi;
-    const int64_t a = std::max(lo, size_start(t, k, s_lo));
-    const int64_t b = std::min(hi, size_start(t, k, s_hi + 1));
+    const int64_t a = std::max(lo, size_start(k, s_lo));
+    const int64_t b = std::min(hi, size_start(k, s_hi + 1));
     const int64_t chunk = s_hi <= 8 ? cs : cl;
     std::vector<WorkItem>& out = L.cls[cls];
     for (int64_t x = a; x < b; x += chunk) {
@@ -241,6 +207,7 @@ void order_items(Plan& pl, ItemLists& L) {
     });
     Plan::Group g;
     g.cls = cls;
+    g.n = pl.pats[v.front().pattern].n;
     g.first = (int64_t)pl.items.size();
     g.count = (int64_t)v.size();
     pl.items.insert(pl.items.end(), v.begin(), v.end());
@@ -258,7 +225,7 @@ Layout layout_for(const Plan& pl, size_t n_modes) {
   Layout L;
   size_t off = 0;
   L.counter = off;
-  off += 256;  // one work counter per engine launch
+  off += al(sizeof(int32_t) * std::max<size_t>(pl.groups.size(), 1));  // one work counter per engine launch
   const size_t stage_begin = off;
   L.modes = off;
   off += al(sizeof(int32_t) * n_modes);
@@ -282,26 +249,9 @@ Layout layout_for(const Plan& pl, size_t n_modes) {
 }
 
 int ensure_ws(gbs_ctx* ctx, size_t bytes) {
-  if (ctx->ws_bytes >= bytes) return GBS_OK;
-  if (!ctx->ws_owned && ctx->ws)
-    return fail(ctx, GBS_ENOMEM, "workspace of %zu bytes is smaller than the %zu the plan needs", ctx->ws_bytes,
-                bytes);
-  size_t nb = std::max(bytes, ctx->ws_bytes * 2);
-  if (ctx->ws) {
-    HIPCHK(ctx, hipDeviceSynchronize());
-    HIPCHK(ctx, hipFree(ctx->ws));
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
-  }
-  if (hipMalloc(&ctx->ws, nb) != hipSuccess) {
-    ctx->ws = nullptr;
-    return fail(ctx, GBS_ENOMEM, "hipMalloc of %zu workspace bytes failed", nb);
-  }
-  ctx->ws_bytes = nb;
-  ctx->ws_owned = true;
-  return GBS_OK;
+  if (ctx->ws && ctx->ws_bytes >= bytes) return GBS_OK;
+  ctx->ws_needed = bytes;
+  return fail(ctx, GBS_ENOMEM, "workspace of %zu bytes is smaller than the %zu the call needs", ctx->ws_bytes, bytes);
 }
 
 int ensure_pinned(gbs_ctx* ctx, int i, size_t bytes) {
@@ -323,8 +273,6 @@ int ensure_pinned(gbs_ctx* ctx, int i, size_t bytes) {
 int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_modes, const double2* A,
              int32_t m, const double* prefactor_dev, double* prob_out, double2* haf_out, gbs_partial* partial_out,
              hipStream_t stream) {
-  const Tables& T = tables();
-  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
   DeviceGuard dg(ctx->device);
   const Layout L = layout_for(pl, n_modes);
   int rc = ensure_ws(ctx, L.total);
@@ -351,7 +299,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], stream));
   ctx->pinned_used[pi] = true;
 
-  // register engine (|Z| <= 16) and workgroup engine (|Z| > 16): separate item lists and counters
+  // one persistent launch per engine variant, each with its own item list and work counter
   EngineArgs ea{};
   ea.A = A;
   ea.modes = modes_host ? reinterpret_cast<const int32_t*>(ws + L.modes) : nullptr;
@@ -359,9 +307,6 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   ea.pats = reinterpret_cast<const PatternDesc*>(ws + L.pats);
   ea.partials = reinterpret_cast<gbs_partial*>(ws + L.partials);
   ea.persistent = ctx->persistent;
-  ea.stage_A = pl.nmax <= 32 ? 1 : 0;
-  ea.nmax = std::max(pl.nmax, 2);
-  ea.kmax = std::max(pl.kmax, 1);
 
   struct Launch {
     int cls;
@@ -379,7 +324,11 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
     ln.a.n_items = (int32_t)g.count;
     ln.a.items = reinterpret_cast<const WorkItem*>(ws + L.items) + g.first;
     ln.a.counter = counters + gi;
-    ln.lds = engine_lds_bytes(g.cls, ea.nmax, ea.kmax, ea.stage_A);
+    // every item of a variant has the same n: LDS sized for that n only (staged copy for n <= 32)
+    ln.a.nmax = std::max(g.n, 2);
+    ln.a.kmax = std::max(g.n / 2, 1);
+    ln.a.stage_A = g.n <= 32 ? 1 : 0;
+    ln.lds = engine_lds_bytes(g.cls, ln.a.nmax, ln.a.kmax, ln.a.stage_A);
     const int per_cu = engine_blocks_per_cu(g.cls, ln.lds);
     if (ln.lds > kLdsBudget) return fail(ctx, GBS_EUNSUPPORTED, "plan needs %zu bytes of LDS", ln.lds);
     ln.grid = (int)g.count;
@@ -408,7 +357,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
 
   if (ctx->use_graph) {
     GraphKey key;
-    key.v = {ea.nmax, ea.kmax, ea.stage_A, ea.persistent, (int64_t)(intptr_t)A,
+    key.v = {ea.persistent, (int64_t)(intptr_t)A,
              (int64_t)(intptr_t)ea.modes, m, fa.batch, (int64_t)(intptr_t)prefactor_dev, (int64_t)(intptr_t)prob_out,
              (int64_t)(intptr_t)haf_out, (int64_t)(intptr_t)partial_out, (int64_t)(intptr_t)ctx->ws, (int64_t)L.pats,
              (int64_t)L.items, (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact,
@@ -418,6 +367,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
       key.v.push_back(ln.grid);
       key.v.push_back((int64_t)ln.lds);
       key.v.push_back(ln.a.n_items);
+      key.v.push_back(ln.a.nmax);
     }
     hipGraphExec_t exec = nullptr;
     for (auto itg = ctx->graphs.begin(); itg != ctx->graphs.end(); ++itg)
@@ -531,8 +481,6 @@ int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GBS_EINVAL;
   if (!check_gfx950(device)) return GBS_EUNSUPPORTED;
-  const Tables& T = tables();
-  if (!T.ok) return T.err;
   DeviceGuard dg(device);
   gbs_ctx* c = new gbs_ctx();
   c->device = device;
@@ -545,17 +493,14 @@ int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_
   bool ev_ok = true;
   for (int i = 0; i < gbs_ctx::kPinRing; ++i)
     ev_ok = ev_ok && hipEventCreateWithFlags(&c->pinned_ev[i], hipEventDisableTiming) == hipSuccess;
-  if (upload_tables(T.host) != 0 || !ev_ok ||
+  if (!ev_ok ||
       hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     gbs_ctx_destroy(c);
     return GBS_EHIP;
   }
-  if (workspace_dev) {
-    c->ws = workspace_dev;
-    c->ws_bytes = workspace_bytes;
-    c->ws_owned = false;
-  }
+  c->ws = workspace_dev;
+  c->ws_bytes = workspace_dev ? workspace_bytes : 0;
   *out = c;
   return GBS_OK;
 }
@@ -571,10 +516,24 @@ int gbs_ctx_destroy(gbs_ctx* c) {
   }
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  if (c->ws_owned && c->ws) (void)hipFree(c->ws);
   delete c;
   return GBS_OK;
 }
+
+int gbs_ctx_set_workspace(gbs_ctx* ctx, void* workspace_dev, size_t workspace_bytes) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (workspace_dev == nullptr && workspace_bytes != 0) return fail(ctx, GBS_EINVAL, "null workspace");
+  DeviceGuard dg(ctx->device);
+  if (ctx->done_recorded) HIPCHK(ctx, hipEventSynchronize(ctx->done_ev));
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+  ctx->graphs.clear();
+  ctx->ws = workspace_dev;
+  ctx->ws_bytes = workspace_dev ? workspace_bytes : 0;
+  return GBS_OK;
+}
+
+size_t gbs_ctx_workspace_needed(const gbs_ctx* ctx) { return ctx ? ctx->ws_needed : 0; }
 
 int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent) {
   if (!ctx) return GBS_EINVAL;
@@ -601,12 +560,10 @@ int64_t gbs_subset_count(int32_t n) { return (n < 0 || n > GBS_N_MAX) ? 0 : subs
 
 double gbs_haf_flops(int32_t n) {
   if (n <= 0 || (n & 1) || n > GBS_N_MAX) return 0.0;
-  const Tables& T = tables();
-  if (!T.ok) return 0.0;
   const int k = n / 2;
   double f = 0.0;
   // the method as formulated: every subset forms all k traces with the chain program for k
-  for (int s = 1; s <= k; ++s) f += (double)T.host.binom[k][s] * flops_subset(T.host.prog[k], k, s);
+  for (int s = 1; s <= k; ++s) f += (double)kBinom.v[k][s] * flops_subset(kChainTable[k], k, s);
   return f;
 }
 
@@ -621,8 +578,6 @@ int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_of
   for (int64_t b = 0; b < batch && !any_data; ++b) any_data = n_host[b] > 0;
   if (any_data && !A_dev) return fail(ctx, GBS_EINVAL, "null matrix pointer");
   if (batch > (int64_t)1 << 30) return fail(ctx, GBS_ERANGE, "batch too large");
-  const Tables& T = tables();
-  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
   Plan pl;
   pl.pats.resize(batch);
   pl.part_off.resize(batch + 1);
@@ -636,7 +591,7 @@ int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_of
     if (elem_off_host[b] < 0) return fail(ctx, GBS_EINVAL, "negative matrix offset");
     pl.pats[b] = PatternDesc{elem_off_host[b], n, 0};
     pl.nvec[b] = n;
-    plan_range(ctx, T.host, pl, lists, (int)b, n, 0, subset_count(n));
+    plan_range(ctx, pl, lists, (int)b, n, 0, subset_count(n));
     pl.part_off[b + 1] = pl.n_partials;
   }
   order_items(pl, lists);
@@ -658,32 +613,70 @@ int haf_batch(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t batch, int
   return haf_batch_varlen(ctx, A_dev, off.data(), nn.data(), batch, haf_out_dev, stream);
 }
 
-int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const double* r_host, void* stream,
-                     gbs_state** out) {
+namespace {
+
+struct StateLayout {
+  size_t B, W, r, pref, total;
+};
+
+StateLayout state_layout(int m) {
+  StateLayout L;
+  const size_t mm = (size_t)m * m;
+  size_t off = 0;
+  L.B = off;
+  off += al(sizeof(double2) * mm);
+  L.W = off;
+  off += al(sizeof(double2) * mm);
+  L.r = off;
+  off += al(sizeof(double) * m);
+  L.pref = off;
+  off += al(sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+size_t gbs_state_bytes(int32_t m) {
+  if (m <= 0 || m > 4096) return 0;
+  return state_layout(m).total;
+}
+
+int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const double* r_host, void* state_mem_dev,
+                     size_t state_mem_bytes, void* stream, gbs_state** out) {
   if (!ctx || !out) return GBS_EINVAL;
   *out = nullptr;
   ctx->last_error.clear();
-  if (!U_dev || !r_host) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (!U_dev || !r_host || !state_mem_dev) return fail(ctx, GBS_EINVAL, "null pointer");
   if (m <= 0 || m > 4096) return fail(ctx, GBS_ERANGE, "m = %d outside [1, 4096]", m);
   for (int i = 0; i < m; ++i)
     if (!std::isfinite(r_host[i])) return fail(ctx, GBS_EINVAL, "non-finite squeezing parameter");
+  const StateLayout L = state_layout(m);
+  if (state_mem_bytes < L.total)
+    return fail(ctx, GBS_ENOMEM, "state memory of %zu bytes is smaller than the %zu needed", state_mem_bytes, L.total);
   DeviceGuard dg(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // r goes through the context's pinned staging ring
+  const int pi = ctx->next_pin();
+  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
+  int rc = ensure_pinned(ctx, pi, sizeof(double) * m);
+  if (rc) return rc;
+  std::memcpy(ctx->pinned[pi], r_host, sizeof(double) * m);
   gbs_state* st = new gbs_state();
   st->device = ctx->device;
   st->m = m;
-  const size_t mm = (size_t)m * m;
-  if (hipMalloc(&st->U, sizeof(double2) * mm) != hipSuccess || hipMalloc(&st->B, sizeof(double2) * mm) != hipSuccess ||
-      hipMalloc(&st->W, sizeof(double2) * mm) != hipSuccess ||
-      hipMalloc(&st->r, sizeof(double) * m) != hipSuccess || hipMalloc(&st->pref, sizeof(double)) != hipSuccess ||
-      hipEventCreateWithFlags(&st->ready, hipEventDisableTiming) != hipSuccess) {
-    gbs_state_destroy(st);
-    return fail(ctx, GBS_ENOMEM, "state allocation failed");
-  }
-  hipError_t e = hipMemcpyAsync(st->U, U_dev, sizeof(double2) * mm, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(st->r, r_host, sizeof(double) * m, hipMemcpyHostToDevice, s);
+  unsigned char* mem = static_cast<unsigned char*>(state_mem_dev);
+  st->B = reinterpret_cast<double2*>(mem + L.B);
+  st->W = reinterpret_cast<double2*>(mem + L.W);
+  st->r = reinterpret_cast<double*>(mem + L.r);
+  st->pref = reinterpret_cast<double*>(mem + L.pref);
+  hipError_t e = hipEventCreateWithFlags(&st->ready, hipEventDisableTiming);
+  if (e == hipSuccess && ctx->done_recorded) e = hipStreamWaitEvent(s, ctx->done_ev, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(st->r, ctx->pinned[pi], sizeof(double) * m, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->pinned_ev[pi], s);
   if (e == hipSuccess) {
-    launch_state(st->U, st->r, m, st->B, st->W, st->pref, s);
+    ctx->pinned_used[pi] = true;
+    launch_state(reinterpret_cast<const double2*>(U_dev), st->r, m, st->B, st->W, st->pref, s);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&st->pref_host, st->pref, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -700,11 +693,6 @@ int gbs_state_destroy(gbs_state* st) {
   if (!st) return GBS_EINVAL;
   DeviceGuard dg(st->device);
   if (st->ready) (void)hipEventSynchronize(st->ready);
-  if (st->U) (void)hipFree(st->U);
-  if (st->B) (void)hipFree(st->B);
-  if (st->W) (void)hipFree(st->W);
-  if (st->r) (void)hipFree(st->r);
-  if (st->pref) (void)hipFree(st->pref);
   if (st->ready) (void)hipEventDestroy(st->ready);
   delete st;
   return GBS_OK;
@@ -746,8 +734,6 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
   if (offsets_host[0] != 0) return fail(ctx, GBS_EINVAL, "offsets[0] must be 0");
   const int64_t total = offsets_host[batch];
   if (total > 0 && !modes_host) return fail(ctx, GBS_EINVAL, "null modes");
-  const Tables& T = tables();
-  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
   Plan pl;
   pl.pats.resize(batch);
   pl.part_off.resize(batch + 1);
@@ -773,7 +759,7 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
       lo = lo_host[b];
       hi = hi_host[b];
     }
-    plan_range(ctx, T.host, pl, lists, (int)b, n, lo, hi);
+    plan_range(ctx, pl, lists, (int)b, n, lo, hi);
     pl.part_off[b + 1] = pl.n_partials;
   }
   order_items(pl, lists);
@@ -809,30 +795,40 @@ int gbs_prob_slices(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host
 }
 
 int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_dev, const int64_t* part_lo_host,
-                 const int64_t* part_hi_host, const int32_t* n_host, const double* sfact_host, int64_t batch,
+                 const int64_t* part_hi_host, const int32_t* modes_host, const int64_t* offsets_host, int64_t batch,
                  double* prob_out_dev, gbs_c128* haf_out_dev, void* stream) {
   if (!ctx) return GBS_EINVAL;
   ctx->last_error.clear();
   if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
   if (batch == 0) return GBS_OK;
-  if (!part_lo_host || !part_hi_host || !n_host) return fail(ctx, GBS_EINVAL, "null pointer");
-  if (prob_out_dev && (!st || !sfact_host)) return fail(ctx, GBS_EINVAL, "prob_out needs a state and sfact");
+  if (!part_lo_host || !part_hi_host || !offsets_host) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (prob_out_dev && !st) return fail(ctx, GBS_EINVAL, "prob_out needs a state");
+  if (st && st->device != ctx->device) return fail(ctx, GBS_EINVAL, "state and context are on different devices");
+  if (offsets_host[0] != 0) return fail(ctx, GBS_EINVAL, "offsets[0] must be 0");
+  if (offsets_host[batch] > 0 && !modes_host) return fail(ctx, GBS_EINVAL, "null modes");
+  Plan pl;
+  pl.part_off.resize(2 * batch);
+  pl.nvec.resize(batch);
+  pl.sfact.assign(batch, 1.0);
   bool any = false;
   for (int64_t b = 0; b < batch; ++b) {
     if (part_lo_host[b] < 0 || part_hi_host[b] < part_lo_host[b])
       return fail(ctx, GBS_EINVAL, "partial range %lld is malformed", (long long)b);
-    if (n_host[b] < 0 || n_host[b] > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n out of range");
+    const int64_t len = offsets_host[b + 1] - offsets_host[b];
+    if (len < 0) return fail(ctx, GBS_EINVAL, "offsets must be non-decreasing");
+    if (len > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "pattern %lld has n = %lld > %d", (long long)b, (long long)len,
+                                     GBS_N_MAX);
+    pl.nvec[b] = (int32_t)len;
+    if (prob_out_dev) {
+      const int rc = pattern_sfact(ctx, modes_host + offsets_host[b], len, st->m, &pl.sfact[b]);
+      if (rc) return rc;
+    }
     any |= part_hi_host[b] > part_lo_host[b];
   }
   if (any && !partials_dev) return fail(ctx, GBS_EINVAL, "null partials");
-  // stage the ranges (lo then hi, in the part_off region), n and sfact
-  Plan pl;
-  pl.part_off.resize(2 * batch);
+  // stage the ranges (lo then hi, in the part_off region), n and prod_j s_j!
   std::copy(part_lo_host, part_lo_host + batch, pl.part_off.begin());
   std::copy(part_hi_host, part_hi_host + batch, pl.part_off.begin() + batch);
-  pl.nvec.assign(n_host, n_host + batch);
-  pl.sfact.assign(batch, 1.0);
-  if (sfact_host) pl.sfact.assign(sfact_host, sfact_host + batch);
   DeviceGuard dg(ctx->device);
   const Layout L = layout_for(pl, 0);
   int rc = ensure_ws(ctx, L.total);
@@ -974,8 +970,6 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
         return fail(ctx, GBS_ERANGE, "mode out of [0, %d) in prefix %lld", m, (long long)b);
     kmax = std::max(kmax, (int)len);
   }
-  const Tables& T = tables();
-  if (!T.ok) return fail(ctx, T.err, "chain program construction failed");
 
   // per-prefix tables: hafnian table offsets, weights F, classes (explicit ones only where modes
   // repeat; a collision-free prefix's 2^(k-1) classes are implicit)

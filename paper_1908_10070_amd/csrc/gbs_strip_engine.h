@@ -3,9 +3,9 @@
 // One wave evaluates one subset at a time on v_mfma_f64_4x4x4_4b_f64, whose four blocks here hold
 // four neighbouring column tiles of one tile row: a d x d complex matrix is T4 tile rows
 // (T4 = ceil(d/4) <= 6) of NR = ceil(T4/4) registers per component, and block b of register (I, R)
-// holds tile (I, 4R + b) in the quad engine's tile layout (lane x + 4b + 16y: element (y, x)). The
-// 4x4x4 FP64 MFMA sustains about 1.5x the rate of the 16x16x4 one on this device, and 4-wide tiles
-// pad d to a multiple of 4 instead of 16.
+// holds tile (I, 4R + b) in the quad engine's tile layout (lane x + 4b + 16y: element (y, x)). Both
+// FP64 MFMA shapes run at the same 32 flops per cycle per SIMD; 4-wide tiles pad d to a multiple of
+// 4 instead of 16.
 //
 // For Z = X Y, output register (I, R) accumulates over the k-tiles K inside d the product of X's
 // tile (I, K) -- broadcast to all four blocks and put into A-operand order (element (x, y) at lane
@@ -14,8 +14,10 @@
 // so a product that overwrites its second factor swaps the factors. Complex products use three real
 // products per step. Traces are tile-local as in the other engines (tr(P Q) pairs each register of
 // P with Q's register read at lane l ^ 17); their reduction, the coefficient recursion and the
-// compensated sum are the register engine's. No LDS traffic besides lane exchanges, no barriers.
+// compensated sum are the shared ones (gbs_engine_common.h). No LDS traffic besides lane exchanges, no barriers.
 #pragma once
+#include "gbs_engine_common.h"
+#include "gbs_quad_engine.h"
 
 namespace gbs {
 namespace {
@@ -416,7 +418,7 @@ __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_
 
 }  // namespace
 
-// LDS: the register engine's layout, then one trace-parking area of kmax x 64 doubles per wave.
+// LDS: the shared item-loop layout (wave_lds_layout), then one trace-parking area of kmax x 64 doubles per wave.
 __host__ __device__ inline size_t strip_lds_bytes(int nmax, int kmax, int stage_A) {
   return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * kmax * 64;
 }

@@ -6,10 +6,11 @@
 // accumulates Z(I, J) = sum_K X(I, K) Y(K, J) with the A operand X(I, K) read from tile (K, I) at lane
 // l ^ 17 (the pair symmetry Q^t = X Q X of every power) and the B operand from tile (K, J). Trace
 // inner products pair a tile with the same tile of the other factor, so they stay local; each wave
-// reduces its k partial traces with the register engine's VALU lane exchanges, and the T*T wave
+// reduces its k partial traces with the shared VALU lane exchanges, and the T*T wave
 // results are added in wave order.
-// Coefficient recursion, compensated summation and partials are as in the register engine.
+// Coefficient recursion, compensated summation and partials are the shared ones (gbs_engine_common.h).
 #pragma once
+#include "gbs_engine_common.h"
 
 namespace gbs {
 namespace {

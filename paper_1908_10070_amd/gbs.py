@@ -1,22 +1,21 @@
 """Thin Python binding of libgbs (include/gbs.h): argument marshalling only.
 
-Device memory and streams come from PyTorch (ROCm); every computation runs in the HIP
-library. There is no CPU fallback: if libgbs.so is missing or the device is not gfx950,
-the calls raise.
+Device memory and streams come from PyTorch (ROCm): every context's workspace and every state's
+memory are torch tensors (the library never allocates device memory; a call that finds the
+workspace too small returns GBS_ENOMEM with the size it needs, and the binding installs a larger
+tensor and repeats the call). Every computation runs in the HIP library. There is no CPU fallback:
+if libgbs.so is missing or the device is not gfx950, the calls raise.
 """
 from __future__ import annotations
 
 import ctypes
-import os
 import pathlib
-from typing import Optional, Sequence, Tuple
+from typing import Optional, Tuple
 
 import numpy as np
 
 _HERE = pathlib.Path(__file__).resolve().parent
-# GBS_LIB selects another build of the same library (e.g. a variant compiled with different engine
-# limits for a comparison); by default the in-tree libgbs.so.
-LIB_PATH = pathlib.Path(os.environ.get("GBS_LIB") or (_HERE / "libgbs.so"))
+LIB_PATH = _HERE / "libgbs.so"
 
 GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6)
 GBS_N_MAX = 46
@@ -24,11 +23,11 @@ GBS_MARGINAL_KMAX = 20
 
 # Every function declared in include/gbs.h.
 EXPORTS = [
-    "gbs_ctx_create", "gbs_ctx_destroy", "gbs_status_str", "gbs_last_error", "gbs_ctx_set_exec",
-    "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops", "haf_batch", "haf_batch_varlen",
-    "gbs_state_create", "gbs_state_destroy", "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch",
-    "gbs_subset_count",
-    "gbs_prob_slices", "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step",
+    "gbs_ctx_create", "gbs_ctx_destroy", "gbs_ctx_set_workspace", "gbs_ctx_workspace_needed", "gbs_status_str",
+    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops",
+    "haf_batch", "haf_batch_varlen", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
+    "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
+    "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step",
 ]
 
 _lib = None
@@ -57,6 +56,9 @@ def lib() -> ctypes.CDLL:
     sig = {
         "gbs_ctx_create": (ctypes.c_int, [ctypes.c_int, vp, sz, ctypes.POINTER(vp)]),
         "gbs_ctx_destroy": (ctypes.c_int, [vp]),
+        "gbs_ctx_set_workspace": (ctypes.c_int, [vp, vp, sz]),
+        "gbs_ctx_workspace_needed": (sz, [vp]),
+        "gbs_state_bytes": (sz, [i32]),
         "gbs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "gbs_last_error": (ctypes.c_char_p, [vp]),
         "gbs_ctx_set_exec": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
@@ -65,14 +67,14 @@ def lib() -> ctypes.CDLL:
         "gbs_haf_flops": (ctypes.c_double, [i32]),
         "haf_batch": (ctypes.c_int, [vp, dp, i32, i64, i64, dp, vp]),
         "haf_batch_varlen": (ctypes.c_int, [vp, dp, dp, dp, i64, dp, vp]),
-        "gbs_state_create": (ctypes.c_int, [vp, dp, i32, dp, vp, ctypes.POINTER(vp)]),
+        "gbs_state_create": (ctypes.c_int, [vp, dp, i32, dp, dp, sz, vp, ctypes.POINTER(vp)]),
         "gbs_state_destroy": (ctypes.c_int, [vp]),
         "gbs_state_info": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
         "gbs_state_copy_B": (ctypes.c_int, [vp, dp, vp]),
         "gbs_prob_batch": (ctypes.c_int, [vp, vp, dp, dp, i64, dp, dp, vp]),
         "gbs_subset_count": (i64, [i32]),
         "gbs_prob_slices": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, i64, dp, dp, vp]),
-        "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, dp, i64, dp, dp, vp]),
+        "gbs_finalize": (ctypes.c_int, [vp, vp, dp, dp, dp, dp, dp, i64, dp, dp, vp]),  # modes, offsets
         "gbs_marginal_batch": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, vp]),
         "gbs_photon_number_pmf": (ctypes.c_int, [i32, ctypes.c_double, i32, dp]),
         "gbs_sample_step": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, dp, dp, vp]),
@@ -143,10 +145,14 @@ class State:
         r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=np.float64), (m,)))
         self._ctx = ctx
         self.m = m
-        self._U = U
-        self._r = r
+        self._U = U  # read by the state kernel on the stream
+        nbytes = int(lib().gbs_state_bytes(m))
+        if nbytes == 0:
+            raise ValueError(f"m = {m} outside the supported range")
+        self._mem = torch.empty(nbytes, dtype=torch.uint8, device=ctx.torch_device)
         h = ctypes.c_void_p()
-        ctx._check(lib().gbs_state_create(ctx.handle, _t_ptr(U), m, _np_ptr(r), _stream_ptr(stream), ctypes.byref(h)))
+        ctx._check(lib().gbs_state_create(ctx.handle, _t_ptr(U), m, _np_ptr(r), _t_ptr(self._mem), nbytes,
+                                          _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 
     def info(self):
@@ -186,25 +192,48 @@ class State:
 class Context:
     """A libgbs context on one device (staging buffers, workspace, graphs, tuning table)."""
 
-    def __init__(self, device: int = 0, workspace=None, use_graph: bool = True, persistent: bool = True):
+    def __init__(self, device: int = 0, workspace=None, use_graph: bool = True, persistent: bool = True,
+                 workspace_bytes: int = 16 << 20, grow: bool = True):
+        """workspace: a device tensor to use as the workspace (fixed: calls that need more raise
+        GBSError(GBS_ENOMEM)); by default a uint8 tensor of workspace_bytes that grows on demand."""
         import torch
         self.device = int(device)
         self.torch_device = torch.device("cuda", self.device)
+        if workspace is None:
+            workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=self.torch_device)
+        else:
+            grow = False
         self._ws = workspace
+        self._grow = grow
         h = ctypes.c_void_p()
-        ws_ptr = _t_ptr(workspace) if workspace is not None else None
-        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
-        rc = lib().gbs_ctx_create(self.device, ws_ptr, ws_bytes, ctypes.byref(h))
+        rc = lib().gbs_ctx_create(self.device, _t_ptr(workspace), self._ws_bytes(), ctypes.byref(h))
         if rc:
             raise GBSError(rc, f"gbs_ctx_create: {lib().gbs_status_str(rc).decode()}")
         self.handle = h
         self.set_exec(use_graph, persistent)
+
+    def _ws_bytes(self) -> int:
+        return self._ws.numel() * self._ws.element_size()
 
     # -- errors
     def _check(self, rc: int):
         if rc:
             msg = lib().gbs_last_error(self.handle).decode()
             raise GBSError(rc, f"{lib().gbs_status_str(rc).decode()}: {msg}")
+
+    def _run(self, fn, *args):
+        """Call fn(handle, *args); on GBS_ENOMEM install a workspace of the size the call needed and
+        call once more (the library enqueues nothing on that error)."""
+        import torch
+        rc = fn(self.handle, *args)
+        if rc == GBS_ENOMEM and self._grow:
+            need = int(lib().gbs_ctx_workspace_needed(self.handle))
+            if need > self._ws_bytes():
+                new = torch.empty(need + need // 4, dtype=torch.uint8, device=self.torch_device)
+                self._check(lib().gbs_ctx_set_workspace(self.handle, _t_ptr(new), new.numel()))
+                self._ws = new
+                rc = fn(self.handle, *args)
+        self._check(rc)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -241,7 +270,7 @@ class Context:
         b, n = A.shape[0], A.shape[1]
         if out is None:
             out = torch.empty(b, dtype=torch.complex128, device=A.device)
-        self._check(lib().haf_batch(self.handle, _t_ptr(A), n, b, n * n, _t_ptr(out), _stream_ptr(stream)))
+        self._run(lib().haf_batch, _t_ptr(A), n, b, n * n, _t_ptr(out), _stream_ptr(stream))
         return out
 
     def haf_batch_varlen(self, A_flat, elem_off, ns, out=None, stream=None):
@@ -250,8 +279,8 @@ class Context:
         ns = np.ascontiguousarray(ns, dtype=np.int32)
         if out is None:
             out = torch.empty(len(ns), dtype=torch.complex128, device=A_flat.device)
-        self._check(lib().haf_batch_varlen(self.handle, _t_ptr(A_flat), _np_ptr(elem_off), _np_ptr(ns), len(ns),
-                                           _t_ptr(out), _stream_ptr(stream)))
+        self._run(lib().haf_batch_varlen, _t_ptr(A_flat), _np_ptr(elem_off), _np_ptr(ns), len(ns), _t_ptr(out),
+                  _stream_ptr(stream))
         return out
 
     # -- probabilities
@@ -267,8 +296,8 @@ class Context:
             prob_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
         if want_haf and haf_out is None:
             haf_out = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
-        self._check(lib().gbs_prob_batch(self.handle, state.handle, _np_ptr(modes), _np_ptr(offsets), b,
-                                         _t_ptr(prob_out), _t_ptr(haf_out), _stream_ptr(stream)))
+        self._run(lib().gbs_prob_batch, state.handle, _np_ptr(modes), _np_ptr(offsets), b, _t_ptr(prob_out),
+                  _t_ptr(haf_out), _stream_ptr(stream))
         return (prob_out, haf_out) if want_haf else prob_out
 
     def marginal_batch(self, state: State, n: int, prefixes, q_out=None, stream=None):
@@ -278,8 +307,8 @@ class Context:
         b = len(offsets) - 1
         if q_out is None:
             q_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
-        self._check(lib().gbs_marginal_batch(self.handle, state.handle, int(n), _np_ptr(modes), _np_ptr(offsets), b,
-                                             _t_ptr(q_out), _stream_ptr(stream)))
+        self._run(lib().gbs_marginal_batch, state.handle, int(n), _np_ptr(modes), _np_ptr(offsets), b, _t_ptr(q_out),
+                  _stream_ptr(stream))
         return q_out
 
     def sample_step(self, state: State, n: int, prefixes, uniforms, weights_out=None, stream=None):
@@ -295,8 +324,8 @@ class Context:
         if weights_out is not None and (weights_out.dtype != torch.float64 or not weights_out.is_contiguous()
                                         or weights_out.numel() != b * state.m):
             raise ValueError("weights_out must be a contiguous float64 tensor of prefixes x m")
-        self._check(lib().gbs_sample_step(self.handle, state.handle, int(n), _np_ptr(modes), _np_ptr(offsets), b,
-                                          _t_ptr(u), _t_ptr(weights_out), _t_ptr(nxt), _stream_ptr(stream)))
+        self._run(lib().gbs_sample_step, state.handle, int(n), _np_ptr(modes), _np_ptr(offsets), b, _t_ptr(u),
+                  _t_ptr(weights_out), _t_ptr(nxt), _stream_ptr(stream))
         return nxt
 
     def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, out_idx=None, stream=None):
@@ -315,31 +344,30 @@ class Context:
             partials_out = torch.empty((max(rows, 1), 4), dtype=torch.float64, device=self.torch_device)
         elif partials_out.shape[0] < rows:
             raise ValueError("partials_out too small for out_idx")
-        self._check(lib().gbs_prob_slices(self.handle, state.handle, _np_ptr(modes), _np_ptr(offsets), _np_ptr(lo),
-                                          _np_ptr(hi), b, _t_ptr(partials_out), _np_ptr(oi), _stream_ptr(stream)))
+        self._run(lib().gbs_prob_slices, state.handle, _np_ptr(modes), _np_ptr(offsets), _np_ptr(lo), _np_ptr(hi), b,
+                  _t_ptr(partials_out), _np_ptr(oi), _stream_ptr(stream))
         return partials_out
 
-    def finalize(self, state: Optional[State], partials, part_lo, part_hi, ns, sfact=None, want_prob=True,
+    def finalize(self, state: Optional[State], partials, part_lo, part_hi, patterns, want_prob=True,
                  prob_out=None, haf_out=None, stream=None):
-        """Pattern b = compensated sum of partials[part_lo[b]:part_hi[b]] -> (prob, haf) tensors."""
+        """Pattern b = compensated sum of partials[part_lo[b]:part_hi[b]] -> (prob, haf) tensors; the
+        patterns (mode lists) give n and, in the library, the prod_j s_j! divisor."""
         import torch
         lo = np.ascontiguousarray(part_lo, dtype=np.int64)
         hi = np.ascontiguousarray(part_hi, dtype=np.int64)
-        ns = np.ascontiguousarray(ns, dtype=np.int32)
-        b = len(ns)
+        modes, offsets = pack_patterns(patterns)
+        b = len(offsets) - 1
         if len(lo) != b or len(hi) != b:
             raise ValueError("one partial range per pattern")
         if b and int(hi.max()) > partials.shape[0]:
             raise ValueError("partial range beyond the partials tensor")
-        sf = None if sfact is None else np.ascontiguousarray(sfact, dtype=np.float64)
         if want_prob and prob_out is None:
             prob_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
         if haf_out is None:
             haf_out = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
-        self._check(lib().gbs_finalize(self.handle, state.handle if state is not None else None, _t_ptr(partials),
-                                       _np_ptr(lo), _np_ptr(hi), _np_ptr(ns), _np_ptr(sf), b,
-                                       _t_ptr(prob_out) if want_prob else None, _t_ptr(haf_out),
-                                       _stream_ptr(stream)))
+        self._run(lib().gbs_finalize, state.handle if state is not None else None, _t_ptr(partials), _np_ptr(lo),
+                  _np_ptr(hi), _np_ptr(modes), _np_ptr(offsets), b, _t_ptr(prob_out) if want_prob else None,
+                  _t_ptr(haf_out), _stream_ptr(stream))
         return (prob_out if want_prob else None), haf_out
 
 
@@ -350,16 +378,3 @@ def photon_number_pmf(m: int, r: float, nmax: int) -> np.ndarray:
     if rc:
         raise GBSError(rc, "gbs_photon_number_pmf failed")
     return out
-
-
-def sfact_of(modes: Sequence[int]) -> float:
-    """prod_j s_j! of a mode list (host-side helper for schedulers)."""
-    ml = [int(v) for v in modes]
-    if len(set(ml)) == len(ml):
-        return 1.0  # no mode repeats
-    _, counts = np.unique(np.asarray(ml, dtype=np.int64), return_counts=True)
-    f = 1.0
-    for c in counts:
-        for v in range(2, int(c) + 1):
-            f *= v
-    return f

@@ -13,8 +13,9 @@ Requests (output patterns, i.e. mode lists) arrive at any time. The server keeps
   earlier ones complete. A request that could never fit is rejected.
 * A step takes slices from active requests, shortest remaining work first, at most ``step_flops``
   of modelled work and at most ``share`` of that from one request, so short requests are not held
-  behind long ones; the oldest active request always gets one slice, so long ones keep moving. Up to ``inflight`` steps are queued on the stream, so the host prepares the next
-  step while the device runs the current one.
+  behind long ones; the oldest active request always gets one slice outside the budget and then
+  competes for the rest like the others, so long ones keep moving. Up to ``inflight`` steps are
+  queued on the stream, so the host prepares the next step while the device runs the current one.
 * When a request's last slice has been launched, a ``gbs_finalize`` launch (its slices' partials,
   in slice order, compensated) follows on the same stream and produces the probability; the
   request completes when that result has been copied back.
@@ -121,8 +122,7 @@ class GpuBackend(SliceBackend):
         if nf:
             lo = [r.pool_off for r in finished]
             hi = [r.pool_off + len(r.slices) for r in finished]
-            self.ctx.finalize(self.state, self.pool, lo, hi, [r.n for r in finished],
-                              [self._gbs.sfact_of(r.modes) for r in finished], want_prob=True,
+            self.ctx.finalize(self.state, self.pool, lo, hi, [r.modes for r in finished], want_prob=True,
                               prob_out=self.prob[slot, :nf], stream=self.stream)
             with torch.cuda.stream(self.stream):
                 self.host[slot, :nf].copy_(self.prob[slot, :nf], non_blocking=True)
@@ -162,11 +162,14 @@ class Server:
         self._stop = False
         self._thread: Optional[threading.Thread] = None
         self.latencies: List[float] = []
+        self.records: List[tuple] = []  # (rid, t_arrival, t_done) of completed requests
         self.completed = 0
         self.rejected = 0
         self.failed = 0
         self.steps = 0
         self.max_concurrent = 0
+        self.arrivals_in_flight = 0  # requests submitted while a step was on the device
+        self.memory_waits = 0        # admission attempts that found the pool too full
         self._t_first = None
         self._t_last = None
 
@@ -185,6 +188,8 @@ class Server:
                 f.set_exception(MemoryError(f"request needs {len(r.slices)} partial slots, pool has {self.pool_entries}"))
                 return f
             self._pending.append(r)
+            if self._steps:
+                self.arrivals_in_flight += 1
             if self._t_first is None:
                 self._t_first = r.t_arrival
         return f
@@ -207,13 +212,23 @@ class Server:
         if self._thread:
             self._thread.join(timeout)
 
+    def latencies_by_rid(self, skip: int = 0) -> List[float]:
+        """Latencies (s) of the completed requests numbered skip and later (the first `skip` are warm-up)."""
+        return [t1 - t0 for rid, t0, t1 in self.records if rid >= skip]
+
+    def span(self, skip: int = 0) -> float:
+        """Seconds from the arrival of the first request numbered >= skip to the last completion."""
+        recs = [r for r in self.records if r[0] >= skip]
+        return max(r[2] for r in recs) - min(r[1] for r in recs) if recs else float("nan")
+
     def stats(self) -> Dict[str, float]:
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
         span = (self._t_last - self._t_first) if (self._t_last and self._t_first) else float("nan")
         return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "mean_ms": float(lat.mean() * 1e3), "completed": self.completed, "rejected": self.rejected,
                 "failed": self.failed, "throughput_req_s": self.completed / span if span == span and span > 0 else 0.0,
-                "steps": self.steps, "max_concurrent": self.max_concurrent}
+                "steps": self.steps, "max_concurrent": self.max_concurrent,
+                "arrivals_in_flight": self.arrivals_in_flight, "memory_waits": self.memory_waits}
 
     # ------------------------------------------------------------ internals
     def _alloc_pool(self, need: int) -> int:
@@ -245,6 +260,7 @@ class Server:
             need = len(r.slices)
             off = self._alloc_pool(need) if need else 0
             if off < 0:
+                self.memory_waits += 1
                 break  # wait for device memory to free up
             self._pending.popleft()
             r.pool_off = off
@@ -273,20 +289,23 @@ class Server:
         for r in order:
             if len(finished) >= self.max_finish:
                 break
-            anti_starve = r is oldest and len(order) > 1
-            if budget <= 0 and not anti_starve:
+            # the oldest request gets one slice even when the budget is spent, then draws from the
+            # budget like the others
+            first_free = r is oldest and len(order) > 1
+            if budget <= 0 and not first_free:
                 continue
             used = 0.0
-            while r.next_slice < len(r.slices) and (anti_starve or (budget > 0 and (used < cap or used == 0.0))):
+            while r.next_slice < len(r.slices) and (first_free or (budget > 0 and (used < cap or used == 0.0))):
                 lo, hi = r.slices[r.next_slice]
                 w = r.work[r.next_slice]
                 jobs.append((r.modes, lo, hi, r.pool_off + r.next_slice))
                 r.next_slice += 1
                 r.remaining -= w
-                if anti_starve:
-                    break  # one slice outside the budget; the budget goes by remaining work
+                used += w  # the request's own share counts every slice
+                if first_free:
+                    first_free = False
+                    continue  # outside the step budget
                 budget -= w
-                used += w
             if r.next_slice == len(r.slices):
                 finished.append(r)
         if finished:
@@ -304,6 +323,7 @@ class Server:
             else:
                 r.t_done = now
                 self.latencies.append(now - r.t_arrival)
+                self.records.append((r.rid, r.t_arrival, now))
                 self.completed += 1
                 r.future.set_result(float(probs[i]))
             self._t_last = now
@@ -350,7 +370,9 @@ class FifoServer:
         self._lock = threading.Lock()
         self._stop = False
         self.latencies: List[float] = []
+        self.records: List[tuple] = []  # (rid, t_arrival, t_done)
         self.completed = 0
+        self._rid = 0
         self._t_first = None
         self._t_last = None
 
@@ -358,10 +380,14 @@ class FifoServer:
         f: Future = Future()
         with self._lock:
             t = time.perf_counter()
-            self._q.append((np.asarray(modes, dtype=np.int32), t, f))
+            self._q.append((np.asarray(modes, dtype=np.int32), t, f, self._rid))
+            self._rid += 1
             if self._t_first is None:
                 self._t_first = t
         return f
+
+    latencies_by_rid = Server.latencies_by_rid
+    span = Server.span
 
     def start(self):
         self._thread = threading.Thread(target=self._loop, daemon=True)
@@ -387,12 +413,13 @@ class FifoServer:
             if item is None:
                 time.sleep(0.0001)
                 continue
-            modes, t0, f = item
+            modes, t0, f, rid = item
             try:
                 p = self.ctx.prob_batch(self.state, [modes])
                 v = float(p.cpu().item())
                 now = time.perf_counter()
                 self.latencies.append(now - t0)
+                self.records.append((rid, t0, now))
                 self.completed += 1
                 self._t_last = now
                 f.set_result(v)

@@ -76,7 +76,6 @@ def test_pack_patterns():
     assert modes.tolist() == [1, 2, 3, 4, 5, 6] and off.tolist() == [0, 2, 2, 6]
     modes, off = gbs.pack_patterns(np.array([[0, 1], [2, 3]]))
     assert off.tolist() == [0, 2, 4]
-    assert gbs.sfact_of([1, 1, 2, 2, 2, 5]) == 2 * 6
 
 
 def test_photon_number_pmf_matches_oracle():

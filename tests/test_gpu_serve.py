@@ -41,17 +41,21 @@ def serve_all(ctx, st, pats, **kw):
 
 def test_served_match_oracle_and_alone(env):
     ctx, st, st_in = env
-    pats = make_requests(41, 48, [8, 10, 12, 14, 16, 18, 20, 22, 24, 26, 28])
+    pats = make_requests(41, 48, [8, 10, 12, 14, 16, 18, 20, 22, 24, 26, 28, 30, 32])
     mixed, stats = serve_all(ctx, st, pats, step_flops=2e9, max_slice=1024)
     assert stats["completed"] == len(pats) and stats["failed"] == 0 and stats["steps"] > 1
     # alone: each request through its own server run
     alone = np.array([serve_all(ctx, st, [p], step_flops=2e9, max_slice=1024)[0][0] for p in pats[:12]])
     assert np.array_equal(mixed[:12], alone)
-    # against the oracle (enumeration up to n = 24, long-double power trace above)
+    # against the oracle (enumeration up to n = 24, long-double power trace above; the first two of
+    # n >= 30, where the oracle takes 10-30 s per matrix)
     B = oracle.state_B(st_in.U, st_in.r)
+    big = 0
     for i, p in enumerate(pats):
-        if len(p) > 24 and i % 3:
-            continue
+        if len(p) >= 30:
+            big += 1
+            if big > 2:
+                continue
         h = oracle.haf_enum(oracle.pattern_matrix(B, p)) if len(p) <= 24 else oracle.haf_pt_ld(oracle.pattern_matrix(B, p))
         ref = abs(h) ** 2 / float(np.prod(np.cosh(st_in.r)))
         assert abs(mixed[i] - ref) <= 1e-9 * ref, (len(p), mixed[i], ref)
@@ -77,3 +81,46 @@ def test_fifo_server(env):
     out = np.array([f.result(timeout=60) for f in futs])
     srv.stop()
     assert np.array_equal(out, ctx.prob_batch(st, pats).cpu().numpy())
+
+
+def test_continuous_batching_arrivals_in_flight_small_pool(env):
+    """Requests arrive while earlier ones are on the GPU, and the partial pool (72 slots of 1024
+    subsets: an n = 32 request takes 64) admits only some at a time, so later ones wait for memory
+    and are admitted as slots free up. Every result equals the request served alone, bit for bit,
+    and the oracle to 1e-9."""
+    import threading
+    import time
+
+    from paper_1908_10070_amd import serve
+    ctx, st, st_in = env
+    pats = make_requests(44, 40, [8, 12, 16, 20, 24, 28, 30, 32])
+    pool = 72
+    be = serve.GpuBackend(ctx, st, pool_entries=pool)
+    srv = serve.Server(be, pool_entries=pool, step_flops=3e9, max_slice=1024, inflight=2).start()
+    futs = [None] * len(pats)
+
+    def feed():
+        for i, p in enumerate(pats):
+            futs[i] = srv.submit(p)
+            time.sleep(0.002)
+
+    th = threading.Thread(target=feed)
+    th.start()
+    th.join()
+    mixed = np.array([f.result(timeout=180) for f in futs])
+    srv.stop()
+    stats = srv.stats()
+    assert stats["completed"] == len(pats) and stats["failed"] == 0 and stats["rejected"] == 0
+    assert stats["arrivals_in_flight"] > 0, "no request arrived while a step was on the device"
+    assert stats["memory_waits"] > 0, "no request waited for pool memory"
+    assert stats["max_concurrent"] < len(pats)
+    for i in range(0, len(pats), 3):
+        alone = serve_all(ctx, st, [pats[i]], step_flops=3e9, max_slice=1024)[0][0]
+        assert alone == mixed[i], (len(pats[i]), alone, mixed[i])
+    B = oracle.state_B(st_in.U, st_in.r)
+    pref = 1.0 / float(np.prod(np.cosh(st_in.r)))
+    for i, p in enumerate(pats):
+        if len(p) > 24:
+            continue
+        ref = abs(oracle.haf_enum(oracle.pattern_matrix(B, p))) ** 2 * pref
+        assert abs(mixed[i] - ref) <= 1e-9 * ref, (len(p), mixed[i], ref)

@@ -145,3 +145,17 @@ def test_slice_plan_depends_only_on_n():
     s = serve.slice_plan(32, 4096)
     assert s[0] == (0, 4096) and s[-1][1] == 2 ** 16 - 1 and len(s) == 16
     assert all(a[1] == b[0] for a, b in zip(s, s[1:]))
+
+
+def test_oldest_request_draws_from_the_budget_after_its_free_slice(setup):
+    """The oldest request gets one slice outside the step budget and then competes for the rest like
+    the others (it is not capped at one slice per step when budget is left)."""
+    U, r, rng = setup
+    long = list(range(8))  # 15 slices of one subset each
+    be = FakeBackend(U, r)
+    srv = serve.Server(be, pool_entries=64, max_slice=1, step_flops=1e9, share=1.0)
+    srv.submit(long)
+    srv.submit([0, 1])
+    srv._admit()
+    jobs, finished = srv._build_step()
+    assert len(jobs) == 16 and len(finished) == 2
