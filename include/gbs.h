@@ -126,6 +126,20 @@ int haf_batch(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t batch, int
 int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_off_host,
                      const int32_t* n_host, int64_t batch, gbs_c128* haf_out_dev, void* stream);
 
+/* haf_batch for callers that cannot allocate memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same arguments, work items, kernels and summation
+ * order as haf_batch at the context's chunk sizes (so the same results, bit for bit), but the plan
+ * is built on the device and the plan, work counters and partial sums live in a static 32 MiB
+ * scratch array per device instead of the context's workspace; no device or pinned host memory is
+ * allocated, nothing is staged from the host, and the launches are eager (no graph). The scratch needs about 56 bytes per work item
+ * plus 36 per matrix (n = 24 at the built-in chunks: 11 items per matrix, so 4096 matrices take
+ * 2.7 MB); a call that needs more returns GBS_ENOMEM and enqueues nothing. All calls on one GPU
+ * share that GPU's scratch, which keeps the last call's contents (the work counters are cleared by
+ * a kernel at the start of every call): calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race and must be ordered by the caller. */
+int haf_batch_noalloc(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t batch, int64_t stride_elems,
+                      gbs_c128* haf_out_dev, void* stream);
+
 /* ------------------------------------------------------------ GBS state */
 
 /* Device bytes a state on m modes needs (B and W, m*m complex128 each, the m squeezing values and

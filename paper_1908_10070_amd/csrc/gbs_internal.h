@@ -136,6 +136,39 @@ void register_grid5_engines(EngineVariant* tab);
 void register_strip_engines(EngineVariant* tab);
 void register_tile_engines(EngineVariant* tab);
 
+// No-allocation hafnian path (haf_batch_noalloc): a uniform-n batch's plan is built on the device in
+// a static scratch array. Per engine launch g, every pattern has count items: item j of pattern p
+// covers [a + j chunk, min(b, a + (j + 1) chunk)) of the canonical subset order and writes partial
+// p * ipp + local_base + j; the launch's items are stored pattern by pattern from index first.
+constexpr int kNoallocMaxGroups = 8;
+struct NoallocGroup {
+  int64_t first;       // first item of this launch in the item array
+  int64_t a, b;        // the launch's range of one pattern's canonical subset order
+  int64_t chunk;       // subsets per item
+  int32_t count;       // items per pattern in this launch
+  int32_t local_base;  // partial index of the launch's first item within its pattern
+};
+struct NoallocPlanArgs {
+  NoallocGroup g[kNoallocMaxGroups];
+  int32_t n_groups;
+  int32_t n;
+  int32_t ipp;             // items (partials) per pattern
+  int32_t pad;
+  int64_t batch;
+  int64_t stride;          // elements between consecutive matrices
+  int64_t total_items;
+  PatternDesc* pats;
+  WorkItem* items;
+  int64_t* part_off;       // batch + 1
+  int32_t* nvec;
+  double* sfact;
+};
+// Device address of the no-allocation scratch on `device` (hipGetSymbolAddress, taken once per
+// device with that device current); nullptr with *err set if the lookup failed.
+void* noalloc_scratch(int device, hipError_t* err);
+size_t noalloc_scratch_bytes();
+void launch_noalloc_plan(const NoallocPlanArgs& a, hipStream_t s);
+
 // Host-side launchers (defined in gbs_kernels.hip).
 int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -164,34 +165,48 @@ struct ItemLists {
   std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
 };
 
-// Split [lo, hi) of pattern p into items: runs of subset sizes that share an engine variant
-// (engine_class), cut into chunks of chunk_small subsets (|Z| <= 8) or chunk_large (larger |Z|).
-void plan_range(const gbs_ctx* ctx, Plan& pl, ItemLists& L, int p, int n, int64_t lo, int64_t hi) {
-  if (hi <= lo) return;
+// The runs of subset sizes of a size-n pattern that share an engine variant (engine_class), in
+// increasing |Z|, each with its range [a, b) of the canonical order clipped to [lo, hi) and its chunk:
+// chunk_small subsets per item for |Z| <= 8, chunk_large above.
+struct ClassRun {
+  int cls;
+  int64_t a, b, chunk;
+};
+
+std::vector<ClassRun> class_runs(const gbs_ctx* ctx, int n, int64_t lo, int64_t hi) {
+  std::vector<ClassRun> out;
   const int k = n / 2;
   int64_t cs, cl;
   chunks_for(ctx, n, &cs, &cl);
-  // contiguous runs of subset sizes that share an engine variant
   for (int s_lo = 1; s_lo <= k;) {
     const int cls = engine_class(s_lo, k);
     int s_hi = s_lo;
     while (s_hi + 1 <= k && engine_class(s_hi + 1, k) == cls) ++s_hi;
     const int64_t a = std::max(lo, size_start(k, s_lo));
     const int64_t b = std::min(hi, size_start(k, s_hi + 1));
-    const int64_t chunk = s_hi <= 8 ? cs : cl;
-    std::vector<WorkItem>& out = L.cls[cls];
-    for (int64_t x = a; x < b; x += chunk) {
+    if (a < b) out.push_back(ClassRun{cls, a, b, s_hi <= 8 ? cs : cl});
+    s_lo = s_hi + 1;
+  }
+  return out;
+}
+
+// Split [lo, hi) of pattern p into items: the class runs cut into chunks; partial indices follow
+// the runs in increasing |Z|.
+void plan_range(const gbs_ctx* ctx, Plan& pl, ItemLists& L, int p, int n, int64_t lo, int64_t hi) {
+  if (hi <= lo) return;
+  for (const ClassRun& r : class_runs(ctx, n, lo, hi)) {
+    std::vector<WorkItem>& out = L.cls[r.cls];
+    for (int64_t x = r.a; x < r.b; x += r.chunk) {
       WorkItem w;
       w.lo = x;
-      w.hi = std::min(b, x + chunk);
+      w.hi = std::min(r.b, x + r.chunk);
       w.pattern = p;
       w.partial = (int32_t)pl.n_partials++;
       out.push_back(w);
     }
-    s_lo = s_hi + 1;
   }
   pl.nmax = std::max(pl.nmax, n);
-  pl.kmax = std::max(pl.kmax, k);
+  pl.kmax = std::max(pl.kmax, n / 2);
 }
 
 // Item order: launches with the biggest tiles first; within a launch larger n first, so long items
@@ -269,6 +284,40 @@ int ensure_pinned(gbs_ctx* ctx, int i, size_t bytes) {
   return GBS_OK;
 }
 
+// One engine launch: its variant, arguments, grid and LDS bytes.
+struct Launch {
+  int cls;
+  EngineArgs a;
+  int grid;
+  size_t lds;
+};
+
+// Launches for the plan's groups; ea holds the arguments common to all of them.
+int build_launches(gbs_ctx* ctx, const std::vector<Plan::Group>& groups, const EngineArgs& ea, const WorkItem* items,
+                   int32_t* counters, int persistent, std::vector<Launch>& launches) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Plan::Group& g = groups[gi];
+    Launch ln;
+    ln.cls = g.cls;
+    ln.a = ea;
+    ln.a.persistent = persistent;
+    ln.a.n_items = (int32_t)g.count;
+    ln.a.items = items + g.first;
+    ln.a.counter = counters + gi;
+    // every item of a variant has the same n: LDS sized for that n only (staged copy for n <= 32)
+    ln.a.nmax = std::max(g.n, 2);
+    ln.a.kmax = std::max(g.n / 2, 1);
+    ln.a.stage_A = g.n <= 32 ? 1 : 0;
+    ln.lds = engine_lds_bytes(g.cls, ln.a.nmax, ln.a.kmax, ln.a.stage_A);
+    if (ln.lds > kLdsBudget) return fail(ctx, GBS_EUNSUPPORTED, "plan needs %zu bytes of LDS", ln.lds);
+    const int per_cu = engine_blocks_per_cu(g.cls, ln.lds);
+    ln.grid = (int)g.count;
+    if (persistent) ln.grid = (int)std::min<int64_t>(g.count, (int64_t)ctx->ncu * per_cu);
+    launches.push_back(ln);
+  }
+  return GBS_OK;
+}
+
 // Copy the staged part of the plan to the device, launch the engine and the finalize kernel.
 int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_modes, const double2* A,
              int32_t m, const double* prefactor_dev, double* prob_out, double2* haf_out, gbs_partial* partial_out,
@@ -308,33 +357,11 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   ea.partials = reinterpret_cast<gbs_partial*>(ws + L.partials);
   ea.persistent = ctx->persistent;
 
-  struct Launch {
-    int cls;
-    EngineArgs a;
-    int grid;
-    size_t lds;
-  };
   std::vector<Launch> launches;
   int32_t* counters = reinterpret_cast<int32_t*>(ws + L.counter);
-  for (size_t gi = 0; gi < pl.groups.size(); ++gi) {
-    const Plan::Group& g = pl.groups[gi];
-    Launch ln;
-    ln.cls = g.cls;
-    ln.a = ea;
-    ln.a.n_items = (int32_t)g.count;
-    ln.a.items = reinterpret_cast<const WorkItem*>(ws + L.items) + g.first;
-    ln.a.counter = counters + gi;
-    // every item of a variant has the same n: LDS sized for that n only (staged copy for n <= 32)
-    ln.a.nmax = std::max(g.n, 2);
-    ln.a.kmax = std::max(g.n / 2, 1);
-    ln.a.stage_A = g.n <= 32 ? 1 : 0;
-    ln.lds = engine_lds_bytes(g.cls, ln.a.nmax, ln.a.kmax, ln.a.stage_A);
-    const int per_cu = engine_blocks_per_cu(g.cls, ln.lds);
-    if (ln.lds > kLdsBudget) return fail(ctx, GBS_EUNSUPPORTED, "plan needs %zu bytes of LDS", ln.lds);
-    ln.grid = (int)g.count;
-    if (ctx->persistent) ln.grid = (int)std::min<int64_t>(g.count, (int64_t)ctx->ncu * per_cu);
-    launches.push_back(ln);
-  }
+  rc = build_launches(ctx, pl.groups, ea, reinterpret_cast<const WorkItem*>(ws + L.items), counters, ctx->persistent,
+                      launches);
+  if (rc) return rc;
 
   FinalizeArgs fa{};
   fa.partials = ea.partials;
@@ -490,6 +517,12 @@ int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_
     return GBS_EHIP;
   }
   c->ncu = p.multiProcessorCount;
+  // device address of the no-allocation entry point's scratch on this device (device current)
+  hipError_t se = hipSuccess;
+  if (!noalloc_scratch(device, &se)) {
+    delete c;
+    return GBS_EHIP;
+  }
   bool ev_ok = true;
   for (int i = 0; i < gbs_ctx::kPinRing; ++i)
     ev_ok = ev_ok && hipEventCreateWithFlags(&c->pinned_ev[i], hipEventDisableTiming) == hipSuccess;
@@ -640,6 +673,117 @@ StateLayout state_layout(int m) {
 size_t gbs_state_bytes(int32_t m) {
   if (m <= 0 || m > 4096) return 0;
   return state_layout(m).total;
+}
+
+int haf_batch_noalloc(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t batch, int64_t stride_elems,
+                      gbs_c128* haf_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (batch < 0) return fail(ctx, GBS_EINVAL, "batch < 0");
+  if (n < 0 || n > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n = %d outside [0, %d]", n, GBS_N_MAX);
+  if (batch > 1 && stride_elems < (int64_t)n * n) return fail(ctx, GBS_EINVAL, "stride smaller than n*n");
+  if (batch == 0) return GBS_OK;
+  if (!haf_out_dev || (n > 0 && !A_dev)) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (batch > (int64_t)1 << 30) return fail(ctx, GBS_ERANGE, "batch too large");
+  DeviceGuard dg(ctx->device);
+  hipError_t se = hipSuccess;
+  unsigned char* scr = static_cast<unsigned char*>(noalloc_scratch(ctx->device, &se));
+  if (!scr) return fail(ctx, GBS_EHIP, "scratch address: %s", hipGetErrorString(se));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // the per-pattern template: one launch per class run, in the order run_plan uses (largest class
+  // first), partial indices in increasing |Z| as plan_range assigns them
+  const std::vector<ClassRun> runs = (n > 0 && n % 2 == 0) ? class_runs(ctx, n, 0, subset_count(n))
+                                                           : std::vector<ClassRun>();
+  NoallocPlanArgs na{};
+  std::vector<int32_t> local_base(runs.size());
+  int32_t ipp = 0;
+  for (size_t r = 0; r < runs.size(); ++r) {
+    local_base[r] = ipp;
+    ipp += (int32_t)((runs[r].b - runs[r].a + runs[r].chunk - 1) / runs[r].chunk);
+  }
+  if (runs.size() > (size_t)kNoallocMaxGroups) return fail(ctx, GBS_EUNSUPPORTED, "too many engine launches");
+  std::vector<Plan::Group> groups;
+  int64_t first = 0;
+  for (size_t q = runs.size(); q-- > 0;) {  // classes increase with |Z|: largest first
+    const ClassRun& r = runs[q];
+    NoallocGroup& G = na.g[groups.size()];
+    G.first = first;
+    G.a = r.a;
+    G.b = r.b;
+    G.chunk = r.chunk;
+    G.count = (int32_t)((r.b - r.a + r.chunk - 1) / r.chunk);
+    G.local_base = local_base[q];
+    Plan::Group pg;
+    pg.cls = r.cls;
+    pg.n = n;
+    pg.first = first;
+    pg.count = batch * G.count;
+    groups.push_back(pg);
+    first += pg.count;
+  }
+  na.n_groups = (int32_t)groups.size();
+  na.n = n;
+  na.ipp = ipp;
+  na.batch = batch;
+  na.stride = stride_elems;
+  na.total_items = first;
+  if (first > INT32_MAX || batch * (int64_t)ipp > INT32_MAX)
+    return fail(ctx, GBS_ERANGE, "batch too large for the no-allocation path");
+
+  // scratch layout: counters, patterns, items, partial offsets, n, prod s!, partials
+  size_t off = 0;
+  const size_t o_cnt = off;
+  off += al(sizeof(int32_t) * std::max<size_t>(groups.size(), 1));
+  const size_t o_pats = off;
+  off += al(sizeof(PatternDesc) * (size_t)batch);
+  const size_t o_items = off;
+  off += al(sizeof(WorkItem) * (size_t)first);
+  const size_t o_poff = off;
+  off += al(sizeof(int64_t) * (size_t)(batch + 1));
+  const size_t o_n = off;
+  off += al(sizeof(int32_t) * (size_t)batch);
+  const size_t o_sf = off;
+  off += al(sizeof(double) * (size_t)batch);
+  const size_t o_part = off;
+  off += al(sizeof(gbs_partial) * (size_t)(batch * ipp));
+  if (off > noalloc_scratch_bytes())
+    return fail(ctx, GBS_ENOMEM, "the call needs %zu bytes of the no-allocation scratch, which holds %zu", off,
+                noalloc_scratch_bytes());
+  na.pats = reinterpret_cast<PatternDesc*>(scr + o_pats);
+  na.items = reinterpret_cast<WorkItem*>(scr + o_items);
+  na.part_off = reinterpret_cast<int64_t*>(scr + o_poff);
+  na.nvec = reinterpret_cast<int32_t*>(scr + o_n);
+  na.sfact = reinterpret_cast<double*>(scr + o_sf);
+
+  EngineArgs ea{};
+  ea.A = reinterpret_cast<const double2*>(A_dev);
+  ea.modes = nullptr;
+  ea.m = 0;
+  ea.pats = na.pats;
+  ea.partials = reinterpret_cast<gbs_partial*>(scr + o_part);
+  std::vector<Launch> launches;
+  int32_t* counters = reinterpret_cast<int32_t*>(scr + o_cnt);
+  int rc = build_launches(ctx, groups, ea, na.items, counters, 1, launches);
+  if (rc) return rc;
+  FinalizeArgs fa{};
+  fa.partials = ea.partials;
+  fa.part_lo = na.part_off;
+  fa.part_hi = na.part_off + 1;
+  fa.n = na.nvec;
+  fa.sfact = na.sfact;
+  fa.batch = batch;
+  fa.haf_out = reinterpret_cast<double2*>(haf_out_dev);
+
+  if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->done_ev, 0));
+  launch_noalloc_plan(na, s);
+  if (!launches.empty()) launch_reset(counters, (int)launches.size(), s);
+  for (const Launch& ln : launches) launch_engine(ln.cls, ln.a, ln.grid, ln.lds, s);
+  launch_finalize(fa, s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
+  ctx->done_recorded = true;
+  return GBS_OK;
 }
 
 int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const double* r_host, void* state_mem_dev,

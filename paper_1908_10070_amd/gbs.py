@@ -25,7 +25,7 @@ GBS_MARGINAL_KMAX = 20
 EXPORTS = [
     "gbs_ctx_create", "gbs_ctx_destroy", "gbs_ctx_set_workspace", "gbs_ctx_workspace_needed", "gbs_status_str",
     "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops",
-    "haf_batch", "haf_batch_varlen", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
+    "haf_batch", "haf_batch_varlen", "haf_batch_noalloc", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
     "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
     "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step",
 ]
@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
         "gbs_haf_flops": (ctypes.c_double, [i32]),
         "haf_batch": (ctypes.c_int, [vp, dp, i32, i64, i64, dp, vp]),
         "haf_batch_varlen": (ctypes.c_int, [vp, dp, dp, dp, i64, dp, vp]),
+        "haf_batch_noalloc": (ctypes.c_int, [vp, dp, i32, i64, i64, dp, vp]),
         "gbs_state_create": (ctypes.c_int, [vp, dp, i32, dp, dp, sz, vp, ctypes.POINTER(vp)]),
         "gbs_state_destroy": (ctypes.c_int, [vp]),
         "gbs_state_info": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
@@ -271,6 +272,19 @@ class Context:
         if out is None:
             out = torch.empty(b, dtype=torch.complex128, device=A.device)
         self._run(lib().haf_batch, _t_ptr(A), n, b, n * n, _t_ptr(out), _stream_ptr(stream))
+        return out
+
+    def haf_batch_noalloc(self, A, out, stream=None):
+        """haf_batch through the entry point that allocates nothing (static device scratch); `out` is
+        required, and the binding allocates nothing either."""
+        import torch
+        if not (isinstance(A, torch.Tensor) and A.is_cuda and A.dtype == torch.complex128 and A.ndim == 3
+                and A.is_contiguous() and A.shape[1] == A.shape[2]):
+            raise TypeError("A must be a contiguous (batch, n, n) complex128 CUDA tensor")
+        if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous() and out.numel() == A.shape[0]):
+            raise TypeError("out must be a contiguous complex128 CUDA tensor with one entry per matrix")
+        b, n = A.shape[0], A.shape[1]
+        self._check(lib().haf_batch_noalloc(self.handle, _t_ptr(A), n, b, n * n, _t_ptr(out), _stream_ptr(stream)))
         return out
 
     def haf_batch_varlen(self, A_flat, elem_off, ns, out=None, stream=None):
