@@ -203,15 +203,18 @@ def extras(gbs, torch, dev, args):
     t = _timed(lambda: ctx.prob_batch(st3, mix), reps=2)
     capacity = len(mix) / t
     srv_out = {"batched_capacity_req_s": capacity,
-               "note": "capacity = 2000 mixed requests in one gbs_prob_batch call; latency = arrival to result on "
-                       "the host; statistics over the requests after the warm-up ones"}
+               "note": "capacity = 2000 mixed requests in one gbs_prob_batch call; latency = scheduled arrival to "
+                       "result on the host; statistics over the requests after the warm-up ones; Python's cyclic "
+                       "garbage collector is held off during both servers' streams (serve.hold_gc)"}
     for load in args.serve_loads:
         rate = load * capacity
         arr, pats = inputs.config4_requests(nreq + warm, rate)
         # every step has a new shape, so the server's context captures no graphs (nothing to replay)
         sctx = gbs.Context(0, use_graph=False)
-        be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16)
-        cont = serve.Server(be, pool_entries=1 << 16, step_flops=args.step_flops, max_slice=4096).start()
+        be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16, lanes=1)
+        be.warmup(range(8, 33, 2))
+        cont = serve.Server(be, pool_entries=1 << 16, step_flops=args.step_flops, max_slice=4096,
+                            hold_gc=True).start()
         serve.replay(cont, arr, pats)
         cont.stop(timeout=600)
         lat_c = np.array(cont.latencies_by_rid(warm)) * 1e3
@@ -222,9 +225,14 @@ def extras(gbs, torch, dev, args):
                               "steps": cont.steps}}
         if not args.no_fifo:
             pp = gbs.Context(0, use_graph=False, persistent=False)
+            for n in range(8, 33, 2):  # load every kernel the stream uses
+                pp.prob_batch(st3, [list(range(n))])
+            torch.cuda.synchronize()
             fifo = serve.FifoServer(pp, st3).start()
+            serve.hold_gc()
             serve.replay(fifo, arr, pats)
             fifo.stop(timeout=900)
+            serve.release_gc()
             lat_f = np.array(fifo.latencies_by_rid(warm)) * 1e3
             res["fifo_per_pattern"] = {"p50_ms": float(np.percentile(lat_f, 50)),
                                        "p99_ms": float(np.percentile(lat_f, 99)), "mean_ms": float(lat_f.mean()),
@@ -318,6 +326,10 @@ def main():
     for _ in range(args.warmup):
         ctx.haf_batch(A, out=out)
     torch.cuda.synchronize()
+    # no cyclic-GC pause inside the timed region (it would stall the host that feeds the device)
+    import gc
+    gc.collect()
+    gc.disable()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     step_ms = []
@@ -331,6 +343,7 @@ def main():
         step_ms.append((e0, e1))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     gpu_ms = [a.elapsed_time(b) for a, b in step_ms]
     ms_per_step = wall * 1e3 / args.steps
     value = batch / (wall / args.steps)
@@ -359,7 +372,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms,
-                     "kernel_ms_median": float(np.median(gpu_ms)),
+                     "kernel_ms_median": float(np.median(gpu_ms)), "kernel_ms_min": float(np.min(gpu_ms)),
+                     "kernel_ms_max": float(np.max(gpu_ms)),
                      "algorithmic_bytes_per_launch": batch * n * n * 16 + batch * 16},
     }
 

@@ -376,11 +376,50 @@ __device__ __forceinline__ void extend_traces(double* tw, int d) {
   }
 }
 
-// Coefficient recursion for the buffered subsets (one lane each) and the compensated sum. With
-// EXT, traces beyond 2|Z| (which the engine leaves unformed) are first extended from the first 2|Z|.
+// a + b = s + e exactly (Knuth's TwoSum); the same (s, e) whichever operand comes first.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// One level of the compensated lane tree: (s, c) += the partner lane's (ps, pc). Both lanes of a pair
+// end with the same values.
+__device__ __forceinline__ void tree_add(double& s, double& c, double ps, double pc) {
+  double t, e;
+  two_sum(s, ps, t, e);
+  c = (c + pc) + e;
+  s = t;
+}
+
+// Partner exchange across the two rows of 16 lanes in each half-wave (lane l ^ 16), by
+// v_permlane16_swap of the value with itself.
+__device__ __forceinline__ double xrow16(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const bool odd_row = (lane >> 4) & 1;
+  return odd_row ? join(lo[0], hi[0]) : join(lo[1], hi[1]);
+}
+
+// Compensated sum over lanes 0..31 of the per-lane pairs (s, c): a fixed tree of TwoSum steps
+// (partners lane ^ 1, lane ^ 2, the mirror lane within 8, the other half of the row of 16, the other
+// row); lanes 0..31 end with the total. The order depends only on the lane numbers.
+__device__ __forceinline__ void lane_tree_sum32(double& s, double& c, int lane) {
+  tree_add(s, c, dpp<kDppXor1>(s), dpp<kDppXor1>(c));
+  tree_add(s, c, dpp<kDppXor2>(s), dpp<kDppXor2>(c));
+  tree_add(s, c, dpp<kDppHalfMirror>(s), dpp<kDppHalfMirror>(c));
+  tree_add(s, c, dpp<kDppXor8>(s), dpp<kDppXor8>(c));
+  tree_add(s, c, xrow16(s, lane), xrow16(c, lane));
+}
+
+// Coefficient recursion for the buffered subsets (one lane each) and the compensated sum of their
+// signed terms, added to the running sum (sr + cr, si + ci) held by every lane. With EXT, traces
+// beyond 2|Z| (which the engine leaves unformed) are first extended from the first 2|Z|.
 template <int K, bool EXT = false>
-__device__ __forceinline__ void combine_batch(double* trw, const int32_t* sz, double2* terms, int cnt, int lane,
-                                              double& sr, double& si, double& cr, double& ci) {
+__device__ __forceinline__ void combine_batch(double* trw, const int32_t* sz, int cnt, int lane, double& sr,
+                                              double& si, double& cr, double& ci) {
+  double2 ck = make_double2(0.0, 0.0);
   if (lane < cnt) {
     if constexpr (EXT) {
       const int d = 2 * sz[lane];
@@ -403,22 +442,22 @@ __device__ __forceinline__ void combine_batch(double* trw, const int32_t* sz, do
       const double iq = kInv.v[q];
       c[q] = make_double2(ar * iq, ai * iq);
     }
-    double2 ck = c[K];
+    ck = c[K];
     if ((K - sz[lane]) & 1) {
       ck.x = -ck.x;
       ck.y = -ck.y;
     }
-    terms[lane] = ck;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (lane == 0) {
-    for (int u = 0; u < cnt; ++u) {
-      neumaier(sr, cr, terms[u].x);
-      neumaier(si, ci, terms[u].y);
-    }
-  }
+  // the batch's terms (zero beyond cnt) summed over lanes 0..31 with compensation, then added to the
+  // running sums (lanes 0..31 hold the same values; the engines read lane 0's)
+  static_assert(kWaveG == 32, "the lane tree covers 32 lanes");
+  double br = ck.x, bcr = 0.0, bi = ck.y, bci = 0.0;
+  lane_tree_sum32(br, bcr, lane);
+  lane_tree_sum32(bi, bci, lane);
+  neumaier(sr, cr, br);
+  neumaier(si, ci, bi);
+  cr += bcr;
+  ci += bci;
 }
 
 __device__ __forceinline__ void wave_sync() {

@@ -15,6 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <utility>
 
 #include "gbs_engine_common.h"
@@ -422,19 +425,31 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
 }
 
 static void allow_lds(int cls) {
-  static bool done[kEngineClasses] = {};
-  if (cls < 0 || cls >= kEngineClasses || done[cls]) return;
+  static std::atomic<bool> done[kEngineClasses] = {};
+  if (cls < 0 || cls >= kEngineClasses || done[cls].load(std::memory_order_acquire)) return;
   (void)hipFuncSetAttribute(variant(cls).fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  done[cls] = true;
+  done[cls].store(true, std::memory_order_release);
 }
 
+// Workgroups per CU from the occupancy API, cached per (variant, LDS bytes): every call of the
+// library sizes its persistent grids with it.
 int engine_blocks_per_cu(int cls, size_t lds) {
   const EngineVariant v = variant(cls);
   if (!v.fn) return 1;
+  static std::mutex mu;
+  static std::map<std::pair<int, size_t>, int> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({cls, lds});
+    if (it != cache.end()) return it->second;
+  }
   allow_lds(cls);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.fn, v.threads, lds) != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
+  nb = nb > 0 ? nb : 1;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[{cls, lds}] = nb;
+  return nb;
 }
 
 void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream_t s) {

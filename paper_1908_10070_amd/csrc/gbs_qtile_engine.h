@@ -194,7 +194,7 @@ __device__ void qtile_range(const PatternView& P, int64_t lo, int64_t hi, int32_
       }
     }
     __syncthreads();
-    if (w == 0) combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    if (w == 0) combine_batch<K>(trw, sz, cnt, lane, sr, si, cr, ci);
     __syncthreads();
   }
 }

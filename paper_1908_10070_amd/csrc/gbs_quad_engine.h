@@ -320,7 +320,7 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
         eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
     }
     wave_sync();
-    combine_batch<K, (K > 4)>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    combine_batch<K, (K > 4)>(trw, sz, cnt, lane, sr, si, cr, ci);
     wave_sync();
   }
 }

@@ -61,19 +61,16 @@ struct gbs_ctx {
   void* ws = nullptr;        // caller-owned workspace
   size_t ws_bytes = 0;
   size_t ws_needed = 0;      // what the last call that found it too small needed
-  // ring of pinned staging buffers: a call waits only for the copy of the call kPinRing calls back
-  // (a ring of four measured 3% slower on the batched n = 24 launch than this one)
-  static constexpr int kPinRing = 2;
+  // ring of pinned staging buffers: a call reuses a buffer once the copy from it (kPinRing calls
+  // back) has run. Six let a caller keep three two-call steps in flight without waiting. All of them
+  // are (re)allocated together, at the first call and whenever a call needs more: pinned allocation
+  // in the middle of a stream of calls stalls the device, so it must not happen in steady state.
+  static constexpr int kPinRing = 6;
   void* pinned[kPinRing] = {};
-  size_t pinned_bytes[kPinRing] = {};
+  size_t pinned_bytes = 0;  // every buffer has this size
   hipEvent_t pinned_ev[kPinRing] = {};
   bool pinned_used[kPinRing] = {};
   int pin_idx = 0;
-  int next_pin() {
-    const int i = pin_idx;
-    pin_idx = (pin_idx + 1) % kPinRing;
-    return i;
-  }
   hipEvent_t done_ev = nullptr;
   bool done_recorded = false;
   hipStream_t cap_stream = nullptr;
@@ -269,18 +266,26 @@ int ensure_ws(gbs_ctx* ctx, size_t bytes) {
   return fail(ctx, GBS_ENOMEM, "workspace of %zu bytes is smaller than the %zu the call needs", ctx->ws_bytes, bytes);
 }
 
-int ensure_pinned(gbs_ctx* ctx, int i, size_t bytes) {
-  if (ctx->pinned_bytes[i] >= bytes) return GBS_OK;
-  if (ctx->pinned[i]) {
-    HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[i]));
-    HIPCHK(ctx, hipHostFree(ctx->pinned[i]));
-    ctx->pinned[i] = nullptr;
-    ctx->pinned_bytes[i] = 0;
+// A pinned staging buffer of at least `bytes` for this call (index in *out): the next one in the
+// ring, after its previous copy has run.
+int acquire_pin(gbs_ctx* ctx, size_t bytes, int* out) {
+  if (ctx->pinned_bytes < bytes) {
+    // grow every buffer together (once their copies have run): 2x headroom, at least 1 MiB
+    const size_t nb = std::max(std::max(bytes, ctx->pinned_bytes) * 2, size_t(1) << 20);
+    for (int i = 0; i < gbs_ctx::kPinRing; ++i) {
+      if (ctx->pinned_used[i]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[i]));
+      if (ctx->pinned[i]) (void)hipHostFree(ctx->pinned[i]);
+      ctx->pinned[i] = nullptr;
+    }
+    ctx->pinned_bytes = 0;
+    for (int i = 0; i < gbs_ctx::kPinRing; ++i)
+      HIPCHK(ctx, hipHostMalloc(&ctx->pinned[i], nb, hipHostMallocDefault));
+    ctx->pinned_bytes = nb;
   }
-  size_t nb = std::max(bytes, ctx->pinned_bytes[i] * 2);
-  nb = std::max(nb, size_t(1) << 20);
-  HIPCHK(ctx, hipHostMalloc(&ctx->pinned[i], nb, hipHostMallocDefault));
-  ctx->pinned_bytes[i] = nb;
+  const int pi = ctx->pin_idx;
+  ctx->pin_idx = (pi + 1) % gbs_ctx::kPinRing;
+  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
+  *out = pi;
   return GBS_OK;
 }
 
@@ -326,10 +331,9 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   const Layout L = layout_for(pl, n_modes);
   int rc = ensure_ws(ctx, L.total);
   if (rc) return rc;
-  // stage into the next pinned buffer (wait until its previous copy has finished)
-  const int pi = ctx->next_pin();
-  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
-  rc = ensure_pinned(ctx, pi, L.staged_bytes);
+  // stage into a free pinned buffer
+  int pi = 0;
+  rc = acquire_pin(ctx, L.staged_bytes, &pi);
   if (rc) return rc;
   unsigned char* h = static_cast<unsigned char*>(ctx->pinned[pi]);
   const size_t base = L.modes;
@@ -801,9 +805,8 @@ int gbs_state_create(gbs_ctx* ctx, const gbs_c128* U_dev, int32_t m, const doubl
   DeviceGuard dg(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   // r goes through the context's pinned staging ring
-  const int pi = ctx->next_pin();
-  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
-  int rc = ensure_pinned(ctx, pi, sizeof(double) * m);
+  int pi = 0;
+  int rc = acquire_pin(ctx, sizeof(double) * m, &pi);
   if (rc) return rc;
   std::memcpy(ctx->pinned[pi], r_host, sizeof(double) * m);
   gbs_state* st = new gbs_state();
@@ -977,9 +980,8 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_
   const Layout L = layout_for(pl, 0);
   int rc = ensure_ws(ctx, L.total);
   if (rc) return rc;
-  const int pi = ctx->next_pin();
-  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
-  rc = ensure_pinned(ctx, pi, L.staged_bytes);
+  int pi = 0;
+  rc = acquire_pin(ctx, L.staged_bytes, &pi);
   if (rc) return rc;
   unsigned char* h = static_cast<unsigned char*>(ctx->pinned[pi]);
   const size_t base = L.modes;
@@ -1250,9 +1252,8 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
   if (extra_dev) *extra_dev = ws + o_extra;
   if (!q_out_dev) q_out_dev = reinterpret_cast<double*>(ws + o_extra);
 
-  const int pi = ctx->next_pin();
-  if (ctx->pinned_used[pi]) HIPCHK(ctx, hipEventSynchronize(ctx->pinned_ev[pi]));
-  rc = ensure_pinned(ctx, pi, stage_bytes);
+  int pi = 0;
+  rc = acquire_pin(ctx, stage_bytes, &pi);
   if (rc) return rc;
   unsigned char* hp = static_cast<unsigned char*>(ctx->pinned[pi]);
   auto put = [&](size_t o, const void* src, size_t bytes) {

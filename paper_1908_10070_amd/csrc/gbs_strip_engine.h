@@ -411,7 +411,7 @@ __device__ void strip_range(const PatternView& P, int64_t lo, int64_t hi, int32_
         eval_strip<K, TH>(P, pl, 2 * s, trw, u, park, lane);
     }
     wave_sync();
-    combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    combine_batch<K>(trw, sz, cnt, lane, sr, si, cr, ci);
     wave_sync();
   }
 }

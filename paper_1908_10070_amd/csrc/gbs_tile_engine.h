@@ -151,7 +151,7 @@ __device__ void tile_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       }
     }
     __syncthreads();
-    if (w == 0) combine_batch<K>(trw, sz, terms, cnt, lane, sr, si, cr, ci);
+    if (w == 0) combine_batch<K>(trw, sz, cnt, lane, sr, si, cr, ci);
     __syncthreads();
   }
 }

@@ -254,6 +254,11 @@ class Context:
     def set_tuning(self, n: int, chunk_small: int, chunk_large: int):
         self._check(lib().gbs_ctx_set_tuning(self.handle, int(n), int(chunk_small), int(chunk_large)))
 
+    def _copy_tuning_from(self, other: "Context"):
+        """The launch-shape table of another context (every n it has an entry for)."""
+        for n in range(0, GBS_N_MAX + 1):
+            self.set_tuning(n, *other.get_tuning(n))
+
     def get_tuning(self, n: int) -> Tuple[int, int]:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().gbs_ctx_get_tuning(self.handle, int(n), ctypes.byref(a), ctypes.byref(b)))
@@ -353,17 +358,19 @@ class Context:
         if len(lo) != b or len(hi) != b:
             raise ValueError("one (lo, hi) pair per pattern")
         oi = None if out_idx is None else np.ascontiguousarray(out_idx, dtype=np.int64)
-        rows = b if oi is None else (int(oi.max()) + 1 if len(oi) else 0)
+        rows = b if oi is None or partials_out is not None else (int(oi.max()) + 1 if len(oi) else 0)
         if partials_out is None:
             partials_out = torch.empty((max(rows, 1), 4), dtype=torch.float64, device=self.torch_device)
-        elif partials_out.shape[0] < rows:
-            raise ValueError("partials_out too small for out_idx")
+        elif oi is not None and len(oi) and (int(oi.max()) >= partials_out.shape[0] or int(oi.min()) < 0):
+            raise ValueError("out_idx outside partials_out")
+        elif oi is None and partials_out.shape[0] < b:
+            raise ValueError("partials_out too small")
         self._run(lib().gbs_prob_slices, state.handle, _np_ptr(modes), _np_ptr(offsets), _np_ptr(lo), _np_ptr(hi), b,
                   _t_ptr(partials_out), _np_ptr(oi), _stream_ptr(stream))
         return partials_out
 
     def finalize(self, state: Optional[State], partials, part_lo, part_hi, patterns, want_prob=True,
-                 prob_out=None, haf_out=None, stream=None):
+                 prob_out=None, haf_out=None, want_haf=True, stream=None):
         """Pattern b = compensated sum of partials[part_lo[b]:part_hi[b]] -> (prob, haf) tensors; the
         patterns (mode lists) give n and, in the library, the prod_j s_j! divisor."""
         import torch
@@ -377,7 +384,7 @@ class Context:
             raise ValueError("partial range beyond the partials tensor")
         if want_prob and prob_out is None:
             prob_out = torch.empty(b, dtype=torch.float64, device=self.torch_device)
-        if haf_out is None:
+        if want_haf and haf_out is None:
             haf_out = torch.empty(b, dtype=torch.complex128, device=self.torch_device)
         self._run(lib().gbs_finalize, state.handle if state is not None else None, _t_ptr(partials), _np_ptr(lo),
                   _np_ptr(hi), _np_ptr(modes), _np_ptr(offsets), b, _t_ptr(prob_out) if want_prob else None,

@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import threading
 import time
 from concurrent.futures import Future
@@ -66,6 +67,18 @@ class Request:
     t_done: float = 0.0
 
 
+def hold_gc():
+    """Collect once, freeze what is alive and switch automatic collection off."""
+    gc.collect()
+    gc.freeze()
+    gc.disable()
+
+
+def release_gc():
+    gc.enable()
+    gc.unfreeze()
+
+
 class SliceBackend:
     """What the server needs from the device. GpuBackend is the real one; tests use fakes.
 
@@ -89,16 +102,32 @@ class SliceBackend:
 
 
 class GpuBackend(SliceBackend):
-    """libgbs on one device: slices into a device partial pool, one finalize launch per step."""
+    """libgbs on one device: slices into a device partial pool, one finalize launch per step.
 
-    def __init__(self, ctx, state, pool_entries: int, max_finish: int = 4096, ring: int = 4, stream=None):
+    Consecutive steps go round-robin to `lanes` (context, stream) pairs, so one step's kernels can
+    start while the previous step's last kernels drain (measured: no gain at two lanes on the served
+    mix, whose steps already fill the device, so one lane is the default). Each context has its own workspace; the
+    partial pool and the state are shared (requests own disjoint pool slots). A step's finalize waits
+    for the previous step's slices (on the other stream): a request's slices are all in that step or
+    earlier ones, and earlier steps on either stream complete before it in stream order."""
+
+    def __init__(self, ctx, state, pool_entries: int, max_finish: int = 4096, ring: int = 8, stream=None,
+                 lanes: int = 1):
         import torch
         from . import gbs
         self._gbs = gbs
         self.ctx = ctx
         self.state = state
         self.torch = torch
-        self.stream = stream or torch.cuda.Stream(device=ctx.torch_device)
+        streams = [stream or torch.cuda.Stream(device=ctx.torch_device)]
+        ctxs = [ctx]
+        for _ in range(1, max(1, lanes)):
+            streams.append(torch.cuda.Stream(device=ctx.torch_device))
+            ctxs.append(gbs.Context(ctx.device, use_graph=False))
+            ctxs[-1]._copy_tuning_from(ctx)
+        self.lanes = list(zip(ctxs, streams))
+        self._lane = 0
+        self._prev_slices = None  # event after the previous step's slices
         self.pool = torch.zeros((pool_entries, 4), dtype=torch.float64, device=ctx.torch_device)
         self.ring = ring
         self.max_finish = max_finish
@@ -106,28 +135,58 @@ class GpuBackend(SliceBackend):
         self.host = torch.zeros((ring, max_finish), dtype=torch.float64).pin_memory()
         self._slot = 0
 
+    @property
+    def stream(self):
+        return self.lanes[0][1]
+
+    def warmup(self, sizes):
+        """One pattern of every size in `sizes` through each lane, so the first real steps do not pay
+        for loading kernels and allocating staging memory."""
+        for ctx, stream in self.lanes:
+            for n in sizes:
+                ctx.prob_batch(self.state, [list(range(n))], stream=stream)
+        self.torch.cuda.synchronize()
+
     def haf_flops(self, n: int) -> float:
         return self._gbs.haf_flops(n) if n > 0 and n % 2 == 0 else 0.0
 
+    @staticmethod
+    def _pack(mode_lists):
+        lens = np.fromiter((len(m) for m in mode_lists), dtype=np.int64, count=len(mode_lists))
+        offsets = np.zeros(len(mode_lists) + 1, dtype=np.int64)
+        np.cumsum(lens, out=offsets[1:])
+        modes = np.concatenate(mode_lists) if len(mode_lists) else np.zeros(0, np.int32)
+        return np.ascontiguousarray(modes, dtype=np.int32), offsets
+
     def launch_step(self, jobs, finished):
         torch = self.torch
+        ctx, stream = self.lanes[self._lane]
+        self._lane = (self._lane + 1) % len(self.lanes)
         if jobs:
-            self.ctx.prob_slices(self.state, [j[0] for j in jobs], [j[1] for j in jobs], [j[2] for j in jobs],
-                                 partials_out=self.pool, out_idx=[j[3] for j in jobs], stream=self.stream)
+            packed = self._pack([j[0] for j in jobs])
+            rng = np.array([(j[1], j[2], j[3]) for j in jobs], dtype=np.int64).reshape(-1, 3)
+            ctx.prob_slices(self.state, packed, rng[:, 0], rng[:, 1], partials_out=self.pool, out_idx=rng[:, 2],
+                            stream=stream)
+        prev = self._prev_slices
+        ev_slices = torch.cuda.Event()
+        ev_slices.record(stream)
+        self._prev_slices = ev_slices
         slot = self._slot
         self._slot = (self._slot + 1) % self.ring
         nf = len(finished)
         if nf > self.max_finish:
             raise ValueError("too many requests finishing in one step")
         if nf:
+            if prev is not None:
+                stream.wait_event(prev)
             lo = [r.pool_off for r in finished]
             hi = [r.pool_off + len(r.slices) for r in finished]
-            self.ctx.finalize(self.state, self.pool, lo, hi, [r.modes for r in finished], want_prob=True,
-                              prob_out=self.prob[slot, :nf], stream=self.stream)
-            with torch.cuda.stream(self.stream):
+            ctx.finalize(self.state, self.pool, lo, hi, self._pack([r.modes for r in finished]), want_prob=True,
+                         prob_out=self.prob[slot, :nf], want_haf=False, stream=stream)
+            with torch.cuda.stream(stream):
                 self.host[slot, :nf].copy_(self.prob[slot, :nf], non_blocking=True)
         ev = torch.cuda.Event()
-        ev.record(self.stream)
+        ev.record(stream)
         return (ev, slot, nf)
 
     def done(self, handle) -> bool:
@@ -141,10 +200,17 @@ class GpuBackend(SliceBackend):
 class Server:
     """Continuous batching over a SliceBackend. Thread-safe submit(); run in a background thread."""
 
-    def __init__(self, backend: SliceBackend, pool_entries: int, max_active: int = 1024,
-                 step_flops: float = 1e11, share: float = 0.5, inflight: int = 2, max_slice: int = 4096,
-                 max_finish: int = 4096):
+    def __init__(self, backend: SliceBackend, pool_entries: int, max_active: int = 8192,
+                 step_flops: float = 1e11, share: float = 0.5, inflight: int = 3, max_slice: int = 4096,
+                 max_finish: int = 4096, hold_gc: bool = False):
+        """hold_gc: while the server runs, freeze the objects alive at start() and switch off Python's
+        cyclic garbage collector (switched back on at stop()). Its full collections pause every
+        thread for tens of milliseconds once tens of thousands of requests and futures are alive,
+        and the device idles meanwhile; a serving process that does not create reference cycles
+        loses nothing by deferring them."""
         self.b = backend
+        self.hold_gc = hold_gc
+        self._gc_was_enabled = None
         self.pool_entries = pool_entries
         self.max_active = max_active
         self.step_flops = step_flops
@@ -170,15 +236,20 @@ class Server:
         self.max_concurrent = 0
         self.arrivals_in_flight = 0  # requests submitted while a step was on the device
         self.memory_waits = 0        # admission attempts that found the pool too full
+        self.host_build_s = 0.0      # host time building steps (scheduling)
+        self.host_launch_s = 0.0     # host time enqueueing steps (marshalling, planning, staging)
         self._t_first = None
         self._t_last = None
 
     # ------------------------------------------------------------ public API
-    def submit(self, modes: Sequence[int]) -> Future:
+    def submit(self, modes: Sequence[int], t_arrival: Optional[float] = None) -> Future:
+        """Queue a request; t_arrival (time.perf_counter() seconds) is when it arrived, default now:
+        latency is measured from it."""
         f: Future = Future()
-        m = np.asarray(modes, dtype=np.int32)
+        m = np.ascontiguousarray(modes, dtype=np.int32)
+        t = time.perf_counter() if t_arrival is None else t_arrival
         with self._lock:
-            r = Request(self._rid, m, len(m), time.perf_counter(), f)
+            r = Request(self._rid, m, len(m), t, f)
             self._rid += 1
             r.slices = slice_plan(r.n, self.max_slice)
             r.work = [subset_flops(r.n, lo, hi, self._haf_flops) for lo, hi in r.slices]
@@ -195,6 +266,8 @@ class Server:
         return f
 
     def start(self):
+        if self.hold_gc:
+            hold_gc()
         self._thread = threading.Thread(target=self._loop, name="gbs-server", daemon=True)
         self._thread.start()
         return self
@@ -211,6 +284,8 @@ class Server:
         self._stop = True
         if self._thread:
             self._thread.join(timeout)
+        if self.hold_gc:
+            release_gc()
 
     def latencies_by_rid(self, skip: int = 0) -> List[float]:
         """Latencies (s) of the completed requests numbered skip and later (the first `skip` are warm-up)."""
@@ -228,7 +303,9 @@ class Server:
                 "mean_ms": float(lat.mean() * 1e3), "completed": self.completed, "rejected": self.rejected,
                 "failed": self.failed, "throughput_req_s": self.completed / span if span == span and span > 0 else 0.0,
                 "steps": self.steps, "max_concurrent": self.max_concurrent,
-                "arrivals_in_flight": self.arrivals_in_flight, "memory_waits": self.memory_waits}
+                "arrivals_in_flight": self.arrivals_in_flight, "memory_waits": self.memory_waits,
+                "host_build_ms_per_step": 1e3 * self.host_build_s / max(self.steps, 1),
+                "host_launch_ms_per_step": 1e3 * self.host_launch_s / max(self.steps, 1)}
 
     # ------------------------------------------------------------ internals
     def _alloc_pool(self, need: int) -> int:
@@ -340,10 +417,14 @@ class Server:
                 self._admit()
                 jobs, finished = ([], [])
                 if len(self._steps) < self.inflight and self._active:
+                    tb = time.perf_counter()
                     jobs, finished = self._build_step()
+                    self.host_build_s += time.perf_counter() - tb
             if jobs or finished:
                 try:
+                    tl = time.perf_counter()
                     h = self.b.launch_step(jobs, finished)
+                    self.host_launch_s += time.perf_counter() - tl
                     with self._lock:
                         self.steps += 1
                         self._steps.append((h, finished))
@@ -376,10 +457,10 @@ class FifoServer:
         self._t_first = None
         self._t_last = None
 
-    def submit(self, modes) -> Future:
+    def submit(self, modes, t_arrival: Optional[float] = None) -> Future:
         f: Future = Future()
         with self._lock:
-            t = time.perf_counter()
+            t = time.perf_counter() if t_arrival is None else t_arrival
             self._q.append((np.asarray(modes, dtype=np.int32), t, f, self._rid))
             self._rid += 1
             if self._t_first is None:
@@ -435,16 +516,19 @@ class FifoServer:
 
 
 def replay(server, arrivals: np.ndarray, patterns: Sequence[Sequence[int]], warmup: int = 0):
-    """Submit patterns at the given arrival times (seconds from start) in real time; returns futures."""
+    """Submit patterns at the given arrival times (seconds from start) in real time; returns futures.
+
+    Every request whose arrival time has passed is submitted at once with that arrival time, then the
+    feeder sleeps until the next one (sleeping releases the interpreter lock, so the feeder does not
+    compete with the server thread); latencies count from the scheduled arrival."""
     futs = []
     t0 = time.perf_counter()
-    for i, (t, p) in enumerate(zip(arrivals, patterns)):
-        while True:
-            now = time.perf_counter() - t0
-            if now >= t:
-                break
-            dt = t - now
-            if dt > 0.0005:
-                time.sleep(dt - 0.0003)
-        futs.append(server.submit(p))
+    i, total = 0, len(arrivals)
+    while i < total:
+        now = time.perf_counter() - t0
+        while i < total and arrivals[i] <= now:
+            futs.append(server.submit(patterns[i], t_arrival=t0 + float(arrivals[i])))
+            i += 1
+        if i < total:
+            time.sleep(max(0.0, float(arrivals[i]) - (time.perf_counter() - t0)))
     return futs

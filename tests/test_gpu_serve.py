@@ -95,7 +95,7 @@ def test_continuous_batching_arrivals_in_flight_small_pool(env):
     ctx, st, st_in = env
     pats = make_requests(44, 40, [8, 12, 16, 20, 24, 28, 30, 32])
     pool = 72
-    be = serve.GpuBackend(ctx, st, pool_entries=pool)
+    be = serve.GpuBackend(ctx, st, pool_entries=pool, lanes=2)  # steps alternate over two streams
     srv = serve.Server(be, pool_entries=pool, step_flops=3e9, max_slice=1024, inflight=2).start()
     futs = [None] * len(pats)
 
