@@ -105,22 +105,23 @@ int orc_haf_enum_batch(const double* A_ri, int n, long batch, double* out_ri) {
 
 /* ---------------------------------------------------------- power trace --- */
 
-/* One definition, instantiated for double and long double. NAME_kappa also returns
-   sum_Z |(-1)^(k-|Z|) c_k(X A_Z)| (the sum of the subset terms' magnitudes, so that
-   kappa = that sum / |Haf| measures the cancellation in the subset sum) in *absum. */
+/* One definition, instantiated for double and long double. NAME_kappa also returns, in
+   stats[0], sum_Z |t_Z| and, in stats[1], sum_Z |t_Z|^2, where t_Z = (-1)^(k-|Z|) c_k(X A_Z)
+   is the subset term: kappa = stats[0] / |Haf| measures the cancellation in the subset sum,
+   and sqrt(stats[1]) / |Haf| its root-sum-square counterpart. */
 #define DEFINE_HAF_PT(NAME, REAL, CPLX, CABS)                                    \
-  int NAME##_kappa(const double* A_ri, int n, double* out_ri, double* absum);   \
+  int NAME##_kappa(const double* A_ri, int n, double* out_ri, double* stats);   \
   int NAME(const double* A_ri, int n, double* out_ri) {                         \
     return NAME##_kappa(A_ri, n, out_ri, NULL);                                 \
   }                                                                             \
-  int NAME##_kappa(const double* A_ri, int n, double* out_ri, double* absum) {  \
-    if (absum) *absum = 0.0;                                                    \
+  int NAME##_kappa(const double* A_ri, int n, double* out_ri, double* stats) {  \
+    if (stats) { stats[0] = 0.0; stats[1] = 0.0; }                             \
     if (n < 0 || n > 64) return 1;                                              \
     if (n % 2) { out_ri[0] = 0.0; out_ri[1] = 0.0; return 0; }                  \
     int k = n / 2;                                                              \
     if (k == 0) {                                                               \
       out_ri[0] = 1.0; out_ri[1] = 0.0;                                         \
-      if (absum) *absum = 1.0;                                                  \
+      if (stats) { stats[0] = 1.0; stats[1] = 1.0; }                            \
       return 0;                                                                 \
     }                                                                           \
     if (k > 40) return 1;                                                       \
@@ -138,7 +139,7 @@ int orc_haf_enum_batch(const double* A_ri, int n, long batch, double* out_ri) {
     for (int i = 0; i < n * n; ++i)                                             \
       A[i] = (REAL)A_ri[2 * i] + (REAL)A_ri[2 * i + 1] * (CPLX)I;               \
     CPLX total = 0;                                                             \
-    REAL mag = 0;                                                               \
+    REAL mag = 0, mag2 = 0;                                                     \
     for (uint64_t Z = 1; Z < (1ull << k); ++Z) {                                \
       int d = 0;                                                                \
       for (int i = 0; i < k; ++i)                                               \
@@ -172,10 +173,11 @@ int orc_haf_enum_batch(const double* A_ri, int n, long batch, double* out_ri) {
       }                                                                         \
       if ((k - s) % 2) total -= c[k]; else total += c[k];                       \
       mag += CABS(c[k]);                                                        \
+      mag2 += CABS(c[k]) * CABS(c[k]);                                          \
     }                                                                           \
     out_ri[0] = (double)creall(total);                                          \
     out_ri[1] = (double)cimagl(total);                                          \
-    if (absum) *absum = (double)mag;                                            \
+    if (stats) { stats[0] = (double)mag; stats[1] = (double)mag2; }             \
     free(A); free(M); free(P); free(Q); free(t); free(c); free(idx);            \
     return 0;                                                                   \
   }

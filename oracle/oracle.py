@@ -117,22 +117,26 @@ def _call_kappa(fname: str, A):
     if A.shape != (n, n):
         raise ValueError("square matrix expected")
     out = np.zeros(2, dtype=np.float64)
-    mag = np.zeros(1, dtype=np.float64)
-    rc = getattr(_lib(), fname)(_ptr(A), n, _ptr(out), _ptr(mag))
+    stats = np.zeros(2, dtype=np.float64)
+    rc = getattr(_lib(), fname)(_ptr(A), n, _ptr(out), _ptr(stats))
     if rc:
         raise RuntimeError(f"{fname} failed with code {rc} (n={n})")
     h = complex(out[0], out[1])
-    return h, float(mag[0]) / abs(h) if h != 0 else float("inf")
+    if h == 0:
+        return h, float("inf"), float("inf")
+    return h, float(stats[0]) / abs(h), float(np.sqrt(stats[1])) / abs(h)
 
 
 def haf_pt_kappa(A):
-    """(Haf, kappa) by the power-trace formula in double: kappa = sum_Z |term(Z)| / |Haf|, the
-    cancellation of the subset sum, which sets the size of the rounding error of any FP64 evaluation."""
+    """(Haf, kappa, kappa2) by the power-trace formula in double: with t_Z the subset terms,
+    kappa = sum_Z |t_Z| / |Haf| is the cancellation of the subset sum (a worst-case rounding error
+    of an FP64 evaluation is about kappa u) and kappa2 = sqrt(sum_Z |t_Z|^2) / |Haf| its
+    root-sum-square counterpart (the size of independent per-term rounding errors added up)."""
     return _call_kappa("orc_haf_pt_kappa", A)
 
 
 def haf_pt_ld_kappa(A):
-    """(Haf, kappa) as haf_pt_kappa, evaluated in long double."""
+    """(Haf, kappa, kappa2) as haf_pt_kappa, evaluated in long double."""
     return _call_kappa("orc_haf_pt_ld_kappa", A)
 
 

@@ -291,6 +291,12 @@ class Server:
         """Latencies (s) of the completed requests numbered skip and later (the first `skip` are warm-up)."""
         return [t1 - t0 for rid, t0, t1 in self.records if rid >= skip]
 
+    def completion_rate(self, skip: int = 0) -> float:
+        """Completed requests per second among those numbered skip and later: (count - 1) over the time
+        from their first completion to their last (equals the arrival rate while the server keeps up)."""
+        done = sorted(t1 for rid, t0, t1 in self.records if rid >= skip)
+        return (len(done) - 1) / (done[-1] - done[0]) if len(done) > 1 and done[-1] > done[0] else float("nan")
+
     def span(self, skip: int = 0) -> float:
         """Seconds from the arrival of the first request numbered >= skip to the last completion."""
         recs = [r for r in self.records if r[0] >= skip]
@@ -468,6 +474,7 @@ class FifoServer:
         return f
 
     latencies_by_rid = Server.latencies_by_rid
+    completion_rate = Server.completion_rate
     span = Server.span
 
     def start(self):

@@ -4,7 +4,8 @@ Config 5: m = 60 Haar interferometer (seed 1005), r = 0.88 on every mode, patter
 36, 40, 44 (pattern seed 2005; index i has n = (36, 40, 44)[i % 3]). The oracle builds
 B = U diag(tanh r) U^t and the pattern matrices itself and evaluates the power-trace formula:
 every n = 36 record in long double (haf_pt_ld_kappa), the others in double (haf_pt_kappa; some also
-hold a long-double value from an earlier run). Each record carries kappa = sum_Z |term(Z)| / |Haf|.
+hold a long-double value from an earlier run). Each record carries kappa = sum_Z |term(Z)| / |Haf|
+and kappa2 = sqrt(sum_Z |term(Z)|^2) / |Haf|.
 Only oracle/ and the seeded input generators are used. Existing records are kept and completed; the
 file is rewritten as each record finishes.
 
@@ -41,17 +42,18 @@ def one(job):
     p, A = matrix(idx)
     rec = dict(rec) if rec else {"index": idx, "n": len(p), "modes": [int(v) for v in p]}
     t0 = time.time()
-    if len(p) == 36 and "haf_pt_ld" not in rec or (len(p) == 36 and "kappa" not in rec):
-        h, kappa = oracle.haf_pt_ld_kappa(A)
+    if len(p) == 36:
+        h, kappa, kappa2 = oracle.haf_pt_ld_kappa(A)
         rec["haf_pt_ld"] = [h.real, h.imag]
         rec["seconds_pt_ld"] = time.time() - t0
     else:
-        h, kappa = oracle.haf_pt_kappa(A)
+        h, kappa, kappa2 = oracle.haf_pt_kappa(A)
         if "haf_pt" in rec:
             assert rec["haf_pt"] == [h.real, h.imag], "double oracle not reproducible"
         rec["haf_pt"] = [h.real, h.imag]
         rec["seconds_pt"] = time.time() - t0
     rec["kappa"] = kappa
+    rec["kappa2"] = kappa2
     print(json.dumps(rec), flush=True)
     return rec
 
@@ -72,7 +74,7 @@ def main():
     recs = {}
     if OUT.exists():
         recs = {r["index"]: r for r in json.loads(OUT.read_text())["records"]}
-    todo = [(i, recs.get(i)) for i in INDICES if i not in recs or "kappa" not in recs[i]]
+    todo = [(i, recs.get(i)) for i in INDICES if i not in recs or "kappa2" not in recs[i]]
     todo.sort(key=lambda j: -(36, 40, 44)[j[0] % 3])  # longest first
     with mp.get_context("fork").Pool(args.jobs) as pool:
         for rec in pool.imap_unordered(one, todo, chunksize=1):

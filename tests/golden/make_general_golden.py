@@ -4,7 +4,8 @@ Inputs: the config-2 recipe (M = (a + ib)/sqrt(2), a, b ~ N(0, 1), A = (M + M^t)
 inputs.random_symmetric(n, count, default_rng(7000 + n)); record i is matrix i of that draw.
 Each value is the oracle's power-trace formula (haf_pt_ld_kappa in long double up to n = 40,
 haf_pt_kappa in double above, where long double would take many hours) together with
-kappa = sum_Z |term(Z)| / |Haf|, the cancellation of the subset sum. Only oracle/ and the seeded
+kappa = sum_Z |term(Z)| / |Haf|, the cancellation of the subset sum, and its root-sum-square
+counterpart kappa2 = sqrt(sum_Z |term(Z)|^2) / |Haf|. Only oracle/ and the seeded
 input generators are used. The file is rewritten as each record finishes, largest n first.
 
 With --blockdiag it writes blockdiag46_haf.json instead: the n = 46 block-diagonal matrix of two
@@ -50,13 +51,13 @@ def one(job):
     A = matrices(n, count)[i]
     t0 = time.time()
     if n <= LD_MAX_N:
-        h, kappa = oracle.haf_pt_ld_kappa(A)
+        h, kappa, kappa2 = oracle.haf_pt_ld_kappa(A)
         prec = "long double"
     else:
-        h, kappa = oracle.haf_pt_kappa(A)
+        h, kappa, kappa2 = oracle.haf_pt_kappa(A)
         prec = "double"
     rec = {"n": n, "index": i, "count": count, "seed": 7000 + n, "haf": [h.real, h.imag], "kappa": kappa,
-           "oracle": prec, "seconds": time.time() - t0}
+           "kappa2": kappa2, "oracle": prec, "seconds": time.time() - t0}
     print(json.dumps(rec), flush=True)
     return rec
 
@@ -88,10 +89,10 @@ def blockdiag46():
 def write_blockdiag():
     A, A1, A2 = blockdiag46()
     t0 = time.time()
-    h, kappa = oracle.haf_pt_kappa(A)
+    h, kappa, kappa2 = oracle.haf_pt_kappa(A)
     exact = complex(oracle.haf_enum(A1)) * complex(oracle.haf_enum(A2))
-    rec = {"n": 46, "haf_pt": [h.real, h.imag], "kappa": kappa, "haf_blocks": [exact.real, exact.imag],
-           "seconds": time.time() - t0}
+    rec = {"n": 46, "haf_pt": [h.real, h.imag], "kappa": kappa, "kappa2": kappa2,
+           "haf_blocks": [exact.real, exact.imag], "seconds": time.time() - t0}
     (HERE / "blockdiag46_haf.json").write_text(json.dumps(rec, indent=1) + "\n")
     print(json.dumps(rec), flush=True)
 
@@ -108,6 +109,7 @@ def main():
     recs = []
     if OUT.exists():
         recs = json.loads(OUT.read_text())["records"]
+    recs = [r for r in recs if "kappa2" in r]  # records from before kappa2 was stored are redone
     have = {(r["n"], r["index"]) for r in recs}
     todo = [j for j in jobs(args.nmax) if (j[0], j[1]) not in have]
     with mp.get_context("fork").Pool(args.jobs) as pool:

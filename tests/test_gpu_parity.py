@@ -4,6 +4,7 @@ Tolerance: relative error 1e-9 on hafnians and probabilities (complex128 through
 """
 import math
 
+import bounds
 import numpy as np
 import pytest
 
@@ -227,9 +228,8 @@ def test_bipartite_permanent_large(ctx, torch_dev, k):
 def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
     """Config 5 (m = 60, r = 0.88, n = 36/40/44 B_S submatrices) in one batched call, against the
     oracle's power trace stored by tests/golden/make_config5_golden.py (long double where present,
-    else double) with each matrix's cancellation kappa = sum_Z |term(Z)| / |Haf|. Bound:
-    n^2 kappa u (u = 2^-53), doubled against a double-precision reference (tests/test_gpu_sizes.py
-    gives the derivation)."""
+    else double) with each matrix's cancellation kappa = sum_Z |term(Z)| / |Haf| (and kappa2, its
+    root-sum-square counterpart). Bound: the rounding bound of tests/bounds.py."""
     import json
     import pathlib
     gold = json.loads((pathlib.Path(__file__).parent / "golden" / "config5_haf.json").read_text())["records"]
@@ -247,10 +247,10 @@ def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
         ld = "haf_pt_ld" in g
         ref = complex(*(g["haf_pt_ld"] if ld else g["haf_pt"]))
         err = relerr(h, ref)
-        bound = g["n"] ** 2 * g["kappa"] * 2.0 ** -53 * (1.0 if ld else 2.0)
-        print(f"config5 index {g['index']} n={g['n']} kappa={g['kappa']:.2e} rel err {err:.2e} vs "
-              f"{'long double' if ld else 'double'} oracle, err/(kappa u) = {err / (g['kappa'] * 2.0 ** -53):.1f}")
-        assert err <= bound, (g["index"], err, bound)
+        b = bounds.bound(g["n"], g["kappa"], g.get("kappa2"), "long double" if ld else "double")
+        print(f"config5 index {g['index']} n={g['n']} kappa={g['kappa']:.2e} kappa2={g.get('kappa2', float('nan')):.2e} "
+              f"rel err {err:.2e} vs {'long double' if ld else 'double'} oracle, bound {b:.2e}")
+        assert err <= b, (g["index"], err, b)
 
 
 def test_config3_full_size_sampled(ctx, torch_dev):
@@ -275,8 +275,8 @@ def test_largest_size_block_diagonal(ctx, torch_dev):
     B_S of the config-5 state (m = 60, r = 0.88), sizes 24 and 22, built the way
     tests/golden/make_general_golden.py --blockdiag builds them; the exact value is the product of
     the blocks' matching sums. Block-diagonal input is the worst case for the subset sum's
-    cancellation (every term mixing the blocks cancels exactly); its kappa, from the oracle's double
-    power trace, is stored with it, and the bound is the stated n^2 kappa u."""
+    cancellation (every term mixing the blocks cancels exactly); its kappa (and kappa2), from the
+    oracle's double power trace, are stored with it, and the bound is that of tests/bounds.py."""
     import json
     import pathlib
     path = pathlib.Path(__file__).parent / "golden" / "blockdiag46_haf.json"
@@ -296,7 +296,7 @@ def test_largest_size_block_diagonal(ctx, torch_dev):
     ref = complex(oracle.haf_enum(A1)) * complex(oracle.haf_enum(A2))
     assert ref == complex(*rec["haf_blocks"])
     err = relerr(h, ref)
-    bound = 46 ** 2 * rec["kappa"] * 2.0 ** -53
-    print(f"n=46 block-diagonal kappa={rec['kappa']:.2e} rel err {err:.2e} err/(kappa u) = "
-          f"{err / (rec['kappa'] * 2.0 ** -53):.1f}")
-    assert err <= bound
+    b = bounds.bound(46, rec["kappa"], rec.get("kappa2"))  # the reference is exact (block product)
+    print(f"n=46 block-diagonal kappa={rec['kappa']:.2e} kappa2={rec.get('kappa2', float('nan')):.2e} "
+          f"rel err {err:.2e} bound {b:.2e}")
+    assert err <= b

@@ -3,22 +3,21 @@
 * n <= 24: random complex-symmetric matrices against the oracle's matching sum (Eq. HafMatch).
 * n = 26..46: the same recipe against stored oracle values (tests/golden/general_haf.json, written
   by tests/golden/make_general_golden.py from oracle/ only), each with its cancellation
-  kappa = sum_Z |term(Z)| / |Haf|.
+  kappa = sum_Z |term(Z)| / |Haf| and root-sum-square kappa2 = sqrt(sum_Z |term(Z)|^2) / |Haf|.
 * Mixed sizes in one call (haf_batch_varlen and gbs_prob_batch): every engine variant at once.
 * The chunk sizes the autotuner can pick: the work-item boundaries move, the results may not.
 
 Tolerance. Up to n = 32 (the sizes of the probability configurations) the bound is 1e-9 relative.
-Above, the subset sum cancels by kappa ~ 1e7..1e10, and no FP64 evaluation of it is more accurate
-than about kappa * u (u = 2^-53); the bound there is kappa_bound(n, kappa) = n^2 kappa u, the
-first-order rounding bound of one subset term (k <= n/2 products of inner length d <= n, then the
-k-step coefficient recursion: (k d + k^2) u <= n^2 u relative to |term|) summed over the terms,
-doubled when the stored value is itself a double-precision power trace.
+Above, the subset sum cancels strongly (kappa = sum |term| / |Haf| ~ 1e7..1e11), and the bound is
+the rounding bound of tests/bounds.py: n^2 u kappa2 with the root-sum-square cancellation kappa2
+stored with each value (n^2 u kappa, the worst case, where kappa2 is not stored).
 """
 import json
 import pathlib
 
 import numpy as np
 import pytest
+from bounds import U53, bound
 
 import oracle
 from paper_1908_10070_amd import inputs
@@ -26,12 +25,7 @@ from paper_1908_10070_amd import inputs
 pytestmark = pytest.mark.gpu
 
 GOLD = pathlib.Path(__file__).parent / "golden"
-U53 = 2.0 ** -53
 TOL = 1e-9
-
-
-def kappa_bound(n, kappa, oracle_prec="long double"):
-    return n * n * kappa * U53 * (2.0 if oracle_prec == "double" else 1.0)
 
 
 def load(name):
@@ -84,10 +78,11 @@ def test_general_large_n(ctx, torch_dev, rec):
     h = ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
     ref = complex(*rec["haf"])
     err = relerr(h, ref)
-    bound = kappa_bound(n, rec["kappa"], rec["oracle"])
-    print(f"n={n} idx={rec['index']} kappa={rec['kappa']:.2e} err={err:.2e} err/(kappa u)={err / (rec['kappa'] * U53):.1f} "
-          f"bound={bound:.2e}")
-    assert err <= bound, (n, err, bound)
+    b = bound(n, rec["kappa"], rec.get("kappa2"), rec["oracle"])
+    k2 = rec.get("kappa2", float("nan"))
+    print(f"n={n} idx={rec['index']} kappa={rec['kappa']:.2e} kappa2={k2:.2e} err={err:.2e} "
+          f"err/(kappa u)={err / (rec['kappa'] * U53):.3f} err/(kappa2 u)={err / (k2 * U53):.2f} bound={b:.2e}")
+    assert err <= b, (n, err, b)
     if n <= 32:
         assert err < TOL, (n, err)
 
@@ -116,7 +111,7 @@ def test_varlen_every_size_in_one_call(ctx, torch_dev):
                 continue
             A = general_matrix(rec)
             refs.append(complex(*rec["haf"]))
-            tols.append(max(TOL, kappa_bound(n, rec["kappa"], rec["oracle"])))
+            tols.append(max(TOL, bound(n, rec["kappa"], rec.get("kappa2"), rec["oracle"])))
         else:
             A = inputs.random_symmetric(n, 1, rng)[0] if n else np.zeros((0, 0), np.complex128)
             refs.append(oracle.haf_enum(A) if n <= 25 else 0j)
@@ -168,7 +163,7 @@ def test_prob_batch_mixed_sizes(ctx, torch_dev):
         pats.append(p)
         refs.append(abs(h) ** 2 * pref)
         # p = |Haf|^2 pref: twice the hafnian's relative error
-        tols.append(2 * kappa_bound(len(p), rec["kappa"], "long double" if ld else "double"))
+        tols.append(2 * bound(len(p), rec["kappa"], rec.get("kappa2"), "long double" if ld else "double"))
     prob = ctx.prob_batch(st, pats).cpu().numpy()
     for i, p in enumerate(pats):
         err = relerr(prob[i], refs[i])

@@ -322,3 +322,50 @@ def test_pins_catch_planted_mistakes():
     conv = _single_mode_convolution(rv, n)
     assert abs(_n_photon_total(U @ Dv @ U.T, rv, n) - conv) < 1e-14
     assert abs(_n_photon_total(U @ Dv @ U.conj().T, rv, n) - conv) > 1e-3
+
+
+# ------------------------------------------------------------------ cancellation statistics
+
+
+def _rank_one_terms(v):
+    """Subset terms of the power-trace formula for A = v v^t in closed form: M_Z = X A_Z has rank one
+    with eigenvalue t = v_Z^t X v_Z = 2 sum_{i in Z} v_{2i} v_{2i+1}, so det(I - lambda M_Z)^(-1/2) =
+    (1 - lambda t)^(-1/2) and c_k = C(2k, k) / 4^k t^k; the term is (-1)^(k-|Z|) c_k."""
+    k = len(v) // 2
+    p = np.array([v[2 * i] * v[2 * i + 1] for i in range(k)])
+    terms = []
+    for Z in range(1, 1 << k):
+        idx = [i for i in range(k) if Z >> i & 1]
+        t = 2 * p[idx].sum()
+        terms.append((-1) ** (k - len(idx)) * math.comb(2 * k, k) / 4 ** k * t ** k)
+    return np.array(terms)
+
+
+@pytest.mark.parametrize("n", [4, 8, 12])
+def test_kappa_closed_form_rank_one(n):
+    """kappa = sum |t_Z| / |Haf| and kappa2 = sqrt(sum |t_Z|^2) / |Haf| against the rank-one closed form
+    of every term (whose sum is (n-1)!! prod v_i)."""
+    rng = np.random.default_rng(600 + n)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    A = np.outer(v, v)
+    terms = _rank_one_terms(v)
+    haf = dfact(n) * np.prod(v)
+    assert abs(terms.sum() - haf) <= 1e-10 * abs(haf)
+    for f in (oracle.haf_pt_kappa, oracle.haf_pt_ld_kappa):
+        h, kappa, kappa2 = f(A)
+        assert abs(h - haf) <= 1e-10 * abs(haf)
+        assert abs(kappa - np.abs(terms).sum() / abs(haf)) <= 1e-10 * kappa
+        assert abs(kappa2 - np.sqrt((np.abs(terms) ** 2).sum()) / abs(haf)) <= 1e-10 * kappa2
+
+
+@pytest.mark.parametrize("n", [2, 6, 10, 14])
+def test_kappa_invariants(n):
+    """kappa >= 1 (triangle inequality), kappa2 <= kappa <= sqrt(N) kappa2 over the N = 2^(n/2) - 1
+    subset terms (Cauchy-Schwarz); a single term (n = 2) gives kappa = kappa2 = 1."""
+    A = inputs.random_symmetric(n, 1, np.random.default_rng(700 + n))[0]
+    h, kappa, kappa2 = oracle.haf_pt_kappa(A)
+    N = 2 ** (n // 2) - 1
+    assert kappa >= 1 - 1e-12
+    assert kappa2 <= kappa * (1 + 1e-12) and kappa <= np.sqrt(N) * kappa2 * (1 + 1e-12)
+    if n == 2:
+        assert abs(kappa - 1) < 1e-15 and abs(kappa2 - 1) < 1e-15
