@@ -204,6 +204,38 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* state, const gbs_partial* partia
                  const int64_t* offsets_host, int64_t batch, double* prob_out_dev, gbs_c128* haf_out_dev,
                  void* stream);
 
+/* ------------------------------------------- the whole output space (App. D, App. I) */
+
+#define GBS_SWEEP_NMAX 32
+
+/* Number of output patterns of n photons in m modes: C(m + n - 1, n) mode multisets with
+ * collisions = 1 (every configuration s with |s| = n), C(m, n) mode sets with collisions = 0.
+ * -1 if n is outside [0, GBS_SWEEP_NMAX], m <= 0, or the count exceeds 2^31 - 1. */
+int64_t gbs_sweep_count(int32_t m, int32_t n, int32_t collisions);
+
+/* Probabilities (Eq. ProOri) and hafnians of every output pattern of n photons against `state`, in
+ * the lexicographic order of the sorted mode lists (the order of Python's
+ * itertools.combinations_with_replacement(range(m), n), or combinations with collisions = 0):
+ * prob_out_dev[i] = |Haf(B_x)|^2 / (prod_j s_j! prod_i cosh r_i), haf_out_dev[i] = Haf(B_x), either
+ * nullable (not both), gbs_sweep_count(m, n, collisions) entries each.
+ * The hafnians share their work across patterns: the hafnians of all patterns of every even size
+ * l < n are kept (the stored sub-hafnians of the paper's exponential-space variant, App. D), and a
+ * size-l hafnian is the matching sum expanded along its lowest position (Eq. HafMatch): l - 1
+ * products of B entries with stored size-(l - 2) hafnians. Work ~ n x count products; workspace
+ * 16 bytes x (the count at size n - 2) x 2. Odd n gives zeros, n = 0 the vacuum (Haf = 1).
+ * Errors: GBS_ERANGE if gbs_sweep_count is -1; as gbs_prob_batch otherwise. */
+int gbs_prob_sweep(gbs_ctx* ctx, const gbs_state* state, int32_t n, int32_t collisions, double* prob_out_dev,
+                   gbs_c128* haf_out_dev, void* stream);
+
+/* Brute-force sampling over a list of probabilities (App. I): [0, 1) is cut into one interval per
+ * entry, of length prob_dev[i] / total (total = their sum, computed by a fixed-order prefix sum in
+ * the workspace and written to total_out_dev if it is not NULL), and index_out_dev[s] receives the
+ * entry whose interval holds uniforms_dev[s] (caller's uniforms in [0, 1), so draws are
+ * reproducible). With the probabilities of gbs_prob_sweep this samples output patterns exactly from
+ * p_n(s) / sum p_n. count <= 2^31 - 1; nsamples may be 0 (then only the total is computed). */
+int gbs_sweep_sample(gbs_ctx* ctx, const double* prob_dev, int64_t count, const double* uniforms_dev,
+                     int64_t nsamples, int64_t* index_out_dev, double* total_out_dev, void* stream);
+
 /* ------------------------------------------- marginal probabilities (sequential sampling) */
 
 #define GBS_MARGINAL_KMAX 20   /* longest prefix */

@@ -169,6 +169,27 @@ void* noalloc_scratch(int device, hipError_t* err);
 size_t noalloc_scratch_bytes();
 void launch_noalloc_plan(const NoallocPlanArgs& a, hipStream_t s);
 
+// Output-space sweep (gbs_sweep.hip): hafnians of every pattern of n photons in m modes from the
+// stored hafnians of all patterns two photons shorter, and the brute-force sampler over them.
+constexpr int kSweepMaxN = 32;
+struct SweepArgs {
+  const double2* B;          // m x m
+  int32_t m;
+  int32_t n;
+  int32_t collisions;        // 1: multisets (modes may repeat); 0: sets
+  int32_t bstride;           // binom row length (n + 1)
+  const uint64_t* binom;     // C(v, i) at binom[v * bstride + i], v < m + n, i <= n
+  int64_t count;             // patterns of size n
+  const double* prefactor;   // device scalar 1 / prod cosh r_i
+  double* prob_out;          // nullable, count entries, lexicographic order
+  double2* haf_out;          // nullable
+};
+void launch_sweep(const SweepArgs& a, double2* tab0, double2* tab1, const int64_t* level_count, hipStream_t s);
+int64_t cdf_blocks(int64_t count);
+void launch_cdf(const double* p, int64_t count, double* cdf, double* bsum, double* total, hipStream_t s);
+void launch_cdf_draw(const double* cdf, int64_t count, const double* total, const double* u, int64_t nsamples,
+                     int64_t* idx, hipStream_t s);
+
 // Host-side launchers (defined in gbs_kernels.hip).
 int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);

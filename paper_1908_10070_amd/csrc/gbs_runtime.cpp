@@ -1033,6 +1033,133 @@ int gbs_marginal_batch(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32
                          static_cast<hipStream_t>(stream));
 }
 
+namespace {
+
+// C(a, b) as an integer, or -1 past 2^62.
+int64_t binom_i64(int64_t a, int64_t b) {
+  if (b < 0 || a < 0 || b > a) return 0;
+  if (b > a - b) b = a - b;
+  unsigned __int128 r = 1;
+  for (int64_t i = 1; i <= b; ++i) {
+    r = r * (unsigned __int128)(a - b + i) / (unsigned __int128)i;
+    if (r > ((unsigned __int128)1 << 62)) return -1;
+  }
+  return (int64_t)r;
+}
+
+constexpr int64_t kSweepMaxCount = (int64_t(1) << 31) - 1;
+
+int64_t sweep_count_of(int32_t m, int32_t n, int32_t collisions) {
+  if (m <= 0 || n < 0 || n > kSweepMaxN) return -1;
+  const int64_t c = collisions ? binom_i64((int64_t)m + n - 1, n) : binom_i64(m, n);
+  return (c < 0 || c > kSweepMaxCount) ? -1 : c;
+}
+
+}  // namespace
+
+int64_t gbs_sweep_count(int32_t m, int32_t n, int32_t collisions) { return sweep_count_of(m, n, collisions); }
+
+int gbs_prob_sweep(gbs_ctx* ctx, const gbs_state* st, int32_t n, int32_t collisions, double* prob_out_dev,
+                   gbs_c128* haf_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (!st) return fail(ctx, GBS_EINVAL, "null state");
+  if (st->device != ctx->device) return fail(ctx, GBS_EINVAL, "state and context are on different devices");
+  const int m = st->m;
+  const int64_t count = sweep_count_of(m, n, collisions);
+  if (count < 0)
+    return fail(ctx, GBS_ERANGE, "the sweep of n = %d photons over m = %d modes has too many patterns (or n > %d)", n,
+                m, kSweepMaxN);
+  if (count == 0) return GBS_OK;  // no pattern (n > m without collisions)
+  if (!prob_out_dev && !haf_out_dev) return fail(ctx, GBS_EINVAL, "no output");
+  // binomials C(v, i), v below the largest universe m + n - 1, i <= n; per even size its count
+  const int U = collisions ? m + n - 1 : m;
+  const int bstride = n + 1;
+  std::vector<uint64_t> binom((size_t)(U + 1) * bstride, 0);
+  for (int v = 0; v <= U; ++v)
+    for (int i = 0; i <= n; ++i) {
+      const int64_t c = binom_i64(v, i);
+      if (c < 0) return fail(ctx, GBS_ERANGE, "binomial C(%d, %d) too large for the sweep's ranks", v, i);
+      binom[(size_t)v * bstride + i] = (uint64_t)c;
+    }
+  std::vector<int64_t> level_count(n + 1, 0);
+  int64_t tab_max = 1;
+  for (int l = 0; l < n; l += 2) {
+    level_count[l] = sweep_count_of(m, l, collisions);
+    tab_max = std::max(tab_max, level_count[l]);
+  }
+  DeviceGuard dg(ctx->device);
+  size_t off = 0;
+  const size_t o_binom = off;
+  off += al(sizeof(uint64_t) * binom.size());
+  const size_t stage = off;
+  const size_t o_t0 = off;
+  off += al(sizeof(double2) * (size_t)tab_max);
+  const size_t o_t1 = off;
+  off += al(sizeof(double2) * (size_t)tab_max);
+  int rc = ensure_ws(ctx, off);
+  if (rc) return rc;
+  int pi = 0;
+  rc = acquire_pin(ctx, stage, &pi);
+  if (rc) return rc;
+  std::memcpy(ctx->pinned[pi], binom.data(), sizeof(uint64_t) * binom.size());
+  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->done_ev, 0));
+  if (hipStreamWaitEvent(s, st->ready, 0) != hipSuccess) return fail(ctx, GBS_EHIP, "state not ready");
+  HIPCHK(ctx, hipMemcpyAsync(ws + o_binom, ctx->pinned[pi], stage, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], s));
+  ctx->pinned_used[pi] = true;
+  SweepArgs a{};
+  a.B = st->B;
+  a.m = m;
+  a.n = n;
+  a.collisions = collisions ? 1 : 0;
+  a.bstride = bstride;
+  a.binom = reinterpret_cast<const uint64_t*>(ws + o_binom);
+  a.count = count;
+  a.prefactor = st->pref;
+  a.prob_out = prob_out_dev;
+  a.haf_out = reinterpret_cast<double2*>(haf_out_dev);
+  launch_sweep(a, reinterpret_cast<double2*>(ws + o_t0), reinterpret_cast<double2*>(ws + o_t1), level_count.data(), s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
+  ctx->done_recorded = true;
+  return GBS_OK;
+}
+
+int gbs_sweep_sample(gbs_ctx* ctx, const double* prob_dev, int64_t count, const double* uniforms_dev, int64_t nsamples,
+                     int64_t* index_out_dev, double* total_out_dev, void* stream) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (count < 0 || nsamples < 0) return fail(ctx, GBS_EINVAL, "negative size");
+  if (count == 0 || (nsamples == 0 && !total_out_dev)) return GBS_OK;
+  if (!prob_dev || (nsamples > 0 && (!uniforms_dev || !index_out_dev))) return fail(ctx, GBS_EINVAL, "null pointer");
+  if (count > kSweepMaxCount) return fail(ctx, GBS_ERANGE, "count too large");
+  DeviceGuard dg(ctx->device);
+  const int64_t nb = cdf_blocks(count);
+  size_t off = 0;
+  const size_t o_cdf = off;
+  off += al(sizeof(double) * (size_t)count);
+  const size_t o_bsum = off;
+  off += al(sizeof(double) * (size_t)nb);
+  const size_t o_tot = off;
+  off += al(sizeof(double));
+  int rc = ensure_ws(ctx, off);
+  if (rc) return rc;
+  unsigned char* ws = static_cast<unsigned char*>(ctx->ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->done_recorded) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->done_ev, 0));
+  double* cdf = reinterpret_cast<double*>(ws + o_cdf);
+  double* total = total_out_dev ? total_out_dev : reinterpret_cast<double*>(ws + o_tot);
+  launch_cdf(prob_dev, count, cdf, reinterpret_cast<double*>(ws + o_bsum), total, s);
+  if (nsamples > 0) launch_cdf_draw(cdf, count, total, uniforms_dev, nsamples, index_out_dev, s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, s));
+  ctx->done_recorded = true;
+  return GBS_OK;
+}
+
 int gbs_photon_number_pmf(int32_t m, double r, int32_t nmax, double* pmf_host) {
   if (m <= 0 || nmax < 0 || !pmf_host || !std::isfinite(r) || r < 0) return GBS_EINVAL;
   for (int n = 0; n <= nmax; ++n) {

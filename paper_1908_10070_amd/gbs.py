@@ -27,7 +27,8 @@ EXPORTS = [
     "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops",
     "haf_batch", "haf_batch_varlen", "haf_batch_noalloc", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
     "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
-    "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step",
+    "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step", "gbs_sweep_count",
+    "gbs_prob_sweep", "gbs_sweep_sample",
 ]
 
 _lib = None
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
         "gbs_marginal_batch": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, vp]),
         "gbs_photon_number_pmf": (ctypes.c_int, [i32, ctypes.c_double, i32, dp]),
         "gbs_sample_step": (ctypes.c_int, [vp, vp, i32, dp, dp, i64, dp, dp, dp, vp]),
+        "gbs_sweep_count": (i64, [i32, i32, i32]),
+        "gbs_prob_sweep": (ctypes.c_int, [vp, vp, i32, i32, dp, dp, vp]),
+        "gbs_sweep_sample": (ctypes.c_int, [vp, dp, i64, dp, i64, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -347,6 +351,36 @@ class Context:
                   _t_ptr(weights_out), _t_ptr(nxt), _stream_ptr(stream))
         return nxt
 
+    def prob_sweep(self, state: State, n: int, collisions: bool = True, want_haf: bool = False, prob_out=None,
+                   haf_out=None, stream=None):
+        """Probabilities (and optionally hafnians) of every pattern of n photons, in lexicographic order
+        of the sorted mode lists (itertools.combinations_with_replacement, or combinations)."""
+        import torch
+        count = sweep_count(state.m, n, collisions)
+        if count < 0:
+            raise GBSError(GBS_ERANGE, f"sweep of n = {n} over m = {state.m} modes is too large")
+        if prob_out is None:
+            prob_out = torch.empty(count, dtype=torch.float64, device=self.torch_device)
+        if want_haf and haf_out is None:
+            haf_out = torch.empty(count, dtype=torch.complex128, device=self.torch_device)
+        self._run(lib().gbs_prob_sweep, state.handle, int(n), int(bool(collisions)), _t_ptr(prob_out), _t_ptr(haf_out),
+                  _stream_ptr(stream))
+        return (prob_out, haf_out) if want_haf else prob_out
+
+    def sweep_sample(self, prob, uniforms, stream=None):
+        """Entries drawn from a probability list (App. I): index_out[s] = the entry whose interval of
+        [0, total) holds uniforms[s] * total -> (int64 index tensor, float64 total tensor of one)."""
+        import torch
+        if prob.dtype != torch.float64 or not prob.is_cuda or not prob.is_contiguous():
+            raise TypeError("prob must be a contiguous float64 CUDA tensor")
+        if uniforms.dtype != torch.float64 or not uniforms.is_cuda or not uniforms.is_contiguous():
+            raise TypeError("uniforms must be a contiguous float64 CUDA tensor")
+        idx = torch.empty(uniforms.numel(), dtype=torch.int64, device=self.torch_device)
+        total = torch.empty(1, dtype=torch.float64, device=self.torch_device)
+        self._run(lib().gbs_sweep_sample, _t_ptr(prob), prob.numel(), _t_ptr(uniforms), uniforms.numel(), _t_ptr(idx),
+                  _t_ptr(total), _stream_ptr(stream))
+        return idx, total
+
     def prob_slices(self, state: State, patterns, lo, hi, partials_out=None, out_idx=None, stream=None):
         """Compensated partial sums over subset ranges [lo, hi) -> float64 tensor of (s_re, s_im, c_re, c_im)
         rows; slice b goes to row out_idx[b] (default b)."""
@@ -390,6 +424,11 @@ class Context:
                   _np_ptr(hi), _np_ptr(modes), _np_ptr(offsets), b, _t_ptr(prob_out) if want_prob else None,
                   _t_ptr(haf_out), _stream_ptr(stream))
         return (prob_out if want_prob else None), haf_out
+
+
+def sweep_count(m: int, n: int, collisions: bool = True) -> int:
+    """Number of output patterns of n photons in m modes (-1 if beyond the sweep's limits)."""
+    return int(lib().gbs_sweep_count(int(m), int(n), int(bool(collisions))))
 
 
 def photon_number_pmf(m: int, r: float, nmax: int) -> np.ndarray:

@@ -71,3 +71,39 @@ class Sampler:
             for i, row in zip(idx, xs):
                 out[i] = Sample(int(nv), [int(v) for v in row], np.bincount(row, minlength=self.m))
         return out
+
+
+class BruteForceSampler:
+    """Brute-force sampling of output patterns (App. I): the probabilities of every n-photon pattern
+    are evaluated once (gbs_prob_sweep, sub-hafnians shared across patterns), then each sample is the
+    pattern whose interval of the cumulative distribution holds a uniform (gbs_sweep_sample). Exact
+    for p_n(s) / sum_s p_n(s); memory and time grow with C(m + n - 1, n)."""
+
+    def __init__(self, ctx, state, n: int, collisions: bool = True):
+        import itertools
+        self.ctx = ctx
+        self.n = n
+        self.m = state.m
+        self.collisions = collisions
+        self.prob = ctx.prob_sweep(state, n, collisions)
+        gen = itertools.combinations_with_replacement if collisions else itertools.combinations
+        self._gen = lambda: gen(range(self.m), n)
+
+    def sample_indices(self, count: int, rng):
+        import torch
+        u = torch.from_numpy(rng.random(count)).to(self.ctx.torch_device)
+        idx, total = self.ctx.sweep_sample(self.prob, u)
+        return idx.cpu().numpy(), float(total.cpu()[0])
+
+    def patterns(self, indices):
+        """Mode lists of the given pattern indices (lexicographic order)."""
+        import itertools
+        want = sorted(set(int(i) for i in indices))
+        out, j = {}, 0
+        for i, p in enumerate(self._gen()):
+            if j < len(want) and i == want[j]:
+                out[i] = p
+                j += 1
+                if j == len(want):
+                    break
+        return [out[int(i)] for i in indices]

@@ -87,3 +87,14 @@ def test_photon_number_pmf_matches_oracle():
         for n in range(61):
             assert abs(p[n] - oracle.photon_number_prob(m, n, r)) <= 1e-12 * max(p[n], 1e-300) + 1e-300
     assert abs(gbs.photon_number_pmf(36, 0.3423, 400).sum() - 1.0) < 1e-12
+
+
+def test_sweep_count():
+    """Number of output patterns: C(m + n - 1, n) with collisions, C(m, n) without; -1 past the limits."""
+    import math
+    for m, n in [(16, 8), (5, 4), (1, 3), (7, 0), (30, 10)]:
+        assert gbs.sweep_count(m, n, True) == math.comb(m + n - 1, n)
+        assert gbs.sweep_count(m, n, False) == math.comb(m, n)
+    assert gbs.sweep_count(50, 20, True) == -1  # beyond 2^31 - 1 patterns
+    assert gbs.sweep_count(4, 33, True) == -1   # n beyond the sweep's limit
+    assert gbs.sweep_count(0, 2, True) == -1
