@@ -98,6 +98,20 @@ const char* gbs_last_error(const gbs_ctx* ctx);
  * Defaults: use_graph = 1, persistent = 1. */
 int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
 
+/* Arithmetic of the subset sum (Sec. III, the power-trace formula), per context:
+ *   GBS_PREC_FP64: FP64 on the matrix cores (default). Rounding error about n^2 u kappa relative,
+ *                  u = 2^-53, kappa = sum_Z |term(Z)| / |Haf| the cancellation of the subset sum.
+ *   GBS_PREC_DD:   double-double (about 106 bits) on the vector ALUs: the same sum with error about
+ *                  n^2 u^2 kappa, so the result is correct to FP64 rounding unless kappa > ~1e25;
+ *                  roughly 10-40x the FP64 cost. For the large-n patterns whose cancellation reaches
+ *                  1e7..1e12 (n = 36..46).
+ * Applies to every later hafnian and probability call on the context (haf_batch, haf_batch_varlen,
+ * haf_batch_noalloc, gbs_prob_batch, gbs_haf_partial); GBS_EINVAL for another value. */
+#define GBS_PREC_FP64 0
+#define GBS_PREC_DD 1
+int gbs_ctx_set_precision(gbs_ctx* ctx, int32_t precision);
+int32_t gbs_ctx_get_precision(const gbs_ctx* ctx);
+
 /* Launch-shape table (what the autotuner writes): for photon number n, the number of subsets per
  * work item for the small-subset engine (subsets with 2|Z| <= 16) and for the large-subset engine.
  * chunk <= 0 restores the built-in default. Results depend only on these values and n, never on

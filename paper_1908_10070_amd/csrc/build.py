@@ -18,9 +18,9 @@ OUT = PKG / "libgbs.so"
 
 # the engine kernels are split over several translation units so that they compile in parallel
 SOURCES = ["gbs_eng_grid5.hip", "gbs_eng_grid4.hip", "gbs_eng_quad.hip", "gbs_eng_tile.hip", "gbs_eng_strip.hip",
-           "gbs_kernels.hip", "gbs_noalloc.hip", "gbs_sweep.hip", "gbs_runtime.cpp"]
+           "gbs_eng_dd.hip", "gbs_kernels.hip", "gbs_noalloc.hip", "gbs_sweep.hip", "gbs_runtime.cpp"]
 HEADERS = ["gbs_internal.h", "gbs_tables.h", "gbs_engine_common.h", "gbs_quad_engine.h", "gbs_tile_engine.h",
-           "gbs_qtile_engine.h", "gbs_strip_engine.h", "gbs_chain_table.h"]
+           "gbs_qtile_engine.h", "gbs_strip_engine.h", "gbs_dd_engine.h", "gbs_chain_table.h"]
 
 ARCH = "gfx950"
 COMMON = [
@@ -32,6 +32,9 @@ COMMON = [
     "-mllvm", "-amdgpu-mfma-vgpr-form",
     f"-I{INCLUDE}", f"-I{HERE}",
 ]
+# per-source flags: the double-double engine is built on error-free transformations (TwoSum, the
+# fma product error), which a contracted a * b + c would silently break
+EXTRA = {"gbs_eng_dd.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:
@@ -57,7 +60,8 @@ def build(force: bool = True, verbose: bool = False, out: pathlib.Path = None, d
         def compile_one(src):
             obj = pathlib.Path(td) / (src + ".o")
             lang = ["-x", "hip"] if src.endswith(".hip") else []
-            cmd = [hipcc(), *COMMON, *["-D" + d for d in defines], *lang, "-c", str(HERE / src), "-o", str(obj)]
+            cmd = [hipcc(), *COMMON, *EXTRA.get(src, []), *["-D" + d for d in defines], *lang, "-c", str(HERE / src),
+                   "-o", str(obj)]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)

@@ -114,11 +114,15 @@ struct MargArgs {
 //   63..69  quad-tile engine, |Z| = 11, 12, k = 17..23               (gbs_eng_tile.hip)
 //   70..80  tile engine, 2x2 16x16 tiles, |Z| = 13..16, k = 13..23   (gbs_eng_tile.hip)
 //   81..87  tile engine, 3x3 16x16 tiles, |Z| >= 17, k = 17..23      (gbs_eng_tile.hip)
-constexpr int kEngineClasses = 88;
+//   88..90  double-double engine (accuracy mode), 2|Z| <= 16, 32, 48; any k (gbs_eng_dd.hip)
+constexpr int kEngineClasses = 91;
 constexpr int kClsQuad = 0, kClsGrid4 = 23, kClsGrid5 = 42, kClsStrip = 57, kClsQtile = 63, kClsTile2 = 70,
-              kClsTile3 = 81;
+              kClsTile3 = 81, kClsDd = 88;
 
-enum EngineKind { kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3 };
+enum EngineKind { kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3, kDdKind = 4 };
+
+// Arithmetic of the subset engines: FP64 (MFMA) or double-double (VALU, error-free transformations).
+enum Precision { kPrecFp64 = 0, kPrecDd = 1 };
 
 // One kernel variant: its entry point, workgroup size, engine kind and tile count per side (tile
 // engines) or largest grid side (quad engines).
@@ -135,6 +139,7 @@ void register_grid4_engines(EngineVariant* tab);
 void register_grid5_engines(EngineVariant* tab);
 void register_strip_engines(EngineVariant* tab);
 void register_tile_engines(EngineVariant* tab);
+void register_dd_engines(EngineVariant* tab);
 
 // No-allocation hafnian path (haf_batch_noalloc): a uniform-n batch's plan is built on the device in
 // a static scratch array. Per engine launch g, every pattern has count items: item j of pattern p
@@ -192,6 +197,7 @@ void launch_cdf_draw(const double* cdf, int64_t count, const double* total, cons
 
 // Host-side launchers (defined in gbs_kernels.hip).
 int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
+int engine_class_dd(int s);        // double-double variant for subsets of size s
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);
 int engine_blocks_per_cu(int cls, size_t lds);
 void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream_t s);

@@ -25,6 +25,7 @@
 #include "gbs_qtile_engine.h"
 #include "gbs_strip_engine.h"
 #include "gbs_tile_engine.h"
+#include "gbs_dd_engine.h"
 
 namespace gbs {
 
@@ -392,6 +393,7 @@ static const EngineVariant* variants() {
     register_grid5_engines(tab);
     register_strip_engines(tab);
     register_tile_engines(tab);
+    register_dd_engines(tab);
     return true;
   }();
   (void)filled;
@@ -416,11 +418,15 @@ int engine_class(int s, int k) {
   return kClsTile3 + (k - 17);
 }
 
+// Double-double engine per subset size: the smallest padded size 16 T that holds M_Z (d = 2s).
+int engine_class_dd(int s) { return kClsDd + (2 * s + 15) / 16 - 1; }
+
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   const EngineVariant v = variant(cls);
   if (v.kind == kQtileKind) return qtile_lds_layout(nmax, kmax, stage_A).total;
   if (v.kind == kStripKind) return strip_lds_bytes(nmax, kmax, stage_A);
   if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
+  if (v.kind == kDdKind) return dd_lds_layout(v.tiles, nmax, kmax).total;
   return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));
 }
 

@@ -76,6 +76,7 @@ struct gbs_ctx {
   hipStream_t cap_stream = nullptr;
   int use_graph = 1;
   int persistent = 1;
+  int precision = kPrecFp64;
   std::map<int, std::pair<int64_t, int64_t>> tuning;
   std::string last_error;
   std::list<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
@@ -170,18 +171,23 @@ struct ClassRun {
   int64_t a, b, chunk;
 };
 
+constexpr int64_t kDdChunk = 32;
+
 std::vector<ClassRun> class_runs(const gbs_ctx* ctx, int n, int64_t lo, int64_t hi) {
   std::vector<ClassRun> out;
   const int k = n / 2;
   int64_t cs, cl;
   chunks_for(ctx, n, &cs, &cl);
+  const bool dd = ctx->precision == kPrecDd;
+  auto cls_of = [&](int s) { return dd ? engine_class_dd(s) : engine_class(s, k); };
   for (int s_lo = 1; s_lo <= k;) {
-    const int cls = engine_class(s_lo, k);
+    const int cls = cls_of(s_lo);
     int s_hi = s_lo;
-    while (s_hi + 1 <= k && engine_class(s_hi + 1, k) == cls) ++s_hi;
+    while (s_hi + 1 <= k && cls_of(s_hi + 1) == cls) ++s_hi;
     const int64_t a = std::max(lo, size_start(k, s_lo));
     const int64_t b = std::min(hi, size_start(k, s_hi + 1));
-    if (a < b) out.push_back(ClassRun{cls, a, b, s_hi <= 8 ? cs : cl});
+    // double-double items: kDdChunk subsets (a subset there costs ~30 FP64 ones)
+    if (a < b) out.push_back(ClassRun{cls, a, b, dd ? kDdChunk : (s_hi <= 8 ? cs : cl)});
     s_lo = s_hi + 1;
   }
   return out;
@@ -577,6 +583,19 @@ int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent) {
   ctx->use_graph = use_graph ? 1 : 0;
   ctx->persistent = persistent ? 1 : 0;
   return GBS_OK;
+}
+
+int gbs_ctx_set_precision(gbs_ctx* ctx, int32_t precision) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (precision != GBS_PREC_FP64 && precision != GBS_PREC_DD)
+    return fail(ctx, GBS_EINVAL, "precision %d is neither GBS_PREC_FP64 nor GBS_PREC_DD", precision);
+  ctx->precision = precision == GBS_PREC_DD ? kPrecDd : kPrecFp64;
+  return GBS_OK;
+}
+
+int32_t gbs_ctx_get_precision(const gbs_ctx* ctx) {
+  return (ctx && ctx->precision == kPrecDd) ? GBS_PREC_DD : GBS_PREC_FP64;
 }
 
 int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chunk_large) {

@@ -20,11 +20,12 @@ LIB_PATH = _HERE / "libgbs.so"
 GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6)
 GBS_N_MAX = 46
 GBS_MARGINAL_KMAX = 20
+GBS_PREC_FP64, GBS_PREC_DD = 0, 1
 
 # Every function declared in include/gbs.h.
 EXPORTS = [
     "gbs_ctx_create", "gbs_ctx_destroy", "gbs_ctx_set_workspace", "gbs_ctx_workspace_needed", "gbs_status_str",
-    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops",
+    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_precision", "gbs_ctx_get_precision", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops",
     "haf_batch", "haf_batch_varlen", "haf_batch_noalloc", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
     "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
     "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step", "gbs_sweep_count",
@@ -63,6 +64,8 @@ def lib() -> ctypes.CDLL:
         "gbs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "gbs_last_error": (ctypes.c_char_p, [vp]),
         "gbs_ctx_set_exec": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "gbs_ctx_set_precision": (ctypes.c_int, [vp, i32]),
+        "gbs_ctx_get_precision": (i32, [vp]),
         "gbs_ctx_set_tuning": (ctypes.c_int, [vp, i32, i64, i64]),
         "gbs_ctx_get_tuning": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "gbs_haf_flops": (ctypes.c_double, [i32]),
@@ -254,6 +257,15 @@ class Context:
     # -- options
     def set_exec(self, use_graph: bool = True, persistent: bool = True):
         self._check(lib().gbs_ctx_set_exec(self.handle, int(use_graph), int(persistent)))
+
+    def set_precision(self, precision):
+        """'fp64' (default) or 'dd' (double-double subset sum), or GBS_PREC_FP64 / GBS_PREC_DD."""
+        code = {"fp64": GBS_PREC_FP64, "dd": GBS_PREC_DD}.get(precision, precision)
+        self._check(lib().gbs_ctx_set_precision(self.handle, int(code)))
+
+    @property
+    def precision(self) -> str:
+        return "dd" if lib().gbs_ctx_get_precision(self.handle) == GBS_PREC_DD else "fp64"
 
     def set_tuning(self, n: int, chunk_small: int, chunk_large: int):
         self._check(lib().gbs_ctx_set_tuning(self.handle, int(n), int(chunk_small), int(chunk_large)))

@@ -98,3 +98,11 @@ def test_sweep_count():
     assert gbs.sweep_count(50, 20, True) == -1  # beyond 2^31 - 1 patterns
     assert gbs.sweep_count(4, 33, True) == -1   # n beyond the sweep's limit
     assert gbs.sweep_count(0, 2, True) == -1
+
+
+def test_precision_null_context():
+    """gbs_ctx_set_precision / gbs_ctx_get_precision reject a null context without touching a device."""
+    from paper_1908_10070_amd import gbs
+    L = gbs.lib()
+    assert L.gbs_ctx_set_precision(None, gbs.GBS_PREC_DD) == gbs.GBS_EINVAL
+    assert L.gbs_ctx_get_precision(None) == gbs.GBS_PREC_FP64

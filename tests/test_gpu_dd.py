@@ -1,0 +1,238 @@
+"""The double-double accuracy mode (gbs_ctx_set_precision(GBS_PREC_DD)) through the C ABI.
+
+The FP64 engines' rounding error grows with the cancellation of the subset sum, kappa = sum_Z
+|term(Z)| / |Haf| (bound n^2 u kappa, u = 2^-53); the double-double engine's is n^2 u^2 kappa, so at
+every supported size its result should be correct to FP64 rounding. Pins:
+
+* rank-one matrices A = v v^t at every even n up to 46: Haf = (n-1)!! prod v_i in closed form, with
+  aligned phases so that kappa reaches ~1e9 (computed here from the closed form of every term);
+* the n = 46 block-diagonal matrix (kappa ~ 1e12) against the product of its blocks' matching sums;
+* general matrices n = 26..44 against the stored oracle values, within the oracle's own error bound;
+* small n against the oracle's matching sum; GBS probabilities on the config-5 state;
+* plan invariance: mixed sizes in one call, the no-allocation entry point, switching back to FP64.
+"""
+import json
+import math
+import pathlib
+
+import numpy as np
+import pytest
+from bounds import U53, bound
+
+import oracle
+from paper_1908_10070_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLD = pathlib.Path(__file__).parent / "golden"
+U64 = 2.0 ** -64  # long double unit roundoff
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def dd_ctx(torch_dev):
+    from paper_1908_10070_amd import gbs
+    c = gbs.Context(0)
+    c.set_precision("dd")
+    assert c.precision == "dd"
+    return c
+
+
+@pytest.fixture(scope="module")
+def fp_ctx(torch_dev):
+    from paper_1908_10070_amd import gbs
+    return gbs.Context(0)
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def relerr(x, ref):
+    return float(abs(complex(x) - complex(ref)) / max(abs(complex(ref)), 1e-300))
+
+
+def dfact(n):
+    return math.prod(range(n - 1, 0, -2)) if n > 0 else 1
+
+
+def rank_one_case(n):
+    """v with nearly aligned phases (so the alternating subset sum cancels strongly), the closed-form
+    hafnian (n-1)!! prod v_i and the kappa, kappa2 of its power-trace terms: for A = v v^t, M_Z has
+    rank one with eigenvalue t_Z = 2 sum_{pairs p in Z} v_{2p} v_{2p+1}, and term(Z) =
+    (-1)^(k-|Z|) C(2k, k) / 4^k t_Z^k."""
+    rng = np.random.default_rng(4700 + n)
+    v = (0.5 + rng.uniform(size=n)) * np.exp(1j * (0.7 + rng.uniform(-0.2, 0.2, size=n)))
+    k = n // 2
+    w = 2 * v[0::2] * v[1::2]
+    t = np.zeros(1, dtype=np.complex128)
+    size = np.zeros(1, dtype=np.int64)
+    for p in range(k):
+        t = np.concatenate([t, t + w[p]])
+        size = np.concatenate([size, size + 1])
+    mag = math.comb(2 * k, k) / 4.0 ** k * np.abs(t[1:]) ** k
+    haf = complex(dfact(n)) * complex(np.prod(v.astype(np.complex128)))
+    kappa = float(mag.sum()) / abs(haf)
+    kappa2 = float(np.sqrt((mag ** 2).sum())) / abs(haf)
+    return np.outer(v, v), haf, kappa, kappa2
+
+
+@pytest.mark.parametrize("n", list(range(2, 47, 2)))
+def test_dd_rank_one_closed_form(dd_ctx, fp_ctx, torch_dev, n):
+    """Every even n: the double-double result within 2e-14 of (n-1)!! prod v_i (the reference's own
+    rounding is ~n u), the FP64 result within its bound n^2 u kappa2."""
+    A, haf, kappa, kappa2 = rank_one_case(n)
+    A_dev = to_dev(A[None], torch_dev)
+    h_dd = dd_ctx.haf_batch(A_dev).cpu().numpy()[0]
+    h_fp = fp_ctx.haf_batch(A_dev).cpu().numpy()[0]
+    e_dd, e_fp = relerr(h_dd, haf), relerr(h_fp, haf)
+    print(f"n={n} kappa={kappa:.2e} kappa2={kappa2:.2e} dd err={e_dd:.2e} fp64 err={e_fp:.2e}")
+    assert e_dd < 2e-14, (n, e_dd)
+    assert e_fp <= max(1e-13, n * n * U53 * kappa2), (n, e_fp)
+
+
+def test_dd_block_diagonal_46(dd_ctx, torch_dev):
+    """n = 46 block diagonal of two config-5 pattern matrices (sizes 24 and 22), the matrix of the FP64
+    engine's largest-size test: its kappa is ~1.5e12, where the FP64 result keeps ~6 digits; the
+    double-double one agrees with the product of the blocks' matching sums to 1e-13."""
+    rec_path = GOLD / "blockdiag46_haf.json"
+    if not rec_path.exists():
+        pytest.skip("blockdiag46_haf.json not written yet")
+    rec = json.loads(rec_path.read_text())
+    rng = np.random.default_rng(46)
+    st_in, _ = inputs.config5()
+    B = oracle.state_B(st_in.U, st_in.r)
+    modes = rng.permutation(60)
+    A1 = oracle.pattern_matrix(B, sorted(modes[:24]))
+    A2 = oracle.pattern_matrix(B, sorted(modes[24:46]))
+    A = np.zeros((46, 46), dtype=np.complex128)
+    A[:24, :24] = A1
+    A[24:, 24:] = A2
+    ref = complex(oracle.haf_enum(A1)) * complex(oracle.haf_enum(A2))
+    assert ref == complex(*rec["haf_blocks"])
+    h = dd_ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
+    err = relerr(h, ref)
+    print(f"n=46 block-diagonal kappa={rec['kappa']:.2e} dd rel err {err:.2e}")
+    assert err < 1e-13
+
+
+def _general_records():
+    p = GOLD / "general_haf.json"
+    return json.loads(p.read_text())["records"] if p.exists() else []
+
+
+GENERAL = _general_records()
+
+
+@pytest.mark.parametrize("rec", GENERAL, ids=[f"n{r['n']}_{r['index']}" for r in GENERAL])
+def test_dd_general_against_oracle(dd_ctx, torch_dev, rec):
+    """General complex-symmetric matrices: the double-double result within the stored oracle value's own
+    error bound (n^2 u' kappa2, u' the oracle's unit roundoff) plus FP64 rounding."""
+    n = rec["n"]
+    A = inputs.random_symmetric(n, rec["count"], np.random.default_rng(rec["seed"]))[rec["index"]]
+    h = dd_ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
+    ref = complex(*rec["haf"])
+    err = relerr(h, ref)
+    u_or = U64 if rec["oracle"] == "long double" else U53
+    k2 = rec.get("kappa2")
+    tol = n * n * u_or * (k2 if k2 is not None else rec["kappa"]) + 8 * U53
+    print(f"n={n} idx={rec['index']} oracle={rec['oracle']} kappa={rec['kappa']:.2e} err={err:.2e} "
+          f"tol={tol:.2e} fp64 bound={bound(n, rec['kappa'], k2, 'long double'):.2e}")
+    assert err <= tol, (n, err, tol)
+
+
+@pytest.mark.parametrize("n", list(range(0, 25)))
+def test_dd_small_n_against_matching_sum(dd_ctx, torch_dev, n):
+    """n = 0..24 (odd n give 0, n = 0 gives 1): a batch of three random matrices against the oracle's
+    matching sum (Eq. HafMatch)."""
+    rng = np.random.default_rng(4800 + n)
+    A = inputs.random_symmetric(n, 3, rng) if n else np.zeros((3, 0, 0), np.complex128)
+    h = dd_ctx.haf_batch(to_dev(A, torch_dev)).cpu().numpy()
+    for i in range(3):
+        if n == 0:
+            assert h[i] == 1
+        elif n % 2:
+            assert h[i] == 0
+        else:
+            ref = oracle.haf_enum(A[i])
+            assert relerr(h[i], ref) < 1e-12, (n, i, relerr(h[i], ref))
+
+
+def test_dd_prob_batch_config5(dd_ctx, torch_dev):
+    """GBS probabilities (Eq. (3)) of the config-5 patterns with stored long-double oracle hafnians:
+    within twice the oracle's bound (p = |Haf|^2 / prod cosh r) plus FP64 rounding."""
+    p = GOLD / "config5_haf.json"
+    recs = [r for r in json.loads(p.read_text())["records"] if "haf_pt_ld" in r] if p.exists() else []
+    if not recs:
+        pytest.skip("no long-double config-5 values stored")
+    st_in, pats = inputs.config5()
+    st = dd_ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    sel = [[int(v) for v in pats[r["index"]]] for r in recs]
+    prob = dd_ctx.prob_batch(st, sel).cpu().numpy()
+    pref = float(np.prod(1.0 / np.cosh(st_in.r)))
+    for r, pr in zip(recs, prob):
+        ref = abs(complex(*r["haf_pt_ld"])) ** 2 * pref
+        n = r["n"]
+        tol = 2 * n * n * U64 * (r.get("kappa2") or r["kappa"]) + 16 * U53
+        err = abs(pr - ref) / ref
+        print(f"index={r['index']} n={n} kappa={r['kappa']:.2e} err={err:.2e} tol={tol:.2e}")
+        assert err <= tol, (r["index"], err, tol)
+
+
+def test_dd_mixed_sizes_noalloc_and_switch(dd_ctx, fp_ctx, torch_dev):
+    """One varlen call with every n = 0..30 gives each matrix's single-call result bit for bit; the
+    no-allocation entry point gives haf_batch's; switching a context back to FP64 gives the FP64
+    engines' results again."""
+    from paper_1908_10070_amd import gbs
+    rng = np.random.default_rng(4900)
+    mats = [inputs.random_symmetric(n, 1, rng)[0] if n else np.zeros((0, 0), np.complex128) for n in range(0, 31)]
+    ns = np.array([a.shape[0] for a in mats], dtype=np.int32)
+    off = np.zeros(len(mats), dtype=np.int64)
+    off[1:] = np.cumsum([a.size for a in mats[:-1]])
+    flat = np.concatenate([a.reshape(-1) for a in mats] + [np.zeros(1, np.complex128)])
+    A_dev = to_dev(flat, torch_dev)
+    h = dd_ctx.haf_batch_varlen(A_dev, off, ns).cpu().numpy()
+    for i in (0, 1, 2, 16, 17, 26, 30):
+        alone = dd_ctx.haf_batch_varlen(A_dev, off[i:i + 1], ns[i:i + 1]).cpu().numpy()[0]
+        assert alone == h[i], int(ns[i])
+    B28 = to_dev(inputs.random_symmetric(28, 4, rng), torch_dev)
+    ref = dd_ctx.haf_batch(B28).cpu().numpy()
+    import torch
+    na = dd_ctx.haf_batch_noalloc(B28, torch.empty(4, dtype=torch.complex128, device=torch_dev)).cpu().numpy()
+    assert np.array_equal(na, ref)
+    c = gbs.Context(0)
+    c.set_precision(gbs.GBS_PREC_DD)
+    assert np.array_equal(c.haf_batch(B28).cpu().numpy(), ref)
+    c.set_precision("fp64")
+    assert c.precision == "fp64"
+    assert np.array_equal(c.haf_batch(B28).cpu().numpy(), fp_ctx.haf_batch(B28).cpu().numpy())
+    with pytest.raises(gbs.GBSError) as ei:
+        c.set_precision(7)
+    assert ei.value.status == gbs.GBS_EINVAL
+
+
+def test_dd_timing_n40(dd_ctx, fp_ctx, torch_dev):
+    """Cost of the accuracy mode against FP64 at n = 40 (printed; bounded loosely)."""
+    import time
+    import torch
+    A = to_dev(inputs.random_symmetric(40, 2, np.random.default_rng(4901)), torch_dev)
+    out = {}
+    for name, c in (("fp64", fp_ctx), ("dd", dd_ctx)):
+        c.haf_batch(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = c.haf_batch(A)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0, h.cpu().numpy())
+    print(f"n=40 batch 2: fp64 {out['fp64'][0] * 1e3:.1f} ms, dd {out['dd'][0] * 1e3:.1f} ms, "
+          f"ratio {out['dd'][0] / out['fp64'][0]:.1f}; max |dd - fp64| / |dd| = "
+          f"{np.max(np.abs(out['dd'][1] - out['fp64'][1]) / np.abs(out['dd'][1])):.2e}")
+    assert out["dd"][0] < 60.0
