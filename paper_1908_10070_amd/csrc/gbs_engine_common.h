@@ -286,12 +286,14 @@ struct PatternView {
 // Gather from the zero-padded staged copy that the item loop below writes (ld = n + 1, row n and
 // column n zero): offset of row a and index of column c of M_Z = X A_Z (d x d) for the pair list
 // pl; rows and columns at or beyond d map to the zero row / column, so every read is unconditional.
+// The pair list is read through an LDS-qualified pointer: 32-bit addresses, direct ds_read.
+typedef const __attribute__((address_space(3))) int32_t lds_i32;
 __device__ __forceinline__ int mz_row(const PatternView& P, const int32_t* pl, int a, int d) {
   const int b = a ^ 1;  // row a of M is row a^1 of A_Z
-  return (a < d ? 2 * pl[b >> 1] + (b & 1) : P.n) * P.ld;
+  return (a < d ? 2 * ((lds_i32*)pl)[b >> 1] + (b & 1) : P.n) * P.ld;
 }
 __device__ __forceinline__ int mz_col(const PatternView& P, const int32_t* pl, int c, int d) {
-  return c < d ? 2 * pl[c >> 1] + (c & 1) : P.n;
+  return c < d ? 2 * ((lds_i32*)pl)[c >> 1] + (c & 1) : P.n;
 }
 __device__ __forceinline__ double2 mz_at(const PatternView& P, int off) {
   lds_d* Al = (lds_d*)P.lds;
@@ -508,7 +510,9 @@ __device__ __forceinline__ void wave_items(const EngineArgs& args, unsigned char
   int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
   double* part = reinterpret_cast<double*>(smem + L.part);
   int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // the wave index is uniform across the wave: readfirstlane lets the compiler keep everything
+  // derived from it (the wave's subset range, masks, sizes) in scalar registers
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
 
   int it = args.persistent ? 0 : (int)blockIdx.x;
   for (;;) {
