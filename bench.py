@@ -167,7 +167,42 @@ def config5_extra(gbs, torch, dev, ctx):
         rows.append(row)
     out["vs_oracle"] = rows
     out["max_rel_err"] = max((r["rel_err"] for r in rows), default=None)
+    out["double_double"] = config5_dd(gbs, torch, dev, ctx, st_in, pats, h, recs)
     return out
+
+
+def config5_dd(gbs, torch, dev, ctx, st_in, pats, h_fp64, recs, sample=6):
+    """The double-double accuracy mode on the first `sample` config-5 patterns (two each of n = 36, 40,
+    44): its time against FP64 on the same patterns, its error against the stored oracle values, and
+    how far the FP64 results lie from it."""
+    sel = [list(map(int, p)) for p in pats[:sample]]
+    c = gbs.Context(0)
+    c.set_precision("dd")
+    st = c.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
+    haf = torch.empty(len(sel), dtype=torch.complex128, device=dev)
+    c.prob_batch(st, [sel[0][:4]], want_haf=True)  # plan and graph machinery warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.prob_batch(st, sel, haf_out=haf)
+    torch.cuda.synchronize()
+    t_dd = time.perf_counter() - t0
+    st64 = ctx.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
+    t_fp = _timed(lambda: ctx.prob_batch(st64, sel), reps=2)
+    hd = haf.cpu().numpy()
+    rows = []
+    for r in recs:
+        if r["index"] >= sample:
+            continue
+        ld = "haf_pt_ld" in r
+        ref = complex(*(r["haf_pt_ld"] if ld else r["haf_pt"]))
+        rows.append({"index": r["index"], "n": r["n"], "ref": "long double" if ld else "double",
+                     "dd_rel_err": float(rel_errs(hd[r["index"]], ref)),
+                     "fp64_rel_err": float(rel_errs(h_fp64[r["index"]], ref))})
+    return {"patterns": sample, "ns": [len(p) for p in sel], "seconds": t_dd, "fp64_seconds": t_fp,
+            "cost_factor": t_dd / t_fp, "vs_oracle": rows,
+            "max_fp64_vs_dd": float(np.max(rel_errs(h_fp64[:sample], hd))),
+            "note": "gbs_ctx_set_precision(GBS_PREC_DD): double-double subset sum on the VALU; the oracle "
+                    "values' own error (long double, n^2 2^-64 kappa2) bounds what dd_rel_err can show"}
 
 
 def extras(gbs, torch, dev, args):
@@ -339,8 +374,9 @@ def main():
     elif args.no_tune:
         chunks = ctx.get_tuning(n)
     else:
-        chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(16, 32, 64, 128, 256),
+        chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(64, 128, 256, 512),
                                cache=None, log=tune_log)
+    shape = ctx.get_shape(n)
 
     for _ in range(args.warmup):
         ctx.haf_batch(A, out=out)
@@ -384,7 +420,9 @@ def main():
         "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
         "config": {"workload": "config2: 4096 random complex-symmetric 24x24 matrices (seed 1002), haf_batch, "
                                "persistent launch replayed from a HIP graph", "n": n, "batch": batch,
-                   "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1])},
+                   "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1]), "engine_shape": int(shape),
+                   "launch_shape_from": "chunks given" if args.chunks else ("built-in table" if args.no_tune
+                                                                             else "autotuned here")},
         "max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),
         "err_sample": f"timed run's output of the first {len(cpu_vals)} matrices vs the oracle's haf_pt (FP64 power "
                       f"trace); the stated tolerance is 1e-9",

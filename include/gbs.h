@@ -119,6 +119,19 @@ int32_t gbs_ctx_get_precision(const gbs_ctx* ctx);
 int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chunk_large);
 int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int64_t* chunk_large);
 
+/* Engine shape (what the autotuner picks besides the chunk sizes): for photon number n, which
+ * engine evaluates the middle subset sizes. Bits:
+ *   GBS_SHAPE_TILE_9_10   |Z| = 9, 10 on the 16x16-tile engine (2x2 tiles) instead of the 4x4-tile
+ *                         quad engine on a 5x5 grid;
+ *   GBS_SHAPE_TILE_11_12  |Z| = 11, 12 on the 16x16-tile engine instead of the strip engine
+ *                         (k <= 16) or the quad-tile engine (k >= 17).
+ * 0 is the built-in choice; -1 removes the entry (back to the built-in table). Results differ only
+ * at the rounding level. GBS_ERANGE for n outside [0, GBS_N_MAX], GBS_EINVAL for unknown bits. */
+#define GBS_SHAPE_TILE_9_10 1
+#define GBS_SHAPE_TILE_11_12 2
+int gbs_ctx_set_shape(gbs_ctx* ctx, int32_t n, int32_t shape);
+int gbs_ctx_get_shape(const gbs_ctx* ctx, int32_t n, int32_t* shape);
+
 /* Algorithmic FP64 flop count of one hafnian of size n: the power-trace method as formulated, every
  * pair subset Z forming all n/2 traces with the library's chain program for n/2 (matrix products,
  * trace inner products, coefficient recursion; a complex multiply-add counts 8). The kernels do

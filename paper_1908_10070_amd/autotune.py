@@ -1,4 +1,4 @@
-"""Autotuner for the work-item chunk sizes of the subset engines.
+"""Autotuner for the launch shape of the subset engines: work-item chunk sizes and engine choice.
 
 The library cuts every pattern's subset order into work items: ``chunk_small`` subsets per item
 for |Z| <= 8 (the quad and one-tile engines) and ``chunk_large`` for larger subsets (tile
@@ -7,10 +7,12 @@ staging of the pattern matrix and the per-wave trace buffers. The best pair depe
 batch size and on the device, so it is measured:
 
 * a coordinate search -- ``chunk_small`` over its candidates with the default ``chunk_large``,
-  then ``chunk_large`` with the best ``chunk_small`` -- timing the real call (``haf_batch`` on the
-  caller's matrices) with HIP events, median of a few repetitions;
-* the winner goes to ``gbs_ctx_set_tuning`` and to a JSON cache keyed by (GPU arch, n), so later
-  contexts load it without measuring (``load_cache``).
+  then ``chunk_large`` with the best ``chunk_small``, then the engine shape (which engine takes
+  |Z| = 9, 10 and |Z| = 11, 12: the 4x4-tile quad grid and strip / quad-tile engines, or the 16x16
+  tile engine; ``gbs_ctx_set_shape``) over the shapes that change anything at this n -- timing the
+  real call (``haf_batch`` on the caller's matrices) with HIP events, median of a few repetitions;
+* the winner goes to ``gbs_ctx_set_tuning`` / ``gbs_ctx_set_shape`` and to a JSON cache keyed by
+  (GPU arch, n), so later contexts load it without measuring (``load_cache``).
 
 Results depend on the chunk sizes only through the order partial sums are added in, i.e. at the
 rounding level; within one context every pattern's result is independent of the batch around it.
@@ -26,7 +28,7 @@ from typing import Dict, Iterable, Optional, Tuple
 DEFAULT_CACHE = pathlib.Path(os.environ.get("GBS_TUNE_CACHE", pathlib.Path.home() / ".cache" / "gbs_tune.json"))
 
 SMALL_CANDIDATES = (128, 256, 512, 1024, 2048, 4096)
-LARGE_CANDIDATES = (8, 16, 32, 64, 128)
+LARGE_CANDIDATES = (8, 16, 32, 64, 128, 256, 512)
 
 
 def _arch(ctx) -> str:
@@ -52,8 +54,10 @@ def _time_call(fn, reps: int) -> float:
 
 def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
          large: Iterable[int] = LARGE_CANDIDATES, cache: Optional[pathlib.Path] = DEFAULT_CACHE,
-         log: Optional[list] = None) -> Tuple[int, int]:
-    """Measure chunk sizes for size-n hafnians of the (batch, n, n) CUDA tensor A; apply and cache them."""
+         log: Optional[list] = None, shapes=True) -> Tuple[int, int]:
+    """Measure chunk sizes, then the engine shape (shapes=True: every shape that differs at n; a
+    tuple: those; False: keep the built-in one), for size-n hafnians of the (batch, n, n) CUDA
+    tensor A; apply and cache them. Returns the chunk pair (the shape is ctx.get_shape(n))."""
     import torch
     out = torch.empty(A.shape[0], dtype=torch.complex128, device=A.device)
     ctx.set_tuning(n, 0, 0)  # start from the built-in defaults
@@ -66,12 +70,36 @@ def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
             log.append({"n": n, "chunk_small": cs, "chunk_large": cl, "ms": t})
         return t
 
+    ctx.set_shape(n, -1)
+    d_shape = ctx.get_shape(n)
     best_s = min(small, key=lambda cs: run(cs, d_large))
     best_l = min(large, key=lambda cl: run(best_s, cl))
     ctx.set_tuning(n, best_s, best_l)
+    best_shape = d_shape
+    if shapes:
+        def run_shape(sh):
+            ctx.set_shape(n, sh)
+            t = _time_call(lambda: ctx.haf_batch(A, out=out), reps)
+            if log is not None:
+                log.append({"n": n, "chunk_small": best_s, "chunk_large": best_l, "shape": sh, "ms": t})
+            return t
+        best_shape = min(shapes_for(n) if shapes is True else shapes, key=run_shape)
+    ctx.set_shape(n, best_shape)
     if cache is not None:
-        save_cache({(_arch(ctx), n): (best_s, best_l)}, cache)
+        save_cache({(_arch(ctx), n): (best_s, best_l, best_shape)}, cache)
     return best_s, best_l
+
+
+def shapes_for(n: int) -> Tuple[int, ...]:
+    """Engine shapes that differ at photon number n: the |Z| = 9, 10 bit needs k >= 9, the |Z| = 11,
+    12 bit k >= 11."""
+    k = n // 2
+    out = [0]
+    if k >= 9:
+        out.append(1)
+    if k >= 11:
+        out += [2, 3]
+    return tuple(out)
 
 
 def save_cache(entries: Dict[tuple, Tuple[int, int]], path: pathlib.Path = DEFAULT_CACHE) -> None:
@@ -82,8 +110,11 @@ def save_cache(entries: Dict[tuple, Tuple[int, int]], path: pathlib.Path = DEFAU
             data = json.loads(path.read_text())
         except (OSError, ValueError):
             data = {}
-    for (arch, n), (cs, cl) in entries.items():
-        data[f"{arch}:{n}"] = {"chunk_small": int(cs), "chunk_large": int(cl)}
+    for (arch, n), v in entries.items():
+        e = {"chunk_small": int(v[0]), "chunk_large": int(v[1])}
+        if len(v) > 2:
+            e["shape"] = int(v[2])
+        data[f"{arch}:{n}"] = e
     path.parent.mkdir(parents=True, exist_ok=True)
     tmp = path.with_suffix(".tmp%d" % os.getpid())
     tmp.write_text(json.dumps(data, indent=1, sort_keys=True))
@@ -105,5 +136,43 @@ def load_cache(ctx, path: pathlib.Path = DEFAULT_CACHE) -> int:
         a, _, n = key.rpartition(":")
         if a == arch:
             ctx.set_tuning(int(n), int(v["chunk_small"]), int(v["chunk_large"]))
+            if "shape" in v:
+                ctx.set_shape(int(n), int(v["shape"]))
             k += 1
     return k
+
+
+# Batch per n for the table: about 5..350 ms of work per call on one MI355X.
+TABLE_BATCH = {16: 16384, 18: 16384, 20: 16384, 22: 8192, 24: 4096, 26: 2048, 28: 1024, 30: 512, 32: 256,
+               34: 128, 36: 64, 38: 32, 40: 16, 42: 8, 44: 4, 46: 2}
+
+
+def tune_table(ns=None, seed: int = 7700, log=None) -> Dict[int, dict]:
+    """Tune every n of ``ns`` (default n = 16..46) on random complex-symmetric matrices (seed + n)
+    in a fresh context each; returns {n: {chunk_small, chunk_large, shape, best_ms}} -- the library's
+    built-in table (kDefaultShape in the runtime) is this output."""
+    import numpy as np
+    import torch
+    from paper_1908_10070_amd import gbs, inputs
+    out = {}
+    for n in (ns or sorted(TABLE_BATCH)):
+        ctx = gbs.Context(0)
+        A = torch.from_numpy(inputs.random_symmetric(n, TABLE_BATCH[n], np.random.default_rng(seed + n))).cuda()
+        lg = []
+        cs, cl = tune(ctx, n, A, reps=3 if n <= 40 else 1, cache=None, log=lg)
+        out[n] = {"batch": TABLE_BATCH[n], "chunk_small": cs, "chunk_large": cl, "shape": ctx.get_shape(n),
+                  "best_ms": min(r["ms"] for r in lg)}
+        if log is not None:
+            log.extend(lg)
+        print(f"n={n}: chunks {cs}/{cl} shape {out[n]['shape']} ({out[n]['best_ms']:.3f} ms)", flush=True)
+        ctx.close()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="autotune the launch shape for every n and print the table")
+    ap.add_argument("--table", action="store_true", required=True)
+    ap.add_argument("ns", nargs="*", type=int)
+    a = ap.parse_args()
+    print(json.dumps(tune_table(a.ns or None), indent=1))

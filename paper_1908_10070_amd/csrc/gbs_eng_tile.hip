@@ -1,6 +1,7 @@
 // Subset-engine kernels for the largest subsets: quad-tile engine for |Z| = 11, 12 at k = 17..23
-// (classes kClsQtile + k - 17), tile engine with 2x2 16x16 tiles for |Z| = 13..16 at k = 13..23
-// (kClsTile2 + k - 13) and with 3x3 tiles for |Z| >= 17 at k = 17..23 (kClsTile3 + k - 17).
+// (classes kClsQtile + k - 17), tile engine with 2x2 16x16 tiles for |Z| = 13..16 (and 9..12 where
+// the engine shape asks for it) at k = 9..23 (kClsTile2 + k - 9) and with 3x3 tiles for |Z| >= 17 at
+// k = 17..23 (kClsTile3 + k - 17).
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -21,7 +22,7 @@ static void fill_qtile(EngineVariant* tab, std::integer_sequence<int, I...>) {
 
 template <int... I>
 static void fill_tile2(EngineVariant* tab, std::integer_sequence<int, I...>) {
-  ((tab[kClsTile2 + I] = EngineVariant{reinterpret_cast<const void*>(&tile_engine_kernel<2, I + 13>), 256,
+  ((tab[kClsTile2 + I] = EngineVariant{reinterpret_cast<const void*>(&tile_engine_kernel<2, I + 9>), 256,
                                        kTileKind, 2}),
    ...);
 }
@@ -35,7 +36,7 @@ static void fill_tile3(EngineVariant* tab, std::integer_sequence<int, I...>) {
 
 void register_tile_engines(EngineVariant* tab) {
   fill_qtile(tab, std::make_integer_sequence<int, 7>{});
-  fill_tile2(tab, std::make_integer_sequence<int, 11>{});
+  fill_tile2(tab, std::make_integer_sequence<int, 15>{});
   fill_tile3(tab, std::make_integer_sequence<int, 7>{});
 }
 

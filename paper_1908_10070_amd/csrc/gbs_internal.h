@@ -112,12 +112,19 @@ struct MargArgs {
 //   42..56  quad engine on a 5x5 tile grid, |Z| = 9, 10, k = 9..23   (gbs_eng_grid5.hip)
 //   57..62  strip engine, 6 tile rows, |Z| = 11, 12, k = 11..16      (gbs_eng_strip.hip)
 //   63..69  quad-tile engine, |Z| = 11, 12, k = 17..23               (gbs_eng_tile.hip)
-//   70..80  tile engine, 2x2 16x16 tiles, |Z| = 13..16, k = 13..23   (gbs_eng_tile.hip)
-//   81..87  tile engine, 3x3 16x16 tiles, |Z| >= 17, k = 17..23      (gbs_eng_tile.hip)
-//   88..90  double-double engine (accuracy mode), 2|Z| <= 16, 32, 48; any k (gbs_eng_dd.hip)
-constexpr int kEngineClasses = 91;
+//   70..84  tile engine, 2x2 16x16 tiles, |Z| = 13..16 (and 9..12 where the engine shape asks for
+//           it), k = 9..23                                             (gbs_eng_tile.hip)
+//   85..91  tile engine, 3x3 16x16 tiles, |Z| >= 17, k = 17..23      (gbs_eng_tile.hip)
+//   92..94  double-double engine (accuracy mode), 2|Z| <= 16, 32, 48; any k (gbs_eng_dd.hip)
+constexpr int kEngineClasses = 95;
 constexpr int kClsQuad = 0, kClsGrid4 = 23, kClsGrid5 = 42, kClsStrip = 57, kClsQtile = 63, kClsTile2 = 70,
-              kClsTile3 = 81, kClsDd = 88;
+              kClsTile3 = 85, kClsDd = 92;
+
+// Engine shape bits (per photon number, chosen by the autotuner): which engine takes the middle
+// subset sizes. Bit set: the 16x16 tile engine (2x2 tiles) instead of the default.
+constexpr int kShapeTile910 = 1;   // |Z| = 9, 10: tile engine instead of the 5x5 quad grid
+constexpr int kShapeTile1112 = 2;  // |Z| = 11, 12: tile engine instead of the strip / quad-tile engine
+constexpr int kShapeMask = 3;
 
 enum EngineKind { kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3, kDdKind = 4 };
 
@@ -196,7 +203,7 @@ void launch_cdf_draw(const double* cdf, int64_t count, const double* total, cons
                      int64_t* idx, hipStream_t s);
 
 // Host-side launchers (defined in gbs_kernels.hip).
-int engine_class(int s, int k);    // variant for subsets of size s of a pattern with k pairs
+int engine_class(int s, int k, int shape = 0);  // variant for subsets of size s, k pairs, engine shape bits
 int engine_class_dd(int s);        // double-double variant for subsets of size s
 size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);
 int engine_blocks_per_cu(int cls, size_t lds);

@@ -409,12 +409,17 @@ static EngineVariant variant(int cls) {
 // MFMA; only the tiles on and above the diagonal), the strip engine for |Z| = 11, 12 up to k = 16 and
 // the quad-tile engine above (where the strip engine's registers spill), the 16x16 tile engines
 // (2x2 and 3x3 tiles per workgroup) for larger subsets.
-int engine_class(int s, int k) {
+// The shape bits move |Z| = 9, 10 and |Z| = 11, 12 to the 2x2 tile engine (chosen per n by the
+// autotuner).
+int engine_class(int s, int k, int shape) {
   if (s <= 6) return kClsQuad + (k - 1);
   if (s <= 8) return kClsGrid4 + (k - 5);
-  if (s <= 10) return kClsGrid5 + (k - 9);
-  if (s <= 12) return k <= 16 ? kClsStrip + (k - 11) : kClsQtile + (k - 17);
-  if (s <= 16) return kClsTile2 + (k - 13);
+  if (s <= 10) return (shape & kShapeTile910) ? kClsTile2 + (k - 9) : kClsGrid5 + (k - 9);
+  if (s <= 12) {
+    if (shape & kShapeTile1112) return kClsTile2 + (k - 9);
+    return k <= 16 ? kClsStrip + (k - 11) : kClsQtile + (k - 17);
+  }
+  if (s <= 16) return kClsTile2 + (k - 9);
   return kClsTile3 + (k - 17);
 }
 

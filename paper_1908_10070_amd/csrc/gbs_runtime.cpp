@@ -78,6 +78,7 @@ struct gbs_ctx {
   int persistent = 1;
   int precision = kPrecFp64;
   std::map<int, std::pair<int64_t, int64_t>> tuning;
+  std::map<int, int> shape;  // engine shape bits per n (kShape*)
   std::string last_error;
   std::list<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
 };
@@ -125,11 +126,24 @@ struct DeviceGuard {
   }
 };
 
+// Built-in launch shape per even n: the autotuner's picks (autotune.tune over chunk sizes and engine
+// shapes, haf_batch on random complex-symmetric matrices, one MI355X; python -m
+// paper_1908_10070_amd.autotune --table reproduces it). Rows below n = 16 repeat n = 16's (a
+// pattern's subsets fit one item either way). {chunk_small, chunk_large, shape}
+struct ShapeRow {
+  int32_t cs, cl, shape;
+};
+constexpr ShapeRow kDefaultShape[GBS_N_MAX / 2 + 1] = {
+    {2048, 64, 0},  {2048, 64, 0},  {2048, 64, 0},  {2048, 64, 0},  {2048, 64, 0},  {2048, 64, 0},
+    {2048, 64, 0},  {2048, 64, 0},  {2048, 64, 0},  {256, 16, 1},   {256, 256, 0},  {512, 256, 2},
+    {512, 512, 0},  {1024, 512, 0}, {512, 512, 0},  {512, 256, 2},  {512, 256, 2},  {512, 128, 0},
+    {256, 128, 0},  {2048, 128, 0}, {1024, 128, 0}, {4096, 256, 0}, {2048, 128, 0}, {4096, 128, 0},
+};
+
 void default_chunks(int n, int64_t* cs, int64_t* cl) {
-  // small-subset items: enough subsets to amortise staging, few enough to balance the quad engine's
-  // larger grids; large-subset items: ~100 us of work (measured: n = 20 prefers 256/64, n = 24 512/64)
-  *cs = n <= 20 ? 256 : 512;
-  *cl = n <= 24 ? 64 : (n <= 32 ? 32 : (n <= 40 ? 16 : 8));
+  const ShapeRow& r = kDefaultShape[(n < 0 ? 0 : (n > GBS_N_MAX ? GBS_N_MAX : n)) / 2];
+  *cs = r.cs;
+  *cl = r.cl;
 }
 
 void chunks_for(const gbs_ctx* ctx, int n, int64_t* cs, int64_t* cl) {
@@ -139,6 +153,14 @@ void chunks_for(const gbs_ctx* ctx, int n, int64_t* cs, int64_t* cl) {
     if (it->second.first > 0) *cs = it->second.first;
     if (it->second.second > 0) *cl = it->second.second;
   }
+}
+
+// Engine shape bits for size-n patterns: the caller's (autotuner's) choice, else the built-in table.
+int default_shape(int n) { return kDefaultShape[(n < 0 ? 0 : (n > GBS_N_MAX ? GBS_N_MAX : n)) / 2].shape; }
+
+int shape_for(const gbs_ctx* ctx, int n) {
+  auto it = ctx->shape.find(n);
+  return it != ctx->shape.end() ? it->second : default_shape(n);
 }
 
 // Host-side plan of one call, laid out exactly as it is copied into the device workspace.
@@ -179,7 +201,8 @@ std::vector<ClassRun> class_runs(const gbs_ctx* ctx, int n, int64_t lo, int64_t 
   int64_t cs, cl;
   chunks_for(ctx, n, &cs, &cl);
   const bool dd = ctx->precision == kPrecDd;
-  auto cls_of = [&](int s) { return dd ? engine_class_dd(s) : engine_class(s, k); };
+  const int shape = shape_for(ctx, n);
+  auto cls_of = [&](int s) { return dd ? engine_class_dd(s) : engine_class(s, k, shape); };
   for (int s_lo = 1; s_lo <= k;) {
     const int cls = cls_of(s_lo);
     int s_hi = s_lo;
@@ -602,6 +625,26 @@ int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chu
   if (!ctx) return GBS_EINVAL;
   if (n < 0 || n > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n = %d outside [0, %d]", n, GBS_N_MAX);
   ctx->tuning[n] = {chunk_small, chunk_large};
+  return GBS_OK;
+}
+
+int gbs_ctx_set_shape(gbs_ctx* ctx, int32_t n, int32_t shape) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (n < 0 || n > GBS_N_MAX) return fail(ctx, GBS_ERANGE, "n = %d outside [0, %d]", n, GBS_N_MAX);
+  if (shape == -1) {
+    ctx->shape.erase(n);
+    return GBS_OK;
+  }
+  if (shape & ~kShapeMask) return fail(ctx, GBS_EINVAL, "unknown engine shape bits 0x%x", shape);
+  ctx->shape[n] = shape;
+  return GBS_OK;
+}
+
+int gbs_ctx_get_shape(const gbs_ctx* ctx, int32_t n, int32_t* shape) {
+  if (!ctx || !shape) return GBS_EINVAL;
+  if (n < 0 || n > GBS_N_MAX) return GBS_ERANGE;
+  *shape = shape_for(ctx, n);
   return GBS_OK;
 }
 

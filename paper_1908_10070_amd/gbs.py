@@ -21,11 +21,12 @@ GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6
 GBS_N_MAX = 46
 GBS_MARGINAL_KMAX = 20
 GBS_PREC_FP64, GBS_PREC_DD = 0, 1
+GBS_SHAPE_TILE_9_10, GBS_SHAPE_TILE_11_12 = 1, 2
 
 # Every function declared in include/gbs.h.
 EXPORTS = [
     "gbs_ctx_create", "gbs_ctx_destroy", "gbs_ctx_set_workspace", "gbs_ctx_workspace_needed", "gbs_status_str",
-    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_precision", "gbs_ctx_get_precision", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_haf_flops",
+    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_precision", "gbs_ctx_get_precision", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_ctx_set_shape", "gbs_ctx_get_shape", "gbs_haf_flops",
     "haf_batch", "haf_batch_varlen", "haf_batch_noalloc", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
     "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
     "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step", "gbs_sweep_count",
@@ -68,6 +69,8 @@ def lib() -> ctypes.CDLL:
         "gbs_ctx_get_precision": (i32, [vp]),
         "gbs_ctx_set_tuning": (ctypes.c_int, [vp, i32, i64, i64]),
         "gbs_ctx_get_tuning": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "gbs_ctx_set_shape": (ctypes.c_int, [vp, i32, i32]),
+        "gbs_ctx_get_shape": (ctypes.c_int, [vp, i32, ctypes.POINTER(i32)]),
         "gbs_haf_flops": (ctypes.c_double, [i32]),
         "haf_batch": (ctypes.c_int, [vp, dp, i32, i64, i64, dp, vp]),
         "haf_batch_varlen": (ctypes.c_int, [vp, dp, dp, dp, i64, dp, vp]),
@@ -271,9 +274,19 @@ class Context:
         self._check(lib().gbs_ctx_set_tuning(self.handle, int(n), int(chunk_small), int(chunk_large)))
 
     def _copy_tuning_from(self, other: "Context"):
-        """The launch-shape table of another context (every n it has an entry for)."""
+        """The launch-shape table of another context: chunk sizes and engine shape for every n."""
         for n in range(0, GBS_N_MAX + 1):
             self.set_tuning(n, *other.get_tuning(n))
+            self.set_shape(n, other.get_shape(n))
+
+    def set_shape(self, n: int, shape: int):
+        """Engine shape bits for size-n patterns (GBS_SHAPE_*); -1 restores the built-in choice."""
+        self._check(lib().gbs_ctx_set_shape(self.handle, int(n), int(shape)))
+
+    def get_shape(self, n: int) -> int:
+        v = ctypes.c_int32()
+        self._check(lib().gbs_ctx_get_shape(self.handle, int(n), ctypes.byref(v)))
+        return v.value
 
     def get_tuning(self, n: int) -> Tuple[int, int]:
         a, b = ctypes.c_int64(), ctypes.c_int64()

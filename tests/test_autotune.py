@@ -10,22 +10,38 @@ from paper_1908_10070_amd import autotune
 class FakeCtx:
     def __init__(self):
         self.t = {}
+        self.sh = {}
 
     def set_tuning(self, n, cs, cl):
         self.t[n] = (cs, cl)
+
+    def set_shape(self, n, shape):
+        self.sh[n] = shape
 
 
 def test_cache_round_trip(tmp_path, monkeypatch):
     path = tmp_path / "tune.json"
     autotune.save_cache({("gfx950", 24): (512, 16), ("gfx942", 24): (1024, 32)}, path)
-    autotune.save_cache({("gfx950", 20): (256, 8)}, path)
+    autotune.save_cache({("gfx950", 20): (256, 8), ("gfx950", 30): (512, 32, 3)}, path)
     data = json.loads(path.read_text())
     assert data["gfx950:24"] == {"chunk_small": 512, "chunk_large": 16}
     assert data["gfx950:20"]["chunk_small"] == 256
+    assert data["gfx950:30"] == {"chunk_small": 512, "chunk_large": 32, "shape": 3}
     ctx = FakeCtx()
     monkeypatch.setattr(autotune, "_arch", lambda c: "gfx950")
-    assert autotune.load_cache(ctx, path) == 2
-    assert ctx.t == {24: (512, 16), 20: (256, 8)}
+    assert autotune.load_cache(ctx, path) == 3
+    assert ctx.t == {24: (512, 16), 20: (256, 8), 30: (512, 32)}
+    assert ctx.sh == {30: 3}
+
+
+def test_shapes_for():
+    """Only shapes that change the engine choice at n are searched: the |Z| = 9, 10 bit from k = 9,
+    the |Z| = 11, 12 bit from k = 11."""
+    assert autotune.shapes_for(16) == (0,)
+    assert autotune.shapes_for(18) == (0, 1)
+    assert autotune.shapes_for(20) == (0, 1)
+    assert autotune.shapes_for(22) == (0, 1, 2, 3)
+    assert autotune.shapes_for(46) == (0, 1, 2, 3)
 
 
 def test_load_cache_missing_or_corrupt(tmp_path, monkeypatch):
@@ -48,7 +64,8 @@ def test_tune_on_device(tmp_path):
     A = torch.from_numpy(A_host).cuda()
     log = []
     cs, cl = autotune.tune(ctx, 18, A, reps=1, small=(64, 256), large=(8, 32), cache=tmp_path / "t.json", log=log)
-    assert (cs, cl) == ctx.get_tuning(18) and len(log) == 4
+    assert (cs, cl) == ctx.get_tuning(18) and len(log) == 6  # 2 + 2 chunk trials, shapes 0 and 1
+    assert ctx.get_shape(18) in (0, 1)
     assert json.loads((tmp_path / "t.json").read_text())
     h = ctx.haf_batch(A).cpu().numpy()
     for i in (0, 100, 255):

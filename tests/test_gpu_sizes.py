@@ -171,6 +171,42 @@ def test_prob_batch_mixed_sizes(ctx, torch_dev):
     del B
 
 
+@pytest.mark.parametrize("n,shape", [(24, 1), (24, 2), (24, 3), (30, 3), (38, 1), (38, 2)])
+def test_engine_shapes(ctx, torch_dev, n, shape):
+    """The engine shapes the autotuner can pick (|Z| = 9, 10 and / or 11, 12 on the 16x16-tile engine)
+    give the oracle's values (n = 24 against the matching sum; n = 30, 38 against the stored ones)
+    and agree with the built-in shape up to the order of the partial sums."""
+    from paper_1908_10070_amd import gbs
+    if n <= 24:
+        A = inputs.random_symmetric(n, 8, np.random.default_rng(5100 + n))
+        refs = [oracle.haf_enum(a) for a in A]
+        tols = [TOL] * len(A)
+    else:
+        recs = [r for r in GENERAL if r["n"] == n]
+        if not recs:
+            pytest.skip(f"no stored value for n = {n}")
+        A = np.stack([general_matrix(r) for r in recs])
+        refs = [complex(*r["haf"]) for r in recs]
+        tols = [max(TOL, bound(n, r["kappa"], r.get("kappa2"), r["oracle"])) for r in recs]
+    A_dev = to_dev(A, torch_dev)
+    c = gbs.Context(0)
+    c.set_shape(n, shape)
+    assert c.get_shape(n) == shape
+    h = c.haf_batch(A_dev).cpu().numpy()
+    base = ctx.haf_batch(A_dev).cpu().numpy()
+    for i in range(len(A)):
+        assert relerr(h[i], refs[i]) <= tols[i], (n, shape, i)
+        assert relerr(h[i], base[i]) <= max(1e-11, 2 * tols[i]), (n, shape, i)
+    # the no-allocation entry point follows the same shape
+    import torch
+    out = torch.empty(len(A), dtype=torch.complex128, device=torch_dev)
+    assert np.array_equal(c.haf_batch_noalloc(A_dev, out).cpu().numpy(), h)
+    c.set_shape(n, -1)
+    assert c.get_shape(n) == 0
+    with pytest.raises(gbs.GBSError):
+        c.set_shape(n, 8)
+
+
 @pytest.mark.parametrize("chunks", [(512, 256), (2048, 16), (128, 8), (4096, 128)])
 def test_tuned_chunk_sizes(torch_dev, chunks):
     """The headline workload (config 2, n = 24) at chunk pairs the autotuner can pick: oracle parity
