@@ -19,7 +19,8 @@
  *   - gbs_c128 is bit-identical to C99 double _Complex, torch.complex128, hipDoubleComplex.
  *   - "_dev" pointers are device memory on the context's device; "_host" pointers are host memory.
  *   - Every entry point returns an int status (GBS_OK on success). Nothing throws or aborts
- *     across the ABI. On failure no work has been enqueued unless the status is GBS_EHIP.
+ *     across the ABI. On failure no work has been enqueued unless the status is GBS_EHIP (or
+ *     GBS_EINVAL from the debug symmetry check, which runs its own kernel first).
  *   - Compute calls enqueue on `stream` (a hipStream_t passed as void*; NULL = legacy default
  *     stream) and return at once; outputs are valid once the stream reaches the work.
  *     Host arrays are read before the call returns and may be reused afterwards.
@@ -97,6 +98,20 @@ const char* gbs_last_error(const gbs_ctx* ctx);
  *                atomic counter); 0 = one workgroup per work item.
  * Defaults: use_graph = 1, persistent = 1. */
 int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
+
+/* Debugging hooks (process-wide, any thread).
+ * gbs_debug_fault_inject(N): the N-th library call from now on that would enqueue compute work
+ *   (hafnians, probabilities, slices, finalize, marginals, sweeps, draws) returns GBS_EHIP with
+ *   "injected launch failure" in gbs_last_error and enqueues nothing; N <= 0 turns it off. The
+ *   environment variable GBS_FAULT_INJECT=launch:N sets the same at the first such call. For testing
+ *   the failure handling of callers (a server must fail that request only and keep serving).
+ * gbs_debug_check_symmetry(on): before haf_batch / haf_batch_varlen run, check every caller-provided
+ *   matrix for |A_ij - A_ji| <= 1e-12 max|A| (the power-trace formula assumes a symmetric matrix and
+ *   otherwise computes the hafnian of its symmetric part's pairing, silently); an asymmetric one makes
+ *   the call return GBS_EINVAL after the check's own kernel and a stream synchronisation. Also
+ *   GBS_CHECK_SYMMETRY=1 in the environment. Off by default: the check costs a synchronisation. */
+int gbs_debug_fault_inject(int64_t launch_n);
+int gbs_debug_check_symmetry(int32_t on);
 
 /* Arithmetic of the subset sum (Sec. III, the power-trace formula), per context:
  *   GBS_PREC_FP64: FP64 on the matrix cores (default). Rounding error about n^2 u kappa relative,

@@ -209,6 +209,8 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A);
 int engine_blocks_per_cu(int cls, size_t lds);
 void launch_engine(int cls, const EngineArgs& a, int grid, size_t lds, hipStream_t s);
 void launch_reset(int32_t* counter, int n, hipStream_t s);
+void launch_sym_check(const double2* A, const PatternDesc* pats, int64_t batch, double tol, int32_t* flags,
+                      hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
 void launch_state(const double2* U, const double* r, int m, double2* B, double2* W, double* prefactor, hipStream_t s);
 void launch_marginal(const MargArgs& a, int kmax, int64_t h_total, hipStream_t s);

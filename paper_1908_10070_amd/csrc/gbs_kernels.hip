@@ -70,6 +70,52 @@ __global__ void finalize_kernel(FinalizeArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- debug symmetry check
+
+// flags[b] = 1 if pattern b's matrix (haf path: row-major n x n at A + src) has a pair of entries with
+// |A_ij - A_ji| > tol * max |A|, else 0. NaN entries compare false and are ignored (they propagate).
+__global__ __launch_bounds__(256) void sym_check_kernel(const double2* A, const PatternDesc* pats, int64_t batch,
+                                                        double tol, int32_t* flags) {
+  __shared__ double red[256];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  for (int64_t b = blockIdx.x; b < batch; b += gridDim.x) {
+    const PatternDesc pd = pats[b];
+    const int n = pd.n;
+    const double2* M = A + pd.src;
+    double mx = 0.0;
+    for (int e = t; e < n * n; e += 256) {
+      const double2 v = M[e];
+      const double a = hypot(v.x, v.y);
+      if (a > mx) mx = a;
+    }
+    red[t] = mx;
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) red[t] = fmax(red[t], red[t + w]);
+      __syncthreads();
+    }
+    const double lim = tol * red[0];
+    for (int e = t; e < n * n; e += 256) {
+      const int i = e / n, j = e - (e / n) * n;
+      if (j > i) {
+        const double2 a = M[e], c = M[(int64_t)j * n + i];
+        if (hypot(a.x - c.x, a.y - c.y) > lim) atomicOr(&bad, 1);
+      }
+    }
+    __syncthreads();
+    if (t == 0) flags[b] = bad;
+    __syncthreads();
+  }
+}
+
+void launch_sym_check(const double2* A, const PatternDesc* pats, int64_t batch, double tol, int32_t* flags,
+                      hipStream_t s) {
+  const int64_t g = batch < 4096 ? batch : 4096;
+  if (g > 0) hipLaunchKernelGGL(sym_check_kernel, dim3((unsigned)g), dim3(256), 0, s, A, pats, batch, tol, flags);
+}
+
 // ---------------------------------------------------------------- state
 
 // B = U diag(tanh r) U^t (transpose), W = U U^t, prefactor = prod_i 1/cosh r_i.

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -114,6 +116,47 @@ int fail(gbs_ctx* ctx, int code, const char* fmt, ...) {
     hipError_t e_ = (expr);                                                                    \
     if (e_ != hipSuccess) return fail(ctx, GBS_EHIP, "%s: %s", #expr, hipGetErrorString(e_));  \
   } while (0)
+
+// Debugging hooks. Fault injection: the N-th call (counted from when it was armed) that would
+// enqueue compute work returns GBS_EHIP instead and enqueues nothing (GBS_FAULT_INJECT=launch:N in the
+// environment, read once, or gbs_debug_fault_inject). Symmetry check of caller-provided matrices
+// before the hafnian path runs (GBS_CHECK_SYMMETRY=1, or gbs_debug_check_symmetry).
+std::atomic<int64_t> g_launches{0};
+std::atomic<int64_t> g_fault_at{-2};  // -2: environment not read yet; <= 0: off
+std::atomic<int> g_check_sym{-1};     // -1: environment not read yet
+
+int64_t fault_at() {
+  int64_t v = g_fault_at.load(std::memory_order_acquire);
+  if (v == -2) {
+    int64_t e = 0;
+    if (const char* s = std::getenv("GBS_FAULT_INJECT")) {
+      long long q = 0;
+      if (std::sscanf(s, "launch:%lld", &q) == 1 && q > 0) e = q;
+    }
+    int64_t expect = -2;
+    g_fault_at.compare_exchange_strong(expect, e);
+    v = g_fault_at.load(std::memory_order_acquire);
+  }
+  return v;
+}
+
+bool check_symmetry_on() {
+  int v = g_check_sym.load(std::memory_order_acquire);
+  if (v < 0) {
+    const char* s = std::getenv("GBS_CHECK_SYMMETRY");
+    int expect = -1;
+    g_check_sym.compare_exchange_strong(expect, (s && s[0] && s[0] != '0') ? 1 : 0);
+    v = g_check_sym.load(std::memory_order_acquire);
+  }
+  return v > 0;
+}
+
+int launch_gate(gbs_ctx* ctx) {
+  const int64_t at = fault_at();
+  const int64_t k = g_launches.fetch_add(1, std::memory_order_acq_rel) + 1;
+  if (at > 0 && k == at) return fail(ctx, GBS_EHIP, "injected launch failure (launch %lld, GBS_FAULT_INJECT)", (long long)k);
+  return GBS_OK;
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -257,7 +300,7 @@ void order_items(Plan& pl, ItemLists& L) {
 }
 
 struct Layout {
-  size_t counter, modes, pats, items, part_off, nvec, sfact, out_idx, partials, total, staged_bytes;
+  size_t counter, modes, pats, items, part_off, nvec, sfact, out_idx, partials, check, total, staged_bytes;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -285,6 +328,8 @@ Layout layout_for(const Plan& pl, size_t n_modes) {
   L.staged_bytes = off - stage_begin;
   L.partials = off;
   off += al(sizeof(gbs_partial) * (size_t)pl.n_partials);
+  L.check = off;  // per-pattern flags of the debug symmetry check (only when it is on)
+  if (check_symmetry_on()) off += al(sizeof(int32_t) * pl.pats.size());
   L.total = off;
   return L;
 }
@@ -357,6 +402,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
              int32_t m, const double* prefactor_dev, double* prob_out, double2* haf_out, gbs_partial* partial_out,
              hipStream_t stream) {
   DeviceGuard dg(ctx->device);
+  if (const int g = launch_gate(ctx)) return g;
   const Layout L = layout_for(pl, n_modes);
   int rc = ensure_ws(ctx, L.total);
   if (rc) return rc;
@@ -380,6 +426,19 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   HIPCHK(ctx, hipMemcpyAsync(ws + base, h, L.staged_bytes, hipMemcpyHostToDevice, stream));
   HIPCHK(ctx, hipEventRecord(ctx->pinned_ev[pi], stream));
   ctx->pinned_used[pi] = true;
+
+  // debug: caller-provided matrices must be symmetric (checked before anything else runs on them)
+  if (A && !modes_host && check_symmetry_on() && !pl.pats.empty()) {
+    int32_t* flags = reinterpret_cast<int32_t*>(ws + L.check);
+    launch_sym_check(A, reinterpret_cast<const PatternDesc*>(ws + L.pats), (int64_t)pl.pats.size(), 1e-12, flags,
+                     stream);
+    std::vector<int32_t> hf(pl.pats.size());
+    HIPCHK(ctx, hipMemcpyAsync(hf.data(), flags, sizeof(int32_t) * hf.size(), hipMemcpyDeviceToHost, stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    for (size_t b = 0; b < hf.size(); ++b)
+      if (hf[b])
+        return fail(ctx, GBS_EINVAL, "matrix %zu is not symmetric (|A_ij - A_ji| > 1e-12 max|A|; GBS_CHECK_SYMMETRY)", b);
+  }
 
   // one persistent launch per engine variant, each with its own item list and work counter
   EngineArgs ea{};
@@ -608,6 +667,17 @@ int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent) {
   return GBS_OK;
 }
 
+int gbs_debug_fault_inject(int64_t launch_n) {
+  g_fault_at.store(launch_n > 0 ? launch_n : 0, std::memory_order_release);
+  g_launches.store(0, std::memory_order_release);
+  return GBS_OK;
+}
+
+int gbs_debug_check_symmetry(int32_t on) {
+  g_check_sym.store(on ? 1 : 0, std::memory_order_release);
+  return GBS_OK;
+}
+
 int gbs_ctx_set_precision(gbs_ctx* ctx, int32_t precision) {
   if (!ctx) return GBS_EINVAL;
   ctx->last_error.clear();
@@ -752,6 +822,7 @@ int haf_batch_noalloc(gbs_ctx* ctx, const gbs_c128* A_dev, int32_t n, int64_t ba
   if (!haf_out_dev || (n > 0 && !A_dev)) return fail(ctx, GBS_EINVAL, "null pointer");
   if (batch > (int64_t)1 << 30) return fail(ctx, GBS_ERANGE, "batch too large");
   DeviceGuard dg(ctx->device);
+  if (const int g = launch_gate(ctx)) return g;
   hipError_t se = hipSuccess;
   unsigned char* scr = static_cast<unsigned char*>(noalloc_scratch(ctx->device, &se));
   if (!scr) return fail(ctx, GBS_EHIP, "scratch address: %s", hipGetErrorString(se));
@@ -1039,6 +1110,7 @@ int gbs_finalize(gbs_ctx* ctx, const gbs_state* st, const gbs_partial* partials_
   std::copy(part_lo_host, part_lo_host + batch, pl.part_off.begin());
   std::copy(part_hi_host, part_hi_host + batch, pl.part_off.begin() + batch);
   DeviceGuard dg(ctx->device);
+  if (const int g = launch_gate(ctx)) return g;
   const Layout L = layout_for(pl, 0);
   int rc = ensure_ws(ctx, L.total);
   if (rc) return rc;
@@ -1151,6 +1223,7 @@ int gbs_prob_sweep(gbs_ctx* ctx, const gbs_state* st, int32_t n, int32_t collisi
     tab_max = std::max(tab_max, level_count[l]);
   }
   DeviceGuard dg(ctx->device);
+  if (const int g = launch_gate(ctx)) return g;
   size_t off = 0;
   const size_t o_binom = off;
   off += al(sizeof(uint64_t) * binom.size());
@@ -1199,6 +1272,7 @@ int gbs_sweep_sample(gbs_ctx* ctx, const double* prob_dev, int64_t count, const 
   if (!prob_dev || (nsamples > 0 && (!uniforms_dev || !index_out_dev))) return fail(ctx, GBS_EINVAL, "null pointer");
   if (count > kSweepMaxCount) return fail(ctx, GBS_ERANGE, "count too large");
   DeviceGuard dg(ctx->device);
+  if (const int g = launch_gate(ctx)) return g;
   const int64_t nb = cdf_blocks(count);
   size_t off = 0;
   const size_t o_cdf = off;
@@ -1404,6 +1478,7 @@ int marginal_common(gbs_ctx* ctx, const gbs_state* st, int32_t n, const int32_t*
 
   // device layout in the workspace: staged tables, then the hafnian tables, class values, extra
   DeviceGuard dg(ctx->device);
+  if (const int g = launch_gate(ctx)) return g;
   size_t off = 0;
   const size_t o_stage = off;
   const size_t o_x = off;

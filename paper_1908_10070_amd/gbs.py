@@ -26,7 +26,8 @@ GBS_SHAPE_TILE_9_10, GBS_SHAPE_TILE_11_12 = 1, 2
 # Every function declared in include/gbs.h.
 EXPORTS = [
     "gbs_ctx_create", "gbs_ctx_destroy", "gbs_ctx_set_workspace", "gbs_ctx_workspace_needed", "gbs_status_str",
-    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_precision", "gbs_ctx_get_precision", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_ctx_set_shape", "gbs_ctx_get_shape", "gbs_haf_flops",
+    "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_precision", "gbs_ctx_get_precision", "gbs_debug_fault_inject",
+    "gbs_debug_check_symmetry", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_ctx_set_shape", "gbs_ctx_get_shape", "gbs_haf_flops",
     "haf_batch", "haf_batch_varlen", "haf_batch_noalloc", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
     "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
     "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step", "gbs_sweep_count",
@@ -34,6 +35,16 @@ EXPORTS = [
 ]
 
 _lib = None
+
+
+def debug_fault_inject(launch_n: int) -> None:
+    """The launch_n-th compute call from now on fails with GBS_EHIP (enqueueing nothing); <= 0: off."""
+    lib().gbs_debug_fault_inject(int(launch_n))
+
+
+def debug_check_symmetry(on: bool) -> None:
+    """Check caller-provided matrices for symmetry before the hafnian path (GBS_EINVAL if not)."""
+    lib().gbs_debug_check_symmetry(1 if on else 0)
 
 
 class GBSError(RuntimeError):
@@ -66,6 +77,8 @@ def lib() -> ctypes.CDLL:
         "gbs_last_error": (ctypes.c_char_p, [vp]),
         "gbs_ctx_set_exec": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "gbs_ctx_set_precision": (ctypes.c_int, [vp, i32]),
+        "gbs_debug_fault_inject": (ctypes.c_int, [i64]),
+        "gbs_debug_check_symmetry": (ctypes.c_int, [i32]),
         "gbs_ctx_get_precision": (i32, [vp]),
         "gbs_ctx_set_tuning": (ctypes.c_int, [vp, i32, i64, i64]),
         "gbs_ctx_get_tuning": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),

@@ -125,6 +125,7 @@ class GpuBackend(SliceBackend):
             streams.append(torch.cuda.Stream(device=ctx.torch_device))
             ctxs.append(gbs.Context(ctx.device, use_graph=False))
             ctxs[-1]._copy_tuning_from(ctx)
+            ctxs[-1].set_precision(ctx.precision)
         self.lanes = list(zip(ctxs, streams))
         self._lane = 0
         self._prev_slices = None  # event after the previous step's slices

@@ -9,8 +9,9 @@ and kappa2 = sqrt(sum_Z |term(Z)|^2) / |Haf|.
 Only oracle/ and the seeded input generators are used. Existing records are kept and completed; the
 file is rewritten as each record finishes.
 
-Usage: python tests/golden/make_config5_golden.py [--jobs 2]
-Runs for hours (n = 44 is ~2^22 subsets with plain repeated multiplication).
+Usage: python tests/golden/make_config5_golden.py [--jobs 2] [--all]
+Runs for hours (n = 44 is ~2^22 subsets with plain repeated multiplication). --all extends the set
+to all 64 patterns (the n = 40 and n = 44 ones in double).
 """
 import argparse
 import json
@@ -70,11 +71,13 @@ def write(recs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=2)
+    ap.add_argument("--all", action="store_true", help="all 64 patterns")
     args = ap.parse_args()
+    indices = list(range(64)) if args.all else INDICES
     recs = {}
     if OUT.exists():
         recs = {r["index"]: r for r in json.loads(OUT.read_text())["records"]}
-    todo = [(i, recs.get(i)) for i in INDICES if i not in recs or "kappa2" not in recs[i]]
+    todo = [(i, recs.get(i)) for i in indices if i not in recs or "kappa2" not in recs[i]]
     todo.sort(key=lambda j: -(36, 40, 44)[j[0] % 3])  # longest first
     with mp.get_context("fork").Pool(args.jobs) as pool:
         for rec in pool.imap_unordered(one, todo, chunksize=1):
