@@ -36,15 +36,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(chunk_small, chunk_large, shape):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when the
-    summary is missing or was taken on other kernel sources."""
+    summary is missing or was taken on other kernel sources or another launch shape."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if (t.get("chunk_small"), t.get("chunk_large"), t.get("engine_shape")) != (chunk_small, chunk_large, shape):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -269,14 +271,15 @@ def extras(gbs, torch, dev, args):
         be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16, lanes=1)
         be.warmup(range(8, 33, 2))
         cont = serve.Server(be, pool_entries=1 << 16, step_flops=args.step_flops, max_slice=4096,
-                            hold_gc=True).start()
+                            hold_gc=True, adaptive=not args.serve_fixed_budget).start()
         serve.replay(cont, arr, pats)
         cont.stop(timeout=600)
         lat_c = np.array(cont.latencies_by_rid(warm)) * 1e3
         res = {"arrival_rate_req_s": rate, "requests": nreq, "warmup_requests": warm,
                "continuous": {"p50_ms": float(np.percentile(lat_c, 50)), "p99_ms": float(np.percentile(lat_c, 99)),
                               "mean_ms": float(lat_c.mean()), "throughput_req_s": cont.completion_rate(warm),
-                              "steps": cont.steps}}
+                              "steps": cont.steps,
+                              "host_ms_per_step": {k: v for k, v in cont.stats().items() if k.startswith("host_")}}}
         if not args.no_fifo:
             pp = gbs.Context(0, use_graph=False, persistent=False)
             for n in range(8, 33, 2):  # load every kernel the stream uses
@@ -316,11 +319,53 @@ def extras(gbs, torch, dev, args):
     return out
 
 
+def run_config3(args):
+    """--workload config3: only the config-3 probability batch (m = 50, r = 0.88, 100,000 twenty-photon
+    patterns, one gbs_prob_batch call per step), timed like the headline; for profiling that path."""
+    import torch
+    from paper_1908_10070_amd import gbs, inputs
+    dev = torch.device("cuda", 0)
+    ctx = gbs.Context(0)
+    st_in, pats = inputs.config3()
+    st = ctx.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
+    from paper_1908_10070_amd.gbs import pack_patterns
+    packed = pack_patterns(pats)
+    prob = torch.empty(len(pats), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        ctx.prob_batch(st, packed, prob_out=prob)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.prob_batch(st, packed, prob_out=prob)
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = [a.elapsed_time(b) for a, b in evs]
+    kern_ms = float(np.mean(gpu_ms))
+    flops = gbs.haf_flops(20) * len(pats)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "config3 probabilities/s", "value": len(pats) / (wall / args.steps), "unit": "probabilities/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
+        "config": {"workload": "config3: m = 50, r = 0.88, 100,000 collision-free 20-photon patterns (seeds 1003/2003), "
+                               "gbs_prob_batch", "chunk_small": ctx.get_tuning(20)[0],
+                   "chunk_large": ctx.get_tuning(20)[1], "engine_shape": ctx.get_shape(20)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                     "kernel_ms": kern_ms, "kernel_ms_min": float(np.min(gpu_ms))}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-pattern", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the probability and serving measurements")
@@ -328,19 +373,28 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8],
                     help="arrival rates as fractions of the measured batched capacity")
-    ap.add_argument("--step-flops", type=float, default=8e11, help="modelled work per server step")
+    ap.add_argument("--step-flops", type=float, default=1.6e12, help="modelled work per server step")
     ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO per-pattern server")
+    ap.add_argument("--serve-fixed-budget", action="store_true",
+                    help="server steps of --step-flops only (no growth with the backlog)")
     ap.add_argument("--no-config5", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="use the built-in chunk sizes")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner here instead of using the built-in table (which is its output)")
+    ap.add_argument("--no-tune", action="store_true", help="the built-in launch-shape table (the default)")
     ap.add_argument("--chunks", type=str, default="",
                     help="fixed chunk sizes 'small,large' instead of tuning (profiling runs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM traffic counters)")
+    ap.add_argument("--workload", choices=("config2", "config3"), default="config2",
+                    help="config3: time only the config-3 probability batch (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "config3":
+        run_config3(args)
+        return
 
     from paper_1908_10070_amd import inputs
 
@@ -364,18 +418,18 @@ def main():
         del src, dst
     ctx = gbs.Context(0, use_graph=True, persistent=True)
     stream = torch.cuda.current_stream()
-    # autotuned chunk sizes for this workload (measured here, not read from a cache)
+    # launch shape: the built-in table (the autotuner's output for every n), or tuned here with --tune
     from paper_1908_10070_amd import autotune
     tune_log = []
     if args.chunks:
         cs, cl = (int(v) for v in args.chunks.split(","))
         ctx.set_tuning(n, cs, cl)
         chunks = ctx.get_tuning(n)
-    elif args.no_tune:
-        chunks = ctx.get_tuning(n)
-    else:
+    elif args.tune:
         chunks = autotune.tune(ctx, n, A, reps=1, small=(256, 512, 1024, 2048), large=(64, 128, 256, 512),
                                cache=None, log=tune_log)
+    else:
+        chunks = ctx.get_tuning(n)
     shape = ctx.get_shape(n)
 
     for _ in range(args.warmup):
@@ -421,13 +475,14 @@ def main():
         "config": {"workload": "config2: 4096 random complex-symmetric 24x24 matrices (seed 1002), haf_batch, "
                                "persistent launch replayed from a HIP graph", "n": n, "batch": batch,
                    "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1]), "engine_shape": int(shape),
-                   "launch_shape_from": "chunks given" if args.chunks else ("built-in table" if args.no_tune
-                                                                             else "autotuned here")},
+                   "launch_shape_from": "chunks given" if args.chunks else ("autotuned here" if args.tune else
+                                                                             "built-in table (autotuner output)")},
         "max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),
         "err_sample": f"timed run's output of the first {len(cpu_vals)} matrices vs the oracle's haf_pt (FP64 power "
                       f"trace); the stated tolerance is 1e-9",
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(int(chunks[0]), int(chunks[1]),
+                                                                                       int(shape)),
                      "flops_per_launch": flops_per_haf * batch, "kernel_ms": kern_ms,
                      "kernel_ms_median": float(np.median(gpu_ms)), "kernel_ms_min": float(np.min(gpu_ms)),
                      "kernel_ms_max": float(np.max(gpu_ms)),

@@ -203,7 +203,7 @@ class Server:
 
     def __init__(self, backend: SliceBackend, pool_entries: int, max_active: int = 8192,
                  step_flops: float = 1e11, share: float = 0.5, inflight: int = 3, max_slice: int = 4096,
-                 max_finish: int = 4096, hold_gc: bool = False):
+                 max_finish: int = 4096, hold_gc: bool = False, adaptive: bool = True):
         """hold_gc: while the server runs, freeze the objects alive at start() and switch off Python's
         cyclic garbage collector (switched back on at stop()). Its full collections pause every
         thread for tens of milliseconds once tens of thousands of requests and futures are alive,
@@ -215,6 +215,9 @@ class Server:
         self.pool_entries = pool_entries
         self.max_active = max_active
         self.step_flops = step_flops
+        # adaptive: a step takes at least its share of the backlog (the active requests' remaining work
+        # over the steps in flight), so steps grow with the load and the device's efficiency with them
+        self.adaptive = adaptive
         self.share = share
         self.inflight = inflight
         self.max_slice = max_slice
@@ -364,7 +367,9 @@ class Server:
         requests keep moving under load."""
         jobs, finished = [], []
         budget = self.step_flops
-        cap = self.step_flops * self.share
+        if self.adaptive:
+            budget = max(budget, sum(r.remaining for r in self._active) / self.inflight)
+        cap = budget * self.share
         order = sorted(self._active, key=lambda r: (r.remaining, r.rid))
         oldest = min(self._active, key=lambda r: r.rid)
         if order and order[0] is not oldest:

@@ -94,7 +94,7 @@ def test_server_fails_only_the_failed_step(env):
     pats = [inputs.collision_free_patterns(50, int(n), 1, rng)[0] for n in rng.choice([8, 12, 16, 20], size=40)]
     alone = ctx.prob_batch(st, pats).cpu().numpy()
     be = serve.GpuBackend(ctx, st, pool_entries=4096)
-    srv = serve.Server(be, pool_entries=4096, step_flops=5e7, max_slice=1024, inflight=1)
+    srv = serve.Server(be, pool_entries=4096, step_flops=5e7, max_slice=1024, inflight=1, adaptive=False)
     futs = [srv.submit(p) for p in pats]
     try:
         gbs.debug_fault_inject(3)

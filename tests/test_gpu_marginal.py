@@ -57,6 +57,38 @@ def test_collision_free_and_colliding_k10_k12_vs_oracle(env):
         assert abs(g - ref) <= TOL * ref, (p, g, ref)
 
 
+def test_term_by_term_theorem1(env):
+    """Against Theorem 1 evaluated term by term (oracle marginal_thm1: every (mu, A, B, a, e) term as
+    the theorem writes it, not the regrouped form the device uses), k = 1..12 with and without
+    repeated modes."""
+    ctx, states = env
+    rng = np.random.default_rng(94)
+    cases = []
+    for m, n, ks in [(5, 8, (1, 3, 5, 7)), (8, 12, (2, 4, 6, 8, 10)), (16, 14, (9, 11, 12)), (8, 14, (12,))]:
+        for k in ks:
+            cases.append((m, n, [int(v) for v in rng.integers(0, m, size=k)]))
+    cases.append((16, 12, [0, 2, 4, 6, 8, 10, 12, 14, 1, 3]))  # collision-free
+    cases.append((8, 10, [5, 5, 5, 5, 1, 1, 7, 7]))          # heavy collisions
+    for m, n, p in cases:
+        st, W = states[m]
+        g = run(ctx, st, n, [p])[0]
+        ref = M.marginal_thm1(W, p, n)
+        assert abs(g - ref) <= TOL * ref, (m, n, p, g, ref)
+
+
+def test_brute_force_large_k(env):
+    """k = 14..18 against the brute-force marginal (q_n summed over every completion, Eq. EqDisE), with
+    n = k + 2 (m^2 completions) and n = k + 4 at m = 5."""
+    ctx, states = env
+    rng = np.random.default_rng(95)
+    for m, k, n in [(8, 14, 16), (8, 16, 18), (8, 18, 20), (5, 14, 18)]:
+        st, W = states[m]
+        p = [int(v) for v in rng.integers(0, m, size=k)]
+        g = run(ctx, st, n, [p])[0]
+        b = M.marginal_brute(W, p, n)
+        assert abs(g - b) <= TOL * b, (m, k, n, g, b)
+
+
 def test_closed_forms(env):
     ctx, states = env
     for m in (5, 16, 36):

@@ -75,7 +75,7 @@ def test_all_requests_complete_with_oracle_values(setup):
     U, r, rng = setup
     pats = [sorted(rng.choice(8, n, replace=False).tolist()) for n in (0, 2, 4, 6, 8, 4, 2, 8)] + [[1, 1, 3, 3]]
     be = FakeBackend(U, r)
-    srv = serve.Server(be, pool_entries=64, max_slice=2, step_flops=50.0)
+    srv = serve.Server(be, pool_entries=64, max_slice=2, step_flops=50.0, adaptive=False)
     got = run_requests(srv, pats)
     for p, v in zip(pats, got):
         assert v == pytest.approx(oracle.prob_ref(U, r, p), rel=1e-13)
@@ -111,7 +111,7 @@ def test_short_requests_are_not_stuck_behind_long_ones(setup):
     shorts = [[0, 1], [2, 3], [4, 5]]
     be = FakeBackend(U, r)
     # small step budget: the long request advances a slice or two per step, the shorts finish early
-    srv = serve.Server(be, pool_entries=64, max_slice=1, step_flops=300.0, share=0.5)
+    srv = serve.Server(be, pool_entries=64, max_slice=1, step_flops=300.0, share=0.5, adaptive=False)
     futs = [srv.submit(long)] + [srv.submit(p) for p in shorts]
     srv.start()
     for f in futs:
@@ -124,7 +124,8 @@ def test_injected_launch_failure_fails_only_its_requests(setup):
     U, r, rng = setup
     pats = [[0, 1], [2, 3], [4, 5], [6, 7], [0, 2]]
     be = FakeBackend(U, r, fail_on_launch=2)
-    srv = serve.Server(be, pool_entries=64, max_slice=4096, step_flops=1.0, share=0.01, inflight=1)
+    srv = serve.Server(be, pool_entries=64, max_slice=4096, step_flops=1.0, share=0.01, inflight=1,
+                       adaptive=False)
     futs = [srv.submit(p) for p in pats]
     srv.start()
     outcomes = []
@@ -159,3 +160,19 @@ def test_oldest_request_draws_from_the_budget_after_its_free_slice(setup):
     srv._admit()
     jobs, finished = srv._build_step()
     assert len(jobs) == 16 and len(finished) == 2
+
+
+def test_adaptive_budget_grows_with_backlog(setup):
+    """With the adaptive budget a step takes at least the backlog over the steps in flight: a queue of
+    40 one-slice requests at a tiny fixed budget goes in a few steps instead of two requests per step."""
+    U, r, rng = setup
+    pats = [sorted(rng.choice(8, 4, replace=False).tolist()) for _ in range(40)]
+    steps = {}
+    for adaptive in (False, True):
+        be = FakeBackend(U, r)
+        srv = serve.Server(be, pool_entries=256, max_slice=4096, step_flops=1.0, share=1.0, inflight=2,
+                           adaptive=adaptive)
+        out = run_requests(srv, pats)
+        assert np.allclose(out, [oracle.prob_ref(U, r, p) for p in pats], rtol=1e-12)
+        steps[adaptive] = srv.stats()["steps"]
+    assert steps[False] >= 20 and steps[True] <= 8, steps  # fixed: one request plus the oldest per step

@@ -61,8 +61,9 @@ def test_noalloc_edge_sizes_and_limit(torch_dev):
         assert call_noalloc(ctx, A_dev, out) == gbs.GBS_OK
         torch.cuda.synchronize()
         assert np.all(out.cpu().numpy() == want), n
-    # a plan beyond the scratch (n = 46 at the built-in chunks needs far more than 32 MiB): rejected,
-    # nothing enqueued, the output untouched
+    # a plan beyond the scratch (n = 46 cut into items of 8 subsets: about 1M items and partials,
+    # ~60 MB against 32 MiB): rejected, nothing enqueued, the output untouched
+    ctx.set_tuning(46, 8, 8)
     A_dev = torch.zeros((1, 46, 46), dtype=torch.complex128, device=torch_dev)
     out = torch.full((1,), complex(7.0, -7.0), dtype=torch.complex128, device=torch_dev)
     assert call_noalloc(ctx, A_dev, out) == gbs.GBS_ENOMEM
