@@ -2,10 +2,11 @@
 //
 // Same method as the FP64 engines -- for every pair subset Z the traces t_j = tr(M_Z^j), j <= k,
 // then c_0 = 1, q c_q = sum_j (t_j / 2) c_{q-j} and the signed term (-1)^(k-|Z|) c_k summed over Z
-// (Sec. III) -- but every value is carried as a double-double, an unevaluated sum hi + lo of two
-// doubles (~106 significant bits). A term's rounding error is then ~u^2 instead of ~u relative to its
-// size, so the cancellation of the subset sum (sum |term| / |Haf| ~ 1e7..1e12 at n = 36..46) no
-// longer limits the result; the pattern matrix itself, given in FP64, is exact input.
+// (the hafnian algorithm cited in Sec. II C) -- but every value is carried as a double-double, an
+// unevaluated sum hi + lo of two doubles (~106 significant bits). A term's rounding error is then ~u^2
+// instead of ~u relative to its size, so the cancellation of the subset sum (sum |term| / |Haf| ~
+// 1e7..1e12 at n = 36..46) no longer limits the result; the pattern matrix itself, given in FP64, is
+// exact input.
 // The arithmetic is error-free transformations on the VALU: the FP64 MFMA rounds every product and
 // has no error-free form.
 //
