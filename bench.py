@@ -320,13 +320,15 @@ def extras(gbs, torch, dev, args):
 
 
 def run_config3(args):
-    """--workload config3: only the config-3 probability batch (m = 50, r = 0.88, 100,000 twenty-photon
-    patterns, one gbs_prob_batch call per step), timed like the headline; for profiling that path."""
+    """--workload config3 / config5: only that probability batch (config 3: m = 50, r = 0.88, 100,000
+    twenty-photon patterns; config 5: m = 60, r = 0.88, 64 patterns of n = 36/40/44), one
+    gbs_prob_batch call per step, timed like the headline; for profiling those paths."""
     import torch
     from paper_1908_10070_amd import gbs, inputs
     dev = torch.device("cuda", 0)
     ctx = gbs.Context(0)
-    st_in, pats = inputs.config3()
+    c5 = args.workload == "config5"
+    st_in, pats = inputs.config5() if c5 else inputs.config3()
     st = ctx.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
     from paper_1908_10070_amd.gbs import pack_patterns
     packed = pack_patterns(pats)
@@ -347,15 +349,16 @@ def run_config3(args):
     wall = time.perf_counter() - t0
     gpu_ms = [a.elapsed_time(b) for a, b in evs]
     kern_ms = float(np.mean(gpu_ms))
-    flops = gbs.haf_flops(20) * len(pats)
+    flops = sum(gbs.haf_flops(len(p)) for p in pats)
     achieved = flops / (kern_ms * 1e-3) / 1e12
+    name = "config5" if c5 else "config3"
     print(json.dumps({
-        "metric": "config3 probabilities/s", "value": len(pats) / (wall / args.steps), "unit": "probabilities/s",
+        "metric": f"{name} probabilities/s", "value": len(pats) / (wall / args.steps), "unit": "probabilities/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
-        "config": {"workload": "config3: m = 50, r = 0.88, 100,000 collision-free 20-photon patterns (seeds 1003/2003), "
-                               "gbs_prob_batch", "chunk_small": ctx.get_tuning(20)[0],
-                   "chunk_large": ctx.get_tuning(20)[1], "engine_shape": ctx.get_shape(20)},
+        "config": {"workload": ("config5: m = 60, r = 0.88, 64 patterns of n = 36/40/44 (seeds 1005/2005)" if c5 else
+                                "config3: m = 50, r = 0.88, 100,000 collision-free 20-photon patterns (seeds 1003/2003)")
+                               + ", gbs_prob_batch"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "flops_per_launch": flops,
                      "kernel_ms": kern_ms, "kernel_ms_min": float(np.min(gpu_ms))}}))
@@ -386,13 +389,13 @@ def main():
                     help="fixed chunk sizes 'small,large' instead of tuning (profiling runs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM traffic counters)")
-    ap.add_argument("--workload", choices=("config2", "config3"), default="config2",
-                    help="config3: time only the config-3 probability batch (profiling)")
+    ap.add_argument("--workload", choices=("config2", "config3", "config5"), default="config2",
+                    help="config3 / config5: time only that probability batch (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.workload == "config3":
+    if args.workload in ("config3", "config5"):
         run_config3(args)
         return
 

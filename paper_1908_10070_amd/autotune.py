@@ -91,15 +91,14 @@ def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
 
 
 def shapes_for(n: int) -> Tuple[int, ...]:
-    """Engine shapes that differ at photon number n: the |Z| = 9, 10 bit needs k >= 9, the |Z| = 11,
-    12 bit k >= 11."""
+    """Engine shapes that differ at photon number n: for |Z| = 9, 10 the 5x5 quad grid, the 16x16 tile
+    engine (bit 1, k >= 9) or the symmetric quad-tile engine (bit 8, k >= 11); for |Z| = 11, 12 the
+    strip / quad-tile engine, the tile engine (bit 2) or the symmetric quad-tile engine (bit 4), both
+    from k >= 11. Every combination of the two bands."""
     k = n // 2
-    out = [0]
-    if k >= 9:
-        out.append(1)
-    if k >= 11:
-        out += [2, 3]
-    return tuple(out)
+    band910 = [0] + ([1] if k >= 9 else []) + ([8] if k >= 11 else [])
+    band1112 = [0] + ([2, 4] if k >= 11 else [])
+    return tuple(a | b for b in band1112 for a in band910)
 
 
 def save_cache(entries: Dict[tuple, Tuple[int, int]], path: pathlib.Path = DEFAULT_CACHE) -> None:

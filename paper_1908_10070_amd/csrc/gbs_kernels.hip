@@ -9,8 +9,8 @@
 // A call's subsets are cut into work items (ranges of one pattern's canonical subset order: by |Z|,
 // then bitmask). Each item runs on the engine kernel for its subset sizes and k (gbs_eng_*.hip; the
 // class table is in gbs_internal.h) and writes one compensated partial sum; finalize_kernel adds a
-// pattern's partials in item order, so a result depends only on n and the chunk sizes, never on the
-// batch around it. This file also holds the state setup (B, W, prefactor), the Theorem-1 marginal
+// pattern's partials in a fixed order (64 strided lane sums, then a lane tree), so a result depends
+// only on n and the launch shape, never on the batch around it. This file also holds the state setup (B, W, prefactor), the Theorem-1 marginal
 // kernels, the inverse-CDF draw of the sampler and the work-counter reset.
 #include <hip/hip_runtime.h>
 
@@ -26,6 +26,7 @@
 #include "gbs_strip_engine.h"
 #include "gbs_tile_engine.h"
 #include "gbs_dd_engine.h"
+#include "gbs_sqt_engine.h"
 
 namespace gbs {
 
@@ -35,17 +36,25 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 
 // ---------------------------------------------------------------- finalize
 
-__global__ void finalize_kernel(FinalizeArgs a) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < a.batch;
-       b += (int64_t)gridDim.x * blockDim.x) {
+// One wave per pattern: lane l adds partials lo + l, lo + l + 64, ... (Neumaier), then a fixed tree of
+// TwoSum steps over the 64 lanes; the order depends only on the pattern's partial range.
+__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < a.batch; b += (int64_t)gridDim.x * 4) {
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    for (int64_t q = a.part_lo[b]; q < a.part_hi[b]; ++q) {
+    for (int64_t q = a.part_lo[b] + lane; q < a.part_hi[b]; q += 64) {
       const gbs_partial p = a.partials[q];
       neumaier(sr, cr, p.s_re);
       neumaier(si, ci, p.s_im);
       cr += p.c_re;
       ci += p.c_im;
     }
+#pragma unroll
+    for (int w = 1; w < 64; w <<= 1) {
+      tree_add(sr, cr, __shfl_xor(sr, w, 64), __shfl_xor(cr, w, 64));
+      tree_add(si, ci, __shfl_xor(si, w, 64), __shfl_xor(ci, w, 64));
+    }
+    if (lane != 0) continue;
     if (a.partial_out) {
       gbs_partial o;
       o.s_re = sr;
@@ -379,8 +388,8 @@ void launch_reset(int32_t* counter, int n, hipStream_t s) {
 }
 
 void launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-  int64_t blocks = (a.batch + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  int64_t blocks = (a.batch + 3) / 4;  // four patterns (waves) per block
+  if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
@@ -440,6 +449,7 @@ static const EngineVariant* variants() {
     register_strip_engines(tab);
     register_tile_engines(tab);
     register_dd_engines(tab);
+    register_sqt_engines(tab);
     return true;
   }();
   (void)filled;
@@ -460,8 +470,12 @@ static EngineVariant variant(int cls) {
 int engine_class(int s, int k, int shape) {
   if (s <= 6) return kClsQuad + (k - 1);
   if (s <= 8) return kClsGrid4 + (k - 5);
-  if (s <= 10) return (shape & kShapeTile910) ? kClsTile2 + (k - 9) : kClsGrid5 + (k - 9);
+  if (s <= 10) {
+    if ((shape & kShapeSqt910) && k >= 11) return kClsSqt + (k - 11);
+    return (shape & kShapeTile910) ? kClsTile2 + (k - 9) : kClsGrid5 + (k - 9);
+  }
   if (s <= 12) {
+    if (shape & kShapeSqt1112) return kClsSqt + (k - 11);
     if (shape & kShapeTile1112) return kClsTile2 + (k - 9);
     return k <= 16 ? kClsStrip + (k - 11) : kClsQtile + (k - 17);
   }
@@ -478,6 +492,7 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   if (v.kind == kStripKind) return strip_lds_bytes(nmax, kmax, stage_A);
   if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
   if (v.kind == kDdKind) return dd_lds_layout(v.tiles, nmax, kmax).total;
+  if (v.kind == kSqtKind) return sqt_lds_layout(nmax, kmax, stage_A).total;
   return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));
 }
 

@@ -21,7 +21,7 @@ GBS_OK, GBS_EINVAL, GBS_ERANGE, GBS_ENOMEM, GBS_EHIP, GBS_EUNSUPPORTED = range(6
 GBS_N_MAX = 46
 GBS_MARGINAL_KMAX = 20
 GBS_PREC_FP64, GBS_PREC_DD = 0, 1
-GBS_SHAPE_TILE_9_10, GBS_SHAPE_TILE_11_12 = 1, 2
+GBS_SHAPE_TILE_9_10, GBS_SHAPE_TILE_11_12, GBS_SHAPE_SQT_11_12, GBS_SHAPE_SQT_9_10 = 1, 2, 4, 8
 
 # Every function declared in include/gbs.h.
 EXPORTS = [

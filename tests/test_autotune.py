@@ -40,8 +40,8 @@ def test_shapes_for():
     assert autotune.shapes_for(16) == (0,)
     assert autotune.shapes_for(18) == (0, 1)
     assert autotune.shapes_for(20) == (0, 1)
-    assert autotune.shapes_for(22) == (0, 1, 2, 3)
-    assert autotune.shapes_for(46) == (0, 1, 2, 3)
+    assert autotune.shapes_for(22) == (0, 1, 8, 2, 3, 10, 4, 5, 12)
+    assert autotune.shapes_for(46) == (0, 1, 8, 2, 3, 10, 4, 5, 12)
 
 
 def test_load_cache_missing_or_corrupt(tmp_path, monkeypatch):
