@@ -7,10 +7,10 @@ staging of the pattern matrix and the per-wave trace buffers. The best pair depe
 batch size and on the device, so it is measured:
 
 * a coordinate search -- ``chunk_small`` over its candidates with the default ``chunk_large``,
-  then ``chunk_large`` with the best ``chunk_small``, then the engine shape (which engine takes
-  |Z| = 9, 10 and |Z| = 11, 12: the 4x4-tile quad grid and strip / quad-tile engines, or the 16x16
-  tile engine; ``gbs_ctx_set_shape``) over the shapes that change anything at this n -- timing the
-  real call (``haf_batch`` on the caller's matrices) with HIP events, median of a few repetitions;
+  then ``chunk_large`` with the best ``chunk_small``, then the engine of each subset-size band in
+  turn (``gbs_ctx_set_shape``: for |Z| = 9, 10 and 11, 12 the built-in engine, the 16x16-tile engine
+  or the symmetric quad-tile engine, where they apply at this n) -- timing the real call
+  (``haf_batch`` on the caller's matrices) with HIP events, median of a few repetitions;
 * the winner goes to ``gbs_ctx_set_tuning`` / ``gbs_ctx_set_shape`` and to a JSON cache keyed by
   (GPU arch, n), so later contexts load it without measuring (``load_cache``).
 
@@ -77,28 +77,48 @@ def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
     ctx.set_tuning(n, best_s, best_l)
     best_shape = d_shape
     if shapes:
+        timed = {}
+
         def run_shape(sh):
-            ctx.set_shape(n, sh)
-            t = _time_call(lambda: ctx.haf_batch(A, out=out), reps)
-            if log is not None:
-                log.append({"n": n, "chunk_small": best_s, "chunk_large": best_l, "shape": sh, "ms": t})
-            return t
-        best_shape = min(shapes_for(n) if shapes is True else shapes, key=run_shape)
+            if sh not in timed:
+                ctx.set_shape(n, sh)
+                timed[sh] = _time_call(lambda: ctx.haf_batch(A, out=out), reps)
+                if log is not None:
+                    log.append({"n": n, "chunk_small": best_s, "chunk_large": best_l, "shape": sh, "ms": timed[sh]})
+            return timed[sh]
+        if shapes is True:
+            # coordinate search over the bands, starting from the built-in shape
+            for band in shape_bands(n):
+                mask = sum(band)
+                best_shape = min(((best_shape & ~mask) | b for b in band), key=run_shape)
+        else:
+            best_shape = min(shapes, key=run_shape)
     ctx.set_shape(n, best_shape)
     if cache is not None:
         save_cache({(_arch(ctx), n): (best_s, best_l, best_shape)}, cache)
     return best_s, best_l
 
 
-def shapes_for(n: int) -> Tuple[int, ...]:
-    """Engine shapes that differ at photon number n: for |Z| = 9, 10 the 5x5 quad grid, the 16x16 tile
-    engine (bit 1, k >= 9) or the symmetric quad-tile engine (bit 8, k >= 11); for |Z| = 11, 12 the
-    strip / quad-tile engine, the tile engine (bit 2) or the symmetric quad-tile engine (bit 4), both
-    from k >= 11. Every combination of the two bands."""
+def shape_bands(n: int):
+    """Engine choices per subset-size band that differ at photon number n, as lists of shape bits (the
+    first entry is the built-in engine): |Z| = 9, 10: 5x5 quad grid, 16x16 tiles (1, k >= 9),
+    symmetric quad-tile (8, k >= 11); |Z| = 11, 12: strip / quad-tile, 16x16 tiles (2), symmetric
+    quad-tile (4), from k >= 11."""
     k = n // 2
-    band910 = [0] + ([1] if k >= 9 else []) + ([8] if k >= 11 else [])
-    band1112 = [0] + ([2, 4] if k >= 11 else [])
-    return tuple(a | b for b in band1112 for a in band910)
+    bands = []
+    if k >= 9:
+        bands.append([0, 1] + ([8] if k >= 11 else []))
+    if k >= 11:
+        bands.append([0, 2, 4])
+    return bands
+
+
+def shapes_for(n: int) -> Tuple[int, ...]:
+    """Every combination of the per-band choices of shape_bands(n)."""
+    out = [0]
+    for band in shape_bands(n):
+        out = [a | b for b in band for a in out]
+    return tuple(out)
 
 
 def save_cache(entries: Dict[tuple, Tuple[int, int]], path: pathlib.Path = DEFAULT_CACHE) -> None:

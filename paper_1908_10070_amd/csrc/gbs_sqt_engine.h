@@ -1,11 +1,13 @@
-// Symmetric quad-tile subset engine for 16 < d = 2|Z| <= 24 (|Z| = 9..12), gfx950.
+// Symmetric quad-tile subset engine, gfx950: a G x G grid of 4x4 tiles for d = 2|Z| <= 4G; built for
+// G = 6 (|Z| = 9..12). (An 8x8 grid for |Z| = 13..16 ran at one wave per SIMD and lost to the 16x16
+// tile engine, 10% slower at n = 44, so it is not built.)
 //
 // A workgroup of four waves evaluates four subsets at a time, one per block of
 // v_mfma_f64_4x4x4_4b_f64 (block b = (lane >> 2) & 3, as in the quad engine); M_Z and its powers are
-// 6x6 grids of 4x4 tiles in the quad engine's lane layout (lane x + 4b + 16y holds element (y, x) of
+// G x G grids of 4x4 tiles in the quad engine's lane layout (lane x + 4b + 16y holds element (y, x) of
 // the tile for block b). Every power Q satisfies Q[i][c] = Q[c^1][i^1], so tile (J, I) is a lane
-// permutation of tile (I, J) and only the 21 tiles with I <= J are stored and multiplied; they are
-// dealt to the waves in row-major order, 6 / 5 / 5 / 5:
+// permutation of tile (I, J) and only the G(G+1)/2 tiles with I <= J are stored and multiplied; they
+// are dealt to the waves in row-major order (G = 6: 6 / 5 / 5 / 5 tiles):
 //   wave 0: (0,0)..(0,5)   wave 1: (1,1)..(1,5)   wave 2: (2,2)..(2,5), (3,3)   wave 3: (3,4), (3,5), (4,4), (4,5), (5,5)
 // Each wave's code is specialised for its tile set (rows and columns are compile-time constants), so
 // every register index is static.
@@ -26,28 +28,29 @@
 namespace gbs {
 namespace {
 
-constexpr int kSqtG = 6;                          // tiles per matrix side (d <= 24)
-constexpr int kSqtStored = kSqtG * (kSqtG + 1) / 2;  // 21 stored tiles
-constexpr int kSqtQ = 6;                          // most tiles per wave
-
-__host__ __device__ constexpr int sqt_idx(int I, int J) { return I * kSqtG - I * (I - 1) / 2 + (J - I); }
+__host__ __device__ constexpr int sqt_stored(int G) { return G * (G + 1) / 2; }
+__host__ __device__ constexpr int sqt_q(int G) { return (sqt_stored(G) + 3) / 4; }  // most tiles per wave
+__host__ __device__ constexpr int sqt_idx(int G, int I, int J) { return I * G - I * (I - 1) / 2 + (J - I); }
 
 // The tile set of wave W: slot q holds tile (I[q], J[q]); rows / cols list the distinct ones, and slot q
 // uses row ri[q] and column ci[q] of those lists.
+template <int G>
 struct SqtPlan {
   int nq, nr, nc;
-  int I[kSqtQ], J[kSqtQ], ri[kSqtQ], ci[kSqtQ];
-  int rows[kSqtG], cols[kSqtG];
+  int I[sqt_q(G)], J[sqt_q(G)], ri[sqt_q(G)], ci[sqt_q(G)];
+  int rows[G], cols[G];
 };
 
-constexpr SqtPlan make_sqt_plan(int W) {
-  SqtPlan p{};
-  // row-major order of the stored tiles, dealt 6 / 5 / 5 / 5
-  int first = W == 0 ? 0 : 6 + 5 * (W - 1);
-  int count = W == 0 ? 6 : 5;
+template <int G>
+constexpr SqtPlan<G> make_sqt_plan(int W) {
+  SqtPlan<G> p{};
+  // row-major order of the stored tiles, dealt in contiguous runs (the first waves take the remainder)
+  constexpr int S = sqt_stored(G), base = S / 4, extra = S % 4;
+  const int count = base + (W < extra ? 1 : 0);
+  const int first = W * base + (W < extra ? W : extra);
   int t = 0;
-  for (int I = 0; I < kSqtG; ++I)
-    for (int J = I; J < kSqtG; ++J, ++t)
+  for (int I = 0; I < G; ++I)
+    for (int J = I; J < G; ++J, ++t)
       if (t >= first && t < first + count) {
         const int q = p.nq++;
         p.I[q] = I;
@@ -64,14 +67,15 @@ constexpr SqtPlan make_sqt_plan(int W) {
   return p;
 }
 
-template <int W>
+template <int G, int W>
 struct SqtPlanOf {
-  static constexpr SqtPlan p = make_sqt_plan(W);
+  static constexpr SqtPlan<G> p = make_sqt_plan<G>(W);
 };
 
+template <int G>
 struct SqtMat {
-  double r[kSqtQ];
-  double i[kSqtQ];
+  double r[sqt_q(G)];
+  double i[sqt_q(G)];
 };
 
 // Lane byte addresses of the three permutations (inside each block): lane ^ 17, transpose, flipped transpose.
@@ -89,36 +93,37 @@ __device__ __forceinline__ SqtLanes sqt_lanes(int lane) {
 }
 
 // Z = X Y for wave W's tiles; T4 = ceil(max d / 4) over the four subsets (uniform). Z may alias X or Y.
-template <int W, bool SAME>
-__device__ __forceinline__ void sqt_mul(const SqtMat& X, const SqtMat& Y, SqtMat& Z, int T4, int lane,
+template <int G, int W, bool SAME>
+__device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, SqtMat<G>& Z, int T4, int lane,
                                         const SqtLanes& ln, double2* xq) {
-  constexpr SqtPlan P = SqtPlanOf<W>::p;
-  double2* yq = SAME ? xq : xq + kSqtStored * 64;
+  constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
+  constexpr int Q = sqt_q(G);
+  double2* yq = SAME ? xq : xq + sqt_stored(G) * 64;
 #pragma unroll
   for (int q = 0; q < P.nq; ++q)
     if (P.J[q] < T4) {
-      const int t = sqt_idx(P.I[q], P.J[q]);
+      const int t = sqt_idx(G, P.I[q], P.J[q]);
       xq[t * 64 + lane] = make_double2(X.r[q], X.i[q]);
       if (!SAME) yq[t * 64 + lane] = make_double2(Y.r[q], Y.i[q]);
     }
   __syncthreads();
-  double t1[kSqtQ], t2[kSqtQ], t3[kSqtQ];
+  double t1[Q], t2[Q], t3[Q];
 #pragma unroll
-  for (int K = 0; K < kSqtG; ++K) {
+  for (int K = 0; K < G; ++K) {
     if (K < T4) {  // k-tiles beyond d hold zeros
-      double2 b[kSqtG];
-      double bs[kSqtG];
+      double2 b[G];
+      double bs[G];
 #pragma unroll
       for (int c = 0; c < P.nc; ++c) {
         const int J = P.cols[c];
-        b[c] = K <= J ? yq[sqt_idx(K, J) * 64 + lane] : yq[sqt_idx(J, K) * 64 + ln.tf];
+        b[c] = K <= J ? yq[sqt_idx(G, K, J) * 64 + lane] : yq[sqt_idx(G, J, K) * 64 + ln.tf];
         bs[c] = b[c].x + b[c].y;
       }
       // one A operand (a row of the wave's tiles) at a time
 #pragma unroll
       for (int r = 0; r < P.nr; ++r) {
         const int I = P.rows[r];
-        const double2 a = K <= I ? xq[sqt_idx(K, I) * 64 + ln.l17] : xq[sqt_idx(I, K) * 64 + ln.tr];
+        const double2 a = K <= I ? xq[sqt_idx(G, K, I) * 64 + ln.l17] : xq[sqt_idx(G, I, K) * 64 + ln.tr];
         const double as = a.x + a.y;
 #pragma unroll
         for (int q = 0; q < P.nq; ++q) {
@@ -142,9 +147,9 @@ __device__ __forceinline__ void sqt_mul(const SqtMat& X, const SqtMat& Y, SqtMat
 }
 
 // per-lane partial of tr(X) over wave W's diagonal tiles
-template <int W>
-__device__ __forceinline__ double2 sqt_diag(const SqtMat& X, int lane) {
-  constexpr SqtPlan P = SqtPlanOf<W>::p;
+template <int G, int W>
+__device__ __forceinline__ double2 sqt_diag(const SqtMat<G>& X, int lane) {
+  constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   double2 t = make_double2(0.0, 0.0);
   if ((lane & 3) == (lane >> 4)) {
 #pragma unroll
@@ -158,9 +163,9 @@ __device__ __forceinline__ double2 sqt_diag(const SqtMat& X, int lane) {
 }
 
 // per-lane partial of tr(X Y) over wave W's tiles (off-diagonal tiles twice, for their mirrors)
-template <int W>
-__device__ __forceinline__ double2 sqt_pair(const SqtMat& X, const SqtMat& Y) {
-  constexpr SqtPlan P = SqtPlanOf<W>::p;
+template <int G, int W>
+__device__ __forceinline__ double2 sqt_pair(const SqtMat<G>& X, const SqtMat<G>& Y) {
+  constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   double2 d = make_double2(0.0, 0.0), o = make_double2(0.0, 0.0);
 #pragma unroll
   for (int q = 0; q < P.nq; ++q) {
@@ -175,25 +180,27 @@ __device__ __forceinline__ double2 sqt_pair(const SqtMat& X, const SqtMat& Y) {
   return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
-// From this k on, the folded traces are parked in LDS (park[(j - 1) * 64 + lane], one area per wave)
-// until the chain ends instead of holding k registers through every product.
+// For G = 6 from this k on, the folded traces are parked in LDS (park[(j - 1) * 64 + lane], one area
+// per wave) until the chain ends instead of holding k registers through every product, so the kernel
+// keeps two waves per SIMD.
 constexpr int kSqtParkK = 18;
+__host__ __device__ constexpr bool sqt_parks(int G, int k) { return G == 6 && k >= kSqtParkK; }
 
-template <int K, int W, int OI, int NS>
-__device__ __forceinline__ void run_ops_sqt(SqtMat (&S)[NS], double (&w)[K], double* park, int T4, int lane,
+template <int K, int G, int W, int OI, int NS>
+__device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&w)[K], double* park, int T4, int lane,
                                             const SqtLanes& ln, double2* xq) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      sqt_mul<W, op.a == op.b>(S[op.a], S[op.b], S[op.x], T4, lane, ln, xq);
+      sqt_mul<G, W, op.a == op.b>(S[op.a], S[op.b], S[op.x], T4, lane, ln, xq);
     } else {
-      const double2 p = op.type == OP_TDIAG ? sqt_diag<W>(S[op.a], lane) : sqt_pair<W>(S[op.a], S[op.b]);
-      if constexpr (K >= kSqtParkK)
+      const double2 p = op.type == OP_TDIAG ? sqt_diag<G, W>(S[op.a], lane) : sqt_pair<G, W>(S[op.a], S[op.b]);
+      if constexpr (sqt_parks(G, K))
         park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
       else
         w[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops_sqt<K, W, OI + 1, NS>(S, w, park, T4, lane, ln, xq);
+    run_ops_sqt<K, G, W, OI + 1, NS>(S, w, park, T4, lane, ln, xq);
   }
 }
 
@@ -201,15 +208,15 @@ __device__ __forceinline__ void run_ops_sqt(SqtMat (&S)[NS], double (&w)[K], dou
 // block-reduced partial traces in tred[((W * 4 + b) * K + j - 1) * 2 + part].
 // Not inlined: with the four wave-specialised copies in one body the register allocator spills; as
 // separate functions each fits two waves per SIMD.
-template <int K, int W>
+template <int K, int G, int W>
 __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4, int T4, int d_b, bool valid_b,
                                          int lane, double2* xq, double* tred, double* park) {
-  constexpr SqtPlan P = SqtPlanOf<W>::p;
+  constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   constexpr int NS = kChainTable[K].nslots;
   const int b = (lane >> 2) & 3;
   const int x = lane & 3, y = lane >> 4;
   const int32_t* pl = pl4 + b * kMaxK;
-  SqtMat S[NS];
+  SqtMat<G> S[NS];
   const int dv = valid_b ? d_b : 0;  // blocks past the last subset gather zeros
 #pragma unroll
   for (int q = 0; q < P.nq; ++q) {
@@ -225,8 +232,8 @@ __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4,
     S[0].i[q] = vi;
   }
   double wt[K];
-  run_ops_sqt<K, W, 0, NS>(S, wt, park, T4, lane, sqt_lanes(lane), xq);
-  if constexpr (K >= kSqtParkK) {
+  run_ops_sqt<K, G, W, 0, NS>(S, wt, park, T4, lane, sqt_lanes(lane), xq);
+  if constexpr (sqt_parks(G, K)) {
 #pragma unroll
     for (int j = 0; j < K; ++j) wt[j] = park[j * 64 + lane];  // each lane reads only what it wrote
   }
@@ -234,7 +241,7 @@ __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4,
 }
 
 // Subsets [lo, hi) of one pattern on the workgroup, four at a time.
-template <int K>
+template <int K, int G>
 __device__ void sqt_range(const PatternView& Pv, int64_t lo, int64_t hi, int32_t* pl4, double2* xq, double* tred,
                           double* trw, int32_t* sz, double* park0, int tid, double& sr, double& si, double& cr,
                           double& ci) {
@@ -272,10 +279,10 @@ __device__ void sqt_range(const PatternView& Pv, int64_t lo, int64_t hi, int32_t
       const int d_b = 2 * (b == 0 ? s4[0] : (b == 1 ? s4[1] : (b == 2 ? s4[2] : s4[3])));
       double* park = park0 + (size_t)w * K * 64;
       switch (w) {
-        case 0: eval_sqt<K, 0>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
-        case 1: eval_sqt<K, 1>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
-        case 2: eval_sqt<K, 2>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
-        default: eval_sqt<K, 3>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
+        case 0: eval_sqt<K, G, 0>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
+        case 1: eval_sqt<K, G, 1>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
+        case 2: eval_sqt<K, G, 2>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
+        default: eval_sqt<K, G, 3>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
       }
       __syncthreads();
       if (tid < 4 * 2 * K) {
@@ -298,7 +305,7 @@ struct SqtLds {
   size_t A, modes, pl, xq, tred, trw, sz, park, item, total;
 };
 
-__host__ __device__ inline SqtLds sqt_lds_layout(int nmax, int kmax, int stage_A) {
+__host__ __device__ inline SqtLds sqt_lds_layout(int G, int nmax, int kmax, int stage_A) {
   SqtLds L;
   size_t off = 0;
   L.A = off;
@@ -308,26 +315,26 @@ __host__ __device__ inline SqtLds sqt_lds_layout(int nmax, int kmax, int stage_A
   L.pl = off;
   off += wal16(sizeof(int32_t) * 4 * kMaxK);
   L.xq = off;  // the stored tiles of both factors of a product
-  off += wal16(sizeof(double) * 2 * 2 * kSqtStored * 64);
+  off += wal16(sizeof(double) * 2 * 2 * sqt_stored(G) * 64);
   L.tred = off;
   off += wal16(sizeof(double) * 4 * 4 * 2 * kmax);
   L.trw = off;
   off += wal16(sizeof(double) * (kmax + 1) * 2 * kWaveG);
   L.sz = off;
   off += wal16(sizeof(int32_t) * kWaveG);
-  L.park = off;  // parked traces, one area per wave, for k >= kSqtParkK
-  off += kmax >= kSqtParkK ? wal16(sizeof(double) * 4 * kmax * 64) : 0;
+  L.park = off;  // parked traces, one area per wave (G = 6, k >= kSqtParkK)
+  off += sqt_parks(G, kmax) ? wal16(sizeof(double) * 4 * kmax * 64) : 0;
   L.item = off;
   off += 16;
   L.total = off;
   return L;
 }
 
-template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void sqt_engine_kernel(
+template <int K, int G>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(G == 6 ? 2 : 1, 8))) void sqt_engine_kernel(
     EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const SqtLds L = sqt_lds_layout(args.nmax, args.kmax, args.stage_A);
+  const SqtLds L = sqt_lds_layout(G, args.nmax, args.kmax, args.stage_A);
   double2* Alds = reinterpret_cast<double2*>(smem + L.A);
   int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
   int32_t* pl4 = reinterpret_cast<int32_t*>(smem + L.pl);
@@ -371,7 +378,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     P.m = args.m;
     P.ld = n;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    if (k == K) sqt_range<K>(P, item.lo, item.hi, pl4, xq, tred, trw, sz, park, tid, sr, si, cr, ci);
+    if (k == K) sqt_range<K, G>(P, item.lo, item.hi, pl4, xq, tred, trw, sz, park, tid, sr, si, cr, ci);
     if (tid == 0) {
       gbs_partial p;
       p.s_re = sr;

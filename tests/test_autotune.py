@@ -35,13 +35,15 @@ def test_cache_round_trip(tmp_path, monkeypatch):
 
 
 def test_shapes_for():
-    """Only shapes that change the engine choice at n are searched: the |Z| = 9, 10 bit from k = 9,
-    the |Z| = 11, 12 bit from k = 11."""
+    """Only engine choices that apply at n are searched: |Z| = 9, 10 from k = 9 (symmetric quad-tile
+    from k = 11), |Z| = 11, 12 from k = 11."""
+    assert autotune.shape_bands(16) == []
     assert autotune.shapes_for(16) == (0,)
     assert autotune.shapes_for(18) == (0, 1)
-    assert autotune.shapes_for(20) == (0, 1)
-    assert autotune.shapes_for(22) == (0, 1, 8, 2, 3, 10, 4, 5, 12)
-    assert autotune.shapes_for(46) == (0, 1, 8, 2, 3, 10, 4, 5, 12)
+    assert autotune.shape_bands(22) == [[0, 1, 8], [0, 2, 4]]
+    assert sorted(autotune.shapes_for(22)) == [0, 1, 2, 3, 4, 5, 8, 10, 12]
+    assert autotune.shape_bands(46) == [[0, 1, 8], [0, 2, 4]]
+    assert len(autotune.shapes_for(46)) == 9
 
 
 def test_load_cache_missing_or_corrupt(tmp_path, monkeypatch):
@@ -64,7 +66,7 @@ def test_tune_on_device(tmp_path):
     A = torch.from_numpy(A_host).cuda()
     log = []
     cs, cl = autotune.tune(ctx, 18, A, reps=1, small=(64, 256), large=(8, 32), cache=tmp_path / "t.json", log=log)
-    assert (cs, cl) == ctx.get_tuning(18) and len(log) == 6  # 2 + 2 chunk trials, shapes 0 and 1
+    assert (cs, cl) == ctx.get_tuning(18) and len(log) == 6  # 2 + 2 chunk trials, shapes 1 and 0
     assert ctx.get_shape(18) in (0, 1)
     assert json.loads((tmp_path / "t.json").read_text())
     h = ctx.haf_batch(A).cpu().numpy()
