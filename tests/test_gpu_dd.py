@@ -236,3 +236,45 @@ def test_dd_timing_n40(dd_ctx, fp_ctx, torch_dev):
           f"ratio {out['dd'][0] / out['fp64'][0]:.1f}; max |dd - fp64| / |dd| = "
           f"{np.max(np.abs(out['dd'][1] - out['fp64'][1]) / np.abs(out['dd'][1])):.2e}")
     assert out["dd"][0] < 60.0
+
+
+def test_dd_slices_and_served_stream(dd_ctx, torch_dev):
+    """The accuracy mode through the serving path: a pattern's subset range cut into three slices
+    (gbs_prob_slices) and combined (gbs_finalize), and a served stream on a double-double context,
+    agree with gbs_prob_batch in double-double to 1e-15 (only the partial-sum order differs), and with
+    the oracle's matching sum to 1e-12."""
+    import torch
+    from paper_1908_10070_amd import gbs, serve
+    st_in, _ = inputs.config3(count=1)
+    st = dd_ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    rng = np.random.default_rng(4902)
+    pats = [inputs.collision_free_patterns(50, n, 1, rng)[0] for n in (8, 12, 16, 20, 24, 26)]
+    ref = dd_ctx.prob_batch(st, pats).cpu().numpy()
+    B = oracle.state_B(st_in.U, st_in.r)
+    pref = float(np.prod(1.0 / np.cosh(st_in.r)))
+    for p, r in zip(pats[:5], ref[:5]):
+        exact = abs(oracle.haf_enum(oracle.pattern_matrix(B, p))) ** 2 * pref
+        assert abs(r - exact) <= 1e-12 * exact, (len(p), r, exact)
+    # slices: [0, c/3), [c/3, 2c/3), [2c/3, c) of each pattern's subset order
+    rows, lo, hi, owner = [], [], [], []
+    for i, p in enumerate(pats):
+        c = gbs.subset_count(len(p))
+        cuts = [0, c // 3, 2 * c // 3, c]
+        for a, b in zip(cuts, cuts[1:]):
+            rows.append(p)
+            lo.append(a)
+            hi.append(b)
+            owner.append(i)
+    parts = dd_ctx.prob_slices(st, rows, lo, hi)
+    plo = np.arange(len(pats), dtype=np.int64) * 3
+    prob, _ = dd_ctx.finalize(st, parts, plo, plo + 3, pats)
+    prob = prob.cpu().numpy()
+    assert np.max(np.abs(prob - ref) / ref) < 1e-15
+    # a served stream on the double-double context (its lanes inherit the precision)
+    be = serve.GpuBackend(dd_ctx, st, pool_entries=1024)
+    srv = serve.Server(be, pool_entries=1024, step_flops=1e9, max_slice=1024)
+    futs = [srv.submit(p) for p in pats]
+    srv.start()
+    served = np.array([f.result(timeout=120) for f in futs])
+    srv.stop()
+    assert np.max(np.abs(served - ref) / ref) < 1e-15
