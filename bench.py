@@ -257,9 +257,12 @@ def extras(gbs, torch, dev, args):
     nreq, warm = args.serve_requests, args.serve_warmup
     mix_rng = np.random.default_rng(3004)
     mix = [inputs.collision_free_patterns(50, int(2 * mix_rng.integers(4, 17)), 1, mix_rng)[0] for _ in range(2000)]
-    t = _timed(lambda: ctx.prob_batch(st3, mix), reps=2)
+    cap_ctx = gbs.Context(0)
+    cap_ctx.set_streams(args.serve_streams)
+    t = _timed(lambda: cap_ctx.prob_batch(st3, mix), reps=2)
     capacity = len(mix) / t
     srv_out = {"batched_capacity_req_s": capacity,
+               "streams_per_step": args.serve_streams,
                "note": "capacity = 2000 mixed requests in one gbs_prob_batch call; latency = scheduled arrival to "
                        "result on the host; statistics over the requests after the warm-up ones; Python's cyclic "
                        "garbage collector is held off during both servers' streams (serve.hold_gc)"}
@@ -268,7 +271,7 @@ def extras(gbs, torch, dev, args):
         arr, pats = inputs.config4_requests(nreq + warm, rate)
         # every step has a new shape, so the server's context captures no graphs (nothing to replay)
         sctx = gbs.Context(0, use_graph=False)
-        be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16, lanes=1)
+        be = serve.GpuBackend(sctx, st3, pool_entries=1 << 16, lanes=1, streams_per_call=args.serve_streams)
         be.warmup(range(8, 33, 2))
         cont = serve.Server(be, pool_entries=1 << 16, step_flops=args.step_flops, max_slice=4096,
                             hold_gc=True, adaptive=not args.serve_fixed_budget).start()
@@ -378,6 +381,9 @@ def main():
                     help="arrival rates as fractions of the measured batched capacity")
     ap.add_argument("--step-flops", type=float, default=1.6e12, help="modelled work per server step")
     ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO per-pattern server")
+    ap.add_argument("--serve-streams", type=int, default=4,
+                    help="streams a mixed batch's kernels are spread over (gbs_ctx_set_streams), for the batched "
+                         "capacity and each server step")
     ap.add_argument("--serve-fixed-budget", action="store_true",
                     help="server steps of --step-flops only (no growth with the backlog)")
     ap.add_argument("--no-config5", action="store_true")

@@ -99,6 +99,14 @@ const char* gbs_last_error(const gbs_ctx* ctx);
  * Defaults: use_graph = 1, persistent = 1. */
 int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
 
+/* Spread each call's engine kernels (one per kernel variant the call needs) round-robin over nstreams
+ * internal streams, forked from the call's stream after its staging copy and joined back before the
+ * final combine, so that the kernels of a mixed batch (a serving step: many sizes, each a few
+ * patterns) run side by side instead of one after another. With use_graph the fork and join are
+ * captured as graph edges. 1 (default) = every kernel on the call's stream. Results are the same bit
+ * for bit. GBS_EINVAL outside [1, 8]; GBS_EHIP if a stream or event cannot be created. */
+int gbs_ctx_set_streams(gbs_ctx* ctx, int32_t nstreams);
+
 /* Debugging hooks (process-wide, any thread).
  * gbs_debug_fault_inject(N): the N-th library call from now on that would enqueue compute work
  *   (hafnians, probabilities, slices, finalize, marginals, sweeps, draws) returns GBS_EHIP with

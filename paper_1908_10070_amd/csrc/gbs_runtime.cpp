@@ -78,6 +78,13 @@ struct gbs_ctx {
   hipStream_t cap_stream = nullptr;
   int use_graph = 1;
   int persistent = 1;
+  // eager launches only: spread a call's engine kernels over this many streams (forked from and
+  // joined back into the caller's stream), so small per-variant kernels overlap
+  static constexpr int kMaxStreams = 8;
+  int nstreams = 1;
+  hipStream_t aux[kMaxStreams] = {};
+  hipEvent_t aux_ev[kMaxStreams] = {};
+  hipEvent_t fork_ev = nullptr;
   int precision = kPrecFp64;
   std::map<int, std::pair<int64_t, int64_t>> tuning;
   std::map<int, int> shape;  // engine shape bits per n (kShape*)
@@ -468,10 +475,30 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   fa.partial_out = partial_out;
   fa.out_idx = pl.out_idx.empty() ? nullptr : reinterpret_cast<const int64_t*>(ws + L.out_idx);
 
-  auto enqueue = [&](hipStream_t s) {
+  // With several streams the engine kernels go round-robin to the auxiliary streams, forked from s
+  // after the staging copy and the counter reset and joined back before the finalize kernel. Under
+  // graph capture the fork and join become graph edges, so a replay runs the kernels side by side.
+  const int ns = ctx->nstreams > 1 ? (int)std::min<size_t>((size_t)ctx->nstreams, launches.size()) : 1;
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
     if (ctx->persistent && !launches.empty()) launch_reset(counters, (int)launches.size(), s);
-    for (const Launch& ln : launches) launch_engine(ln.cls, ln.a, ln.grid, ln.lds, s);
+    if (ns > 1) {
+      hipError_t e = hipEventRecord(ctx->fork_ev, s);
+      for (int j = 0; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(ctx->aux[j], ctx->fork_ev, 0);
+      if (e != hipSuccess) return e;
+      for (size_t i = 0; i < launches.size(); ++i) {
+        const Launch& ln = launches[i];
+        launch_engine(ln.cls, ln.a, ln.grid, ln.lds, ctx->aux[i % ns]);
+      }
+      for (int j = 0; j < ns && e == hipSuccess; ++j) {
+        e = hipEventRecord(ctx->aux_ev[j], ctx->aux[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->aux_ev[j], 0);
+      }
+      if (e != hipSuccess) return e;
+    } else {
+      for (const Launch& ln : launches) launch_engine(ln.cls, ln.a, ln.grid, ln.lds, s);
+    }
     if (fa.batch > 0) launch_finalize(fa, s);
+    return hipGetLastError();
   };
 
   if (ctx->use_graph) {
@@ -480,7 +507,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
              (int64_t)(intptr_t)ea.modes, m, fa.batch, (int64_t)(intptr_t)prefactor_dev, (int64_t)(intptr_t)prob_out,
              (int64_t)(intptr_t)haf_out, (int64_t)(intptr_t)partial_out, (int64_t)(intptr_t)ctx->ws, (int64_t)L.pats,
              (int64_t)L.items, (int64_t)L.partials, (int64_t)L.part_off, (int64_t)L.nvec, (int64_t)L.sfact,
-             (int64_t)L.out_idx, (int64_t)pl.out_idx.size()};
+             (int64_t)L.out_idx, (int64_t)pl.out_idx.size(), ns};
     for (const Launch& ln : launches) {
       key.v.push_back(ln.cls);
       key.v.push_back(ln.grid);
@@ -498,8 +525,12 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
     if (!exec) {
       hipGraph_t g = nullptr;
       HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-      enqueue(ctx->cap_stream);
-      HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &g));
+      hipError_t ce = enqueue(ctx->cap_stream);
+      hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(ctx, GBS_EHIP, "graph capture: %s", hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
       hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return fail(ctx, GBS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
@@ -511,8 +542,7 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
     }
     HIPCHK(ctx, hipGraphLaunch(exec, stream));
   } else {
-    enqueue(stream);
-    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, enqueue(stream));
   }
   HIPCHK(ctx, hipEventRecord(ctx->done_ev, stream));
   ctx->done_recorded = true;
@@ -641,6 +671,11 @@ int gbs_ctx_destroy(gbs_ctx* c) {
   }
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (int i = 0; i < gbs_ctx::kMaxStreams; ++i) {
+    if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
+    if (c->aux_ev[i]) (void)hipEventDestroy(c->aux_ev[i]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   delete c;
   return GBS_OK;
 }
@@ -689,6 +724,21 @@ int gbs_ctx_set_precision(gbs_ctx* ctx, int32_t precision) {
 
 int32_t gbs_ctx_get_precision(const gbs_ctx* ctx) {
   return (ctx && ctx->precision == kPrecDd) ? GBS_PREC_DD : GBS_PREC_FP64;
+}
+
+int gbs_ctx_set_streams(gbs_ctx* ctx, int32_t nstreams) {
+  if (!ctx) return GBS_EINVAL;
+  ctx->last_error.clear();
+  if (nstreams < 1 || nstreams > gbs_ctx::kMaxStreams)
+    return fail(ctx, GBS_EINVAL, "nstreams = %d outside [1, %d]", nstreams, gbs_ctx::kMaxStreams);
+  DeviceGuard dg(ctx->device);
+  if (!ctx->fork_ev) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  for (int i = 0; i < nstreams; ++i) {
+    if (!ctx->aux[i]) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+    if (!ctx->aux_ev[i]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming));
+  }
+  ctx->nstreams = nstreams;
+  return GBS_OK;
 }
 
 int gbs_ctx_set_tuning(gbs_ctx* ctx, int32_t n, int64_t chunk_small, int64_t chunk_large) {

@@ -150,6 +150,26 @@ def test_batch_composition_is_bitwise_invariant(ctx, torch_dev):
         assert np.array_equal(c2.haf_batch(to_dev(A, torch_dev)).cpu().numpy(), full)
 
 
+def test_multi_stream_launches_are_bitwise_equal(ctx, torch_dev):
+    """Spreading a mixed batch's kernels over several streams changes only their overlap."""
+    from paper_1908_10070_amd import gbs
+    rng = np.random.default_rng(24)
+    m = 40
+    U = inputs.haar_unitary(m, rng)
+    r = np.full(m, 0.88)
+    st = ctx.state(to_dev(U, torch_dev), r)
+    pats = [sorted(rng.choice(m, int(n), replace=False).tolist()) for n in rng.choice(range(4, 31, 2), 60)]
+    ref = ctx.prob_batch(st, pats).cpu().numpy()
+    for ns, graph, persistent in [(4, False, True), (8, False, False), (3, False, True), (4, True, True),
+                                  (8, True, False)]:
+        c2 = gbs.Context(0, use_graph=graph, persistent=persistent)
+        c2.set_streams(ns)
+        for _ in range(3):  # a graph is captured on the first call and replayed after
+            assert np.array_equal(c2.prob_batch(st, pats).cpu().numpy(), ref), (ns, graph)
+    with pytest.raises(gbs.GBSError):
+        c2.set_streams(9)
+
+
 def test_graph_replays(ctx, torch_dev):
     import torch
     rng = np.random.default_rng(22)

@@ -28,9 +28,9 @@ def make_requests(seed, count, sizes):
     return [inputs.collision_free_patterns(50, int(n), 1, rng)[0] for n in ns]
 
 
-def serve_all(ctx, st, pats, **kw):
+def serve_all(ctx, st, pats, streams_per_call=1, **kw):
     from paper_1908_10070_amd import serve
-    be = serve.GpuBackend(ctx, st, pool_entries=4096)
+    be = serve.GpuBackend(ctx, st, pool_entries=4096, streams_per_call=streams_per_call)
     srv = serve.Server(be, pool_entries=4096, **kw)
     futs = [srv.submit(p) for p in pats]
     srv.start()
@@ -68,6 +68,10 @@ def test_served_equals_batched_for_single_slice_patterns(env):
     served, _ = serve_all(ctx, st, pats, step_flops=5e8)
     batched = ctx.prob_batch(st, pats).cpu().numpy()
     assert np.array_equal(served, batched)
+    from paper_1908_10070_amd import gbs
+    c4 = gbs.Context(0, use_graph=False)
+    served4, _ = serve_all(c4, st, pats, streams_per_call=4, step_flops=5e8)
+    assert np.array_equal(served4, batched)
 
 
 def test_fifo_server(env):
