@@ -7,7 +7,8 @@ staging of the pattern matrix and the per-wave trace buffers. The best pair depe
 batch size and on the device, so it is measured:
 
 * a coordinate search -- ``chunk_small`` over its candidates with the default ``chunk_large``,
-  then ``chunk_large`` with the best ``chunk_small``, then the engine of each subset-size band in
+  then ``chunk_large`` with the best ``chunk_small`` (of chunk sizes within 1% of the fastest, the
+  smallest), then the engine of each subset-size band in
   turn (``gbs_ctx_set_shape``: for |Z| = 9, 10 and 11, 12 the built-in engine, the 16x16-tile engine
   or the symmetric quad-tile engine, where they apply at this n) -- timing the real call
   (``haf_batch`` on the caller's matrices) with HIP events, median of a few repetitions;
@@ -29,6 +30,15 @@ DEFAULT_CACHE = pathlib.Path(os.environ.get("GBS_TUNE_CACHE", pathlib.Path.home(
 
 SMALL_CANDIDATES = (128, 256, 512, 1024, 2048, 4096)
 LARGE_CANDIDATES = (8, 16, 32, 64, 128, 256, 512)
+# chunk sizes within this fraction of the fastest count as tied; the smallest of them is taken, since
+# smaller work items spread a call smaller than the tuning batch (a serving step) over more workgroups
+TIE = 0.01
+
+
+def smallest_within(times: Dict[int, float], tol: float = TIE) -> int:
+    """The smallest candidate whose time is within (1 + tol) of the fastest one's."""
+    best = min(times.values())
+    return min(c for c, t in times.items() if t <= best * (1.0 + tol))
 
 
 def _arch(ctx) -> str:
@@ -72,8 +82,8 @@ def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
 
     ctx.set_shape(n, -1)
     d_shape = ctx.get_shape(n)
-    best_s = min(small, key=lambda cs: run(cs, d_large))
-    best_l = min(large, key=lambda cl: run(best_s, cl))
+    best_s = smallest_within({cs: run(cs, d_large) for cs in small})
+    best_l = smallest_within({cl: run(best_s, cl) for cl in large})
     ctx.set_tuning(n, best_s, best_l)
     best_shape = d_shape
     if shapes:

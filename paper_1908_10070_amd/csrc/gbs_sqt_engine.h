@@ -180,27 +180,50 @@ __device__ __forceinline__ double2 sqt_pair(const SqtMat<G>& X, const SqtMat<G>&
   return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
-// For G = 6 from this k on, the folded traces are parked in LDS (park[(j - 1) * 64 + lane], one area
-// per wave) until the chain ends instead of holding k registers through every product, so the kernel
-// keeps two waves per SIMD.
-constexpr int kSqtParkK = 18;
-__host__ __device__ constexpr bool sqt_parks(int G, int k) { return G == 6 && k >= kSqtParkK; }
+// Traces are block-reduced four at a time as the chain forms them: the q-th trace operation of the
+// program goes to slot q % 4 of a four-value buffer, and each full buffer (and the last, partial one)
+// is reduced over the 16 lanes of every block at once and written to tred. Holding the k folded
+// traces until the chain ends would take k registers, or an LDS area of k x 64 doubles per wave that
+// at k >= 18 left room for one workgroup per CU.
+__host__ __device__ constexpr int sqt_trace_ord(const ChainProgram& p, int oi) {
+  int c = 0;
+  for (int i = 0; i < oi; ++i) c += p.ops[i].type != OP_MUL;
+  return c;
+}
+// trace index j of the ord-th trace operation (0 past the last)
+__host__ __device__ constexpr int sqt_trace_at(const ChainProgram& p, int ord) {
+  int c = 0;
+  for (int i = 0; i < p.nops; ++i)
+    if (p.ops[i].type != OP_MUL) {
+      if (c == ord) return p.ops[i].x;
+      ++c;
+    }
+  return 0;
+}
 
 template <int K, int G, int W, int OI, int NS>
-__device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&w)[K], double* park, int T4, int lane,
+__device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&tb)[4], double* tred_b, int T4, int lane,
                                             const SqtLanes& ln, double2* xq) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       sqt_mul<G, W, op.a == op.b>(S[op.a], S[op.b], S[op.x], T4, lane, ln, xq);
     } else {
+      constexpr int ord = sqt_trace_ord(kChainTable[K], OI), slot = ord % 4, first = ord - slot;
       const double2 p = op.type == OP_TDIAG ? sqt_diag<G, W>(S[op.a], lane) : sqt_pair<G, W>(S[op.a], S[op.b]);
-      if constexpr (sqt_parks(G, K))
-        park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
-      else
-        w[op.x - 1] = fold32(p.x, p.y);
+      tb[slot] = fold32(p.x, p.y);
+      if constexpr (slot == 3 || ord == K - 1) {
+#pragma unroll
+        for (int q = slot + 1; q < 4; ++q) tb[q] = 0.0;
+        constexpr int j0 = sqt_trace_at(kChainTable[K], first), j1 = sqt_trace_at(kChainTable[K], first + 1),
+                      j2 = sqt_trace_at(kChainTable[K], first + 2), j3 = sqt_trace_at(kChainTable[K], first + 3);
+        reduce_folded_quad<4>(tb, lane, [&](int q, int part, double v) {
+          const int j = q == 1 ? j0 : (q == 2 ? j1 : (q == 3 ? j2 : j3));
+          if (q - 1 <= slot) tred_b[(j - 1) * 2 + part] = v;
+        });
+      }
     }
-    run_ops_sqt<K, G, W, OI + 1, NS>(S, w, park, T4, lane, ln, xq);
+    run_ops_sqt<K, G, W, OI + 1, NS>(S, tb, tred_b, T4, lane, ln, xq);
   }
 }
 
@@ -210,9 +233,10 @@ __device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&w)[K], 
 // separate functions each fits two waves per SIMD.
 template <int K, int G, int W>
 __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4, int T4, int d_b, bool valid_b,
-                                         int lane, double2* xq, double* tred, double* park) {
+                                         int lane, double2* xq, double* tred) {
   constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   constexpr int NS = kChainTable[K].nslots;
+  static_assert(sqt_trace_ord(kChainTable[K], kChainTable[K].nops) == K, "one operation per trace");
   const int b = (lane >> 2) & 3;
   const int x = lane & 3, y = lane >> 4;
   const int32_t* pl = pl4 + b * kMaxK;
@@ -231,19 +255,14 @@ __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4,
     S[0].r[q] = vr;
     S[0].i[q] = vi;
   }
-  double wt[K];
-  run_ops_sqt<K, G, W, 0, NS>(S, wt, park, T4, lane, sqt_lanes(lane), xq);
-  if constexpr (sqt_parks(G, K)) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) wt[j] = park[j * 64 + lane];  // each lane reads only what it wrote
-  }
-  reduce_folded_quad<K>(wt, lane, [&](int j, int part, double v) { tred[((W * 4 + b) * K + j - 1) * 2 + part] = v; });
+  double tb[4];
+  run_ops_sqt<K, G, W, 0, NS>(S, tb, tred + (W * 4 + b) * K * 2, T4, lane, sqt_lanes(lane), xq);
 }
 
 // Subsets [lo, hi) of one pattern on the workgroup, four at a time.
 template <int K, int G>
 __device__ void sqt_range(const PatternView& Pv, int64_t lo, int64_t hi, int32_t* pl4, double2* xq, double* tred,
-                          double* trw, int32_t* sz, double* park0, int tid, double& sr, double& si, double& cr,
+                          double* trw, int32_t* sz, int tid, double& sr, double& si, double& cr,
                           double& ci) {
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int b = (lane >> 2) & 3;
@@ -277,12 +296,11 @@ __device__ void sqt_range(const PatternView& Pv, int64_t lo, int64_t hi, int32_t
         if (q < nv && s4[q] > smax) smax = s4[q];
       const int T4 = (smax + 1) >> 1;  // ceil(2 smax / 4)
       const int d_b = 2 * (b == 0 ? s4[0] : (b == 1 ? s4[1] : (b == 2 ? s4[2] : s4[3])));
-      double* park = park0 + (size_t)w * K * 64;
       switch (w) {
-        case 0: eval_sqt<K, G, 0>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
-        case 1: eval_sqt<K, G, 1>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
-        case 2: eval_sqt<K, G, 2>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
-        default: eval_sqt<K, G, 3>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred, park); break;
+        case 0: eval_sqt<K, G, 0>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred); break;
+        case 1: eval_sqt<K, G, 1>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred); break;
+        case 2: eval_sqt<K, G, 2>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred); break;
+        default: eval_sqt<K, G, 3>(Pv, pl4, T4, d_b, b < nv, lane, xq, tred); break;
       }
       __syncthreads();
       if (tid < 4 * 2 * K) {
@@ -302,7 +320,7 @@ __device__ void sqt_range(const PatternView& Pv, int64_t lo, int64_t hi, int32_t
 }  // namespace
 
 struct SqtLds {
-  size_t A, modes, pl, xq, tred, trw, sz, park, item, total;
+  size_t A, modes, pl, xq, tred, trw, sz, item, total;
 };
 
 __host__ __device__ inline SqtLds sqt_lds_layout(int G, int nmax, int kmax, int stage_A) {
@@ -322,8 +340,6 @@ __host__ __device__ inline SqtLds sqt_lds_layout(int G, int nmax, int kmax, int 
   off += wal16(sizeof(double) * (kmax + 1) * 2 * kWaveG);
   L.sz = off;
   off += wal16(sizeof(int32_t) * kWaveG);
-  L.park = off;  // parked traces, one area per wave (G = 6, k >= kSqtParkK)
-  off += sqt_parks(G, kmax) ? wal16(sizeof(double) * 4 * kmax * 64) : 0;
   L.item = off;
   off += 16;
   L.total = off;
@@ -342,7 +358,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(G == 6
   double* tred = reinterpret_cast<double*>(smem + L.tred);
   double* trw = reinterpret_cast<double*>(smem + L.trw);
   int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz);
-  double* park = reinterpret_cast<double*>(smem + L.park);
   int32_t* item_sh = reinterpret_cast<int32_t*>(smem + L.item);
   const int tid = threadIdx.x;
 
@@ -378,7 +393,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(G == 6
     P.m = args.m;
     P.ld = n;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    if (k == K) sqt_range<K, G>(P, item.lo, item.hi, pl4, xq, tred, trw, sz, park, tid, sr, si, cr, ci);
+    if (k == K) sqt_range<K, G>(P, item.lo, item.hi, pl4, xq, tred, trw, sz, tid, sr, si, cr, ci);
     if (tid == 0) {
       gbs_partial p;
       p.s_re = sr;

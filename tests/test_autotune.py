@@ -46,6 +46,13 @@ def test_shapes_for():
     assert len(autotune.shapes_for(46)) == 9
 
 
+def test_ties_go_to_the_smaller_chunk():
+    assert autotune.smallest_within({128: 10.05, 256: 10.0, 512: 9.98}) == 128
+    assert autotune.smallest_within({128: 10.5, 256: 10.0, 512: 9.98}) == 256
+    assert autotune.smallest_within({64: 3.0}) == 64
+    assert autotune.smallest_within({8: 2.0, 16: 1.0}, tol=0.0) == 16
+
+
 def test_load_cache_missing_or_corrupt(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "_arch", lambda c: "gfx950")
     assert autotune.load_cache(FakeCtx(), tmp_path / "none.json") == 0
