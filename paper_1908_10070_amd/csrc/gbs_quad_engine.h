@@ -206,6 +206,45 @@ __device__ __forceinline__ void reduce_folded_quad(const double (&w)[K], int lan
   }
 }
 
+// Batched trace reduction for engines whose LDS budget cannot hold a parking area: the q-th trace
+// operation of a chain program goes to slot q % 4 of a four-value buffer, and each full buffer (and
+// the last, partial one) is reduced over the 16 lanes of every block at once (reduce_folded_quad) and
+// handed to store(j, part, value) with its trace index j. The exchanges per trace are those of one
+// reduction at the end; the buffer's registers stay live across the products in between, which is why
+// the one-wave engines above park their traces instead (their occupancy is bound by registers, not LDS).
+__host__ __device__ constexpr int chain_trace_ord(const ChainProgram& p, int oi) {
+  int c = 0;
+  for (int i = 0; i < oi; ++i) c += p.ops[i].type != OP_MUL;
+  return c;
+}
+// trace index j of the ord-th trace operation (0 past the last)
+__host__ __device__ constexpr int chain_trace_at(const ChainProgram& p, int ord) {
+  int c = 0;
+  for (int i = 0; i < p.nops; ++i)
+    if (p.ops[i].type != OP_MUL) {
+      if (c == ord) return p.ops[i].x;
+      ++c;
+    }
+  return 0;
+}
+
+template <int KK, int OI, typename Store>
+__device__ __forceinline__ void push_trace(double (&tb)[4], double v, int lane, Store store) {
+  static_assert(chain_trace_ord(kChainTable[KK], kChainTable[KK].nops) == KK, "one operation per trace");
+  constexpr int ord = chain_trace_ord(kChainTable[KK], OI), slot = ord % 4, first = ord - slot;
+  tb[slot] = v;
+  if constexpr (slot == 3 || ord == KK - 1) {
+#pragma unroll
+    for (int q = slot + 1; q < 4; ++q) tb[q] = 0.0;
+    constexpr int j0 = chain_trace_at(kChainTable[KK], first), j1 = chain_trace_at(kChainTable[KK], first + 1),
+                  j2 = chain_trace_at(kChainTable[KK], first + 2), j3 = chain_trace_at(kChainTable[KK], first + 3);
+    reduce_folded_quad<4>(tb, lane, [&](int q, int part, double x) {
+      const int j = q == 1 ? j0 : (q == 2 ? j1 : (q == 3 ? j2 : j3));
+      if (q - 1 <= slot) store(j, part, x);
+    });
+  }
+}
+
 // Four subsets (one per block) with matrices of at most 4*T4 rows; forms the first KK of the K
 // traces (KK >= 2|Z| for all four, so the combine step extends the rest exactly).
 template <int K, int T4, int KK>

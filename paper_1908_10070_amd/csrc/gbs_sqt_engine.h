@@ -180,27 +180,7 @@ __device__ __forceinline__ double2 sqt_pair(const SqtMat<G>& X, const SqtMat<G>&
   return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
-// Traces are block-reduced four at a time as the chain forms them: the q-th trace operation of the
-// program goes to slot q % 4 of a four-value buffer, and each full buffer (and the last, partial one)
-// is reduced over the 16 lanes of every block at once and written to tred. Holding the k folded
-// traces until the chain ends would take k registers, or an LDS area of k x 64 doubles per wave that
-// at k >= 18 left room for one workgroup per CU.
-__host__ __device__ constexpr int sqt_trace_ord(const ChainProgram& p, int oi) {
-  int c = 0;
-  for (int i = 0; i < oi; ++i) c += p.ops[i].type != OP_MUL;
-  return c;
-}
-// trace index j of the ord-th trace operation (0 past the last)
-__host__ __device__ constexpr int sqt_trace_at(const ChainProgram& p, int ord) {
-  int c = 0;
-  for (int i = 0; i < p.nops; ++i)
-    if (p.ops[i].type != OP_MUL) {
-      if (c == ord) return p.ops[i].x;
-      ++c;
-    }
-  return 0;
-}
-
+// Traces are block-reduced four at a time as the chain forms them (push_trace).
 template <int K, int G, int W, int OI, int NS>
 __device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&tb)[4], double* tred_b, int T4, int lane,
                                             const SqtLanes& ln, double2* xq) {
@@ -209,19 +189,8 @@ __device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&tb)[4],
     if constexpr (op.type == OP_MUL) {
       sqt_mul<G, W, op.a == op.b>(S[op.a], S[op.b], S[op.x], T4, lane, ln, xq);
     } else {
-      constexpr int ord = sqt_trace_ord(kChainTable[K], OI), slot = ord % 4, first = ord - slot;
       const double2 p = op.type == OP_TDIAG ? sqt_diag<G, W>(S[op.a], lane) : sqt_pair<G, W>(S[op.a], S[op.b]);
-      tb[slot] = fold32(p.x, p.y);
-      if constexpr (slot == 3 || ord == K - 1) {
-#pragma unroll
-        for (int q = slot + 1; q < 4; ++q) tb[q] = 0.0;
-        constexpr int j0 = sqt_trace_at(kChainTable[K], first), j1 = sqt_trace_at(kChainTable[K], first + 1),
-                      j2 = sqt_trace_at(kChainTable[K], first + 2), j3 = sqt_trace_at(kChainTable[K], first + 3);
-        reduce_folded_quad<4>(tb, lane, [&](int q, int part, double v) {
-          const int j = q == 1 ? j0 : (q == 2 ? j1 : (q == 3 ? j2 : j3));
-          if (q - 1 <= slot) tred_b[(j - 1) * 2 + part] = v;
-        });
-      }
+      push_trace<K, OI>(tb, fold32(p.x, p.y), lane, [&](int j, int part, double v) { tred_b[(j - 1) * 2 + part] = v; });
     }
     run_ops_sqt<K, G, W, OI + 1, NS>(S, tb, tred_b, T4, lane, ln, xq);
   }
@@ -236,7 +205,6 @@ __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4,
                                          int lane, double2* xq, double* tred) {
   constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   constexpr int NS = kChainTable[K].nslots;
-  static_assert(sqt_trace_ord(kChainTable[K], kChainTable[K].nops) == K, "one operation per trace");
   const int b = (lane >> 2) & 3;
   const int x = lane & 3, y = lane >> 4;
   const int32_t* pl = pl4 + b * kMaxK;
