@@ -150,7 +150,9 @@ int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int6
  *                         (k <= 16) or the quad-tile engine (k >= 17).
  *   GBS_SHAPE_SQT_11_12   |Z| = 11, 12 on the symmetric quad-tile engine (4x4 tiles, only those on and
  *                         above the diagonal, spread over four waves); needs k = n/2 >= 11;
- *   GBS_SHAPE_SQT_9_10    |Z| = 9, 10 on the symmetric quad-tile engine (k >= 11).
+ *   GBS_SHAPE_SQT_9_10    |Z| = 9, 10 on the symmetric quad-tile engine (k >= 11);
+ *   GBS_SHAPE_SQT_13_14   |Z| = 13, 14 on the symmetric quad-tile engine on a 7x7 grid instead of
+ *                         the 16x16-tile engine (k >= 13).
  * The quad-tile bits win over the tile bits of the same band. -1 removes the entry (back to the
  * built-in table). Results differ only at the rounding level. GBS_ERANGE for n outside
  * [0, GBS_N_MAX], GBS_EINVAL for unknown bits. */
@@ -158,6 +160,7 @@ int gbs_ctx_get_tuning(const gbs_ctx* ctx, int32_t n, int64_t* chunk_small, int6
 #define GBS_SHAPE_TILE_11_12 2
 #define GBS_SHAPE_SQT_11_12 4
 #define GBS_SHAPE_SQT_9_10 8
+#define GBS_SHAPE_SQT_13_14 16
 int gbs_ctx_set_shape(gbs_ctx* ctx, int32_t n, int32_t shape);
 int gbs_ctx_get_shape(const gbs_ctx* ctx, int32_t n, int32_t* shape);
 

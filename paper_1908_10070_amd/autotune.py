@@ -8,9 +8,10 @@ batch size and on the device, so it is measured:
 
 * a coordinate search -- ``chunk_small`` over its candidates with the default ``chunk_large``,
   then ``chunk_large`` with the best ``chunk_small`` (of chunk sizes within 1% of the fastest, the
-  smallest), then the engine of each subset-size band in
-  turn (``gbs_ctx_set_shape``: for |Z| = 9, 10 and 11, 12 the built-in engine, the 16x16-tile engine
-  or the symmetric quad-tile engine, where they apply at this n) -- timing the real call
+  smallest), then the engine of each subset-size band (another engine only if more than 1% faster) in
+  turn (``gbs_ctx_set_shape``: for |Z| = 9, 10 and 11, 12 the default engine, the 16x16-tile engine
+  or the symmetric quad-tile engine; for |Z| = 13, 14 the 16x16-tile engine or the 7x7 symmetric
+  quad-tile engine; where they apply at this n) -- timing the real call
   (``haf_batch`` on the caller's matrices) with HIP events, median of a few repetitions;
 * the winner goes to ``gbs_ctx_set_tuning`` / ``gbs_ctx_set_shape`` and to a JSON cache keyed by
   (GPU arch, n), so later contexts load it without measuring (``load_cache``).
@@ -39,6 +40,12 @@ def smallest_within(times: Dict[int, float], tol: float = TIE) -> int:
     """The smallest candidate whose time is within (1 + tol) of the fastest one's."""
     best = min(times.values())
     return min(c for c, t in times.items() if t <= best * (1.0 + tol))
+
+
+def faster_than(current: int, times: Dict[int, float], tol: float = TIE) -> int:
+    """The fastest candidate if it beats `current` by more than tol, else `current`."""
+    best = min(times, key=times.get)
+    return best if times[best] < times[current] * (1.0 - tol) else current
 
 
 def _arch(ctx) -> str:
@@ -97,10 +104,14 @@ def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
                     log.append({"n": n, "chunk_small": best_s, "chunk_large": best_l, "shape": sh, "ms": timed[sh]})
             return timed[sh]
         if shapes is True:
-            # coordinate search over the bands, starting from the built-in shape
+            # coordinate search over the bands, starting from the built-in shape; another engine
+            # replaces the current one only if it is faster by more than TIE (ties keep the table)
             for band in shape_bands(n):
                 mask = sum(band)
-                best_shape = min(((best_shape & ~mask) | b for b in band), key=run_shape)
+                cands = [(best_shape & ~mask) | b for b in band]
+                if best_shape not in cands:
+                    cands.insert(0, best_shape)
+                best_shape = faster_than(best_shape, {c: run_shape(c) for c in cands})
         else:
             best_shape = min(shapes, key=run_shape)
     ctx.set_shape(n, best_shape)
@@ -111,15 +122,18 @@ def tune(ctx, n: int, A, reps: int = 3, small: Iterable[int] = SMALL_CANDIDATES,
 
 def shape_bands(n: int):
     """Engine choices per subset-size band that differ at photon number n, as lists of shape bits (the
-    first entry is the built-in engine): |Z| = 9, 10: 5x5 quad grid, 16x16 tiles (1, k >= 9),
+    first entry is the default engine): |Z| = 9, 10: 5x5 quad grid, 16x16 tiles (1, k >= 9),
     symmetric quad-tile (8, k >= 11); |Z| = 11, 12: strip / quad-tile, 16x16 tiles (2), symmetric
-    quad-tile (4), from k >= 11."""
+    quad-tile (4), from k >= 11; |Z| = 13, 14: 16x16 tiles, symmetric quad-tile on a 7x7 grid (16),
+    from k >= 13."""
     k = n // 2
     bands = []
     if k >= 9:
         bands.append([0, 1] + ([8] if k >= 11 else []))
     if k >= 11:
         bands.append([0, 2, 4])
+    if k >= 13:
+        bands.append([0, 16])
     return bands
 
 

@@ -17,7 +17,7 @@ INCLUDE = ROOT / "include"
 OUT = PKG / "libgbs.so"
 
 # the engine kernels are split over several translation units so that they compile in parallel
-SOURCES = ["gbs_eng_sqt.hip", "gbs_eng_grid5.hip", "gbs_eng_grid4.hip", "gbs_eng_quad.hip", "gbs_eng_tile.hip", "gbs_eng_strip.hip",
+SOURCES = ["gbs_eng_sqt.hip", "gbs_eng_sqt7.hip", "gbs_eng_grid5.hip", "gbs_eng_grid4.hip", "gbs_eng_quad.hip", "gbs_eng_tile.hip", "gbs_eng_strip.hip",
            "gbs_eng_dd.hip", "gbs_kernels.hip", "gbs_noalloc.hip", "gbs_sweep.hip", "gbs_runtime.cpp"]
 HEADERS = ["gbs_internal.h", "gbs_tables.h", "gbs_engine_common.h", "gbs_quad_engine.h", "gbs_tile_engine.h",
            "gbs_qtile_engine.h", "gbs_strip_engine.h", "gbs_dd_engine.h", "gbs_sqt_engine.h", "gbs_chain_table.h"]

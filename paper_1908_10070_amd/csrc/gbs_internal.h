@@ -116,20 +116,22 @@ struct MargArgs {
 //           it), k = 9..23                                             (gbs_eng_tile.hip)
 //   85..91  tile engine, 3x3 16x16 tiles, |Z| >= 17, k = 17..23      (gbs_eng_tile.hip)
 //   92..94  double-double engine (accuracy mode), 2|Z| <= 16, 32, 48; any k (gbs_eng_dd.hip)
-//   95..107 symmetric quad-tile engine, |Z| = 11, 12 (and 9, 10), k = 11..23 (gbs_eng_sqt.hip)
-constexpr int kEngineClasses = 108;
+//   95..107 symmetric quad-tile engine, 6x6 grid, |Z| = 11, 12 (and 9, 10), k = 11..23 (gbs_eng_sqt.hip)
+//   108..118 symmetric quad-tile engine, 7x7 grid, |Z| = 13, 14, k = 13..23 (gbs_eng_sqt7.hip)
+constexpr int kEngineClasses = 119;
 constexpr int kClsQuad = 0, kClsGrid4 = 23, kClsGrid5 = 42, kClsStrip = 57, kClsQtile = 63, kClsTile2 = 70,
-              kClsTile3 = 85, kClsDd = 92, kClsSqt = 95;
+              kClsTile3 = 85, kClsDd = 92, kClsSqt = 95, kClsSqt7 = 108;
 
 // Engine shape bits (per photon number, chosen by the autotuner): which engine takes the middle
 // subset sizes instead of the default (the 5x5 quad grid for |Z| = 9, 10; the strip engine at k <= 16
-// and the quad-tile engine above for |Z| = 11, 12). The symmetric quad-tile bits win over the tile bits
-// and need k >= 11.
+// and the quad-tile engine above for |Z| = 11, 12; the 2x2 16x16-tile engine for |Z| = 13..16). The
+// symmetric quad-tile bits win over the tile bits and need k >= 11.
 constexpr int kShapeTile910 = 1;   // |Z| = 9, 10: 16x16 tile engine (2x2 tiles)
 constexpr int kShapeTile1112 = 2;  // |Z| = 11, 12: 16x16 tile engine
 constexpr int kShapeSqt1112 = 4;   // |Z| = 11, 12: symmetric quad-tile engine
 constexpr int kShapeSqt910 = 8;    // |Z| = 9, 10: symmetric quad-tile engine
-constexpr int kShapeMask = 15;
+constexpr int kShapeSqt1314 = 16;  // |Z| = 13, 14: symmetric quad-tile engine on a 7x7 grid
+constexpr int kShapeMask = 31;
 
 enum EngineKind { kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3, kDdKind = 4, kSqtKind = 5 };
 
@@ -153,6 +155,7 @@ void register_strip_engines(EngineVariant* tab);
 void register_tile_engines(EngineVariant* tab);
 void register_dd_engines(EngineVariant* tab);
 void register_sqt_engines(EngineVariant* tab);
+void register_sqt7_engines(EngineVariant* tab);
 
 // No-allocation hafnian path (haf_batch_noalloc): a uniform-n batch's plan is built on the device in
 // a static scratch array. Per engine launch g, every pattern has count items: item j of pattern p

@@ -450,6 +450,7 @@ static const EngineVariant* variants() {
     register_tile_engines(tab);
     register_dd_engines(tab);
     register_sqt_engines(tab);
+    register_sqt7_engines(tab);
     return true;
   }();
   (void)filled;
@@ -479,7 +480,7 @@ int engine_class(int s, int k, int shape) {
     if (shape & kShapeTile1112) return kClsTile2 + (k - 9);
     return k <= 16 ? kClsStrip + (k - 11) : kClsQtile + (k - 17);
   }
-  if (s <= 16) return kClsTile2 + (k - 9);
+  if (s <= 16) return (shape & kShapeSqt1314) && s <= 14 ? kClsSqt7 + (k - 13) : kClsTile2 + (k - 9);
   return kClsTile3 + (k - 17);
 }
 

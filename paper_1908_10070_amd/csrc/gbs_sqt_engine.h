@@ -1,14 +1,16 @@
 // Symmetric quad-tile subset engine, gfx950: a G x G grid of 4x4 tiles for d = 2|Z| <= 4G; built for
-// G = 6 (|Z| = 9..12). (An 8x8 grid for |Z| = 13..16 ran at one wave per SIMD and lost to the 16x16
-// tile engine, 10% slower at n = 44, so it is not built.)
+// G = 6 (|Z| = 9..12) and G = 7 (|Z| = 13, 14), both at two waves per SIMD. (An 8x8 grid for
+// |Z| = 15, 16 needs more than 256 registers per wave and 74 KB of LDS for the published factors, ran at
+// one wave per SIMD and lost to the 16x16 tile engine, so it is not built.)
 //
 // A workgroup of four waves evaluates four subsets at a time, one per block of
 // v_mfma_f64_4x4x4_4b_f64 (block b = (lane >> 2) & 3, as in the quad engine); M_Z and its powers are
 // G x G grids of 4x4 tiles in the quad engine's lane layout (lane x + 4b + 16y holds element (y, x) of
 // the tile for block b). Every power Q satisfies Q[i][c] = Q[c^1][i^1], so tile (J, I) is a lane
 // permutation of tile (I, J) and only the G(G+1)/2 tiles with I <= J are stored and multiplied; they
-// are dealt to the waves in row-major order (G = 6: 6 / 5 / 5 / 5 tiles):
-//   wave 0: (0,0)..(0,5)   wave 1: (1,1)..(1,5)   wave 2: (2,2)..(2,5), (3,3)   wave 3: (3,4), (3,5), (4,4), (4,5), (5,5)
+// are dealt to the waves in row-major order (G = 6: 6 / 5 / 5 / 5 tiles; G = 7: 7 each):
+//   G = 6: wave 0: (0,0)..(0,5)   wave 1: (1,1)..(1,5)   wave 2: (2,2)..(2,5), (3,3)
+//          wave 3: (3,4), (3,5), (4,4), (4,5), (5,5)
 // Each wave's code is specialised for its tile set (rows and columns are compile-time constants), so
 // every register index is static.
 //
@@ -315,7 +317,7 @@ __host__ __device__ inline SqtLds sqt_lds_layout(int G, int nmax, int kmax, int 
 }
 
 template <int K, int G>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(G == 6 ? 2 : 1, 8))) void sqt_engine_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(G <= 7 ? 2 : 1, 8))) void sqt_engine_kernel(
     EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const SqtLds L = sqt_lds_layout(G, args.nmax, args.kmax, args.stage_A);

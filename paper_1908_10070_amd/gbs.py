@@ -22,6 +22,7 @@ GBS_N_MAX = 46
 GBS_MARGINAL_KMAX = 20
 GBS_PREC_FP64, GBS_PREC_DD = 0, 1
 GBS_SHAPE_TILE_9_10, GBS_SHAPE_TILE_11_12, GBS_SHAPE_SQT_11_12, GBS_SHAPE_SQT_9_10 = 1, 2, 4, 8
+GBS_SHAPE_SQT_13_14 = 16
 
 # Every function declared in include/gbs.h.
 EXPORTS = [

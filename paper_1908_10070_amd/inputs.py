@@ -38,6 +38,14 @@ def random_symmetric(n: int, batch: int, rng: np.random.Generator) -> np.ndarray
     return np.ascontiguousarray((mm + np.swapaxes(mm, 1, 2)) / 2.0)
 
 
+def bipartite(k: int, rng: np.random.Generator):
+    """(W, A): a k x k complex Gaussian W = (a + ib)/sqrt(2) and the 2k x 2k block matrix
+    A = [[0, W], [W^t, 0]] (whose hafnian is the permanent of W)."""
+    W = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2.0)
+    A = np.block([[np.zeros((k, k)), W], [W.T, np.zeros((k, k))]])
+    return W, np.ascontiguousarray(A)
+
+
 def collision_free_patterns(m: int, n: int, count: int, rng: np.random.Generator) -> np.ndarray:
     """count x n int32 array; each row a sorted uniformly random n-subset of range(m)."""
     if n > m:

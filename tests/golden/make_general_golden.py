@@ -10,8 +10,11 @@ input generators are used. The file is rewritten as each record finishes, larges
 
 With --blockdiag it writes blockdiag46_haf.json instead: the n = 46 block-diagonal matrix of two
 config-5 pattern matrices (the exact value is the product of the blocks' matching sums) with its kappa.
+With --bipartite it writes bipartite_haf.json: the bipartite block matrices [[0, W], [W^t, 0]] of
+inputs.bipartite(k, default_rng(300 + k)), k = 17..23 (hafnian = permanent of W), with the same
+oracle precisions and kappa, kappa2.
 
-Usage: python tests/golden/make_general_golden.py [--jobs 6] [--nmax 46] [--blockdiag]
+Usage: python tests/golden/make_general_golden.py [--jobs 6] [--nmax 46] [--blockdiag | --bipartite]
 n = 46 in double takes a few CPU-hours (2^23 subsets with plain repeated multiplication).
 """
 import argparse
@@ -97,14 +100,50 @@ def write_blockdiag():
     print(json.dumps(rec), flush=True)
 
 
+def one_bipartite(k):
+    _, A = inputs.bipartite(k, np.random.default_rng(300 + k))
+    n = 2 * k
+    t0 = time.time()
+    if n <= LD_MAX_N:
+        h, kappa, kappa2 = oracle.haf_pt_ld_kappa(A)
+        prec = "long double"
+    else:
+        h, kappa, kappa2 = oracle.haf_pt_kappa(A)
+        prec = "double"
+    rec = {"k": k, "n": n, "seed": 300 + k, "haf": [h.real, h.imag], "kappa": kappa, "kappa2": kappa2,
+           "oracle": prec, "seconds": time.time() - t0}
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
+def write_bipartite(jobs_n):
+    path = HERE / "bipartite_haf.json"
+    recs = json.loads(path.read_text())["records"] if path.exists() else []
+    have = {r["k"] for r in recs}
+    todo = [k for k in range(23, 16, -1) if k not in have]
+    with mp.get_context("fork").Pool(jobs_n) as pool:
+        for rec in pool.imap_unordered(one_bipartite, todo, chunksize=1):
+            recs.append(rec)
+            out = {"source": "oracle haf_pt_ld_kappa (n <= 40) / haf_pt_kappa (n > 40) on "
+                             "inputs.bipartite(k, default_rng(300 + k))",
+                   "records": sorted(recs, key=lambda r: r["k"])}
+            tmp = path.with_suffix(".tmp")
+            tmp.write_text(json.dumps(out, indent=1) + "\n")
+            os.replace(tmp, path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=min(6, os.cpu_count() or 1))
     ap.add_argument("--nmax", type=int, default=46)
     ap.add_argument("--blockdiag", action="store_true", help="write blockdiag46_haf.json instead")
+    ap.add_argument("--bipartite", action="store_true", help="write bipartite_haf.json instead")
     args = ap.parse_args()
     if args.blockdiag:
         write_blockdiag()
+        return
+    if args.bipartite:
+        write_bipartite(args.jobs)
         return
     recs = []
     if OUT.exists():

@@ -36,14 +36,16 @@ def test_cache_round_trip(tmp_path, monkeypatch):
 
 def test_shapes_for():
     """Only engine choices that apply at n are searched: |Z| = 9, 10 from k = 9 (symmetric quad-tile
-    from k = 11), |Z| = 11, 12 from k = 11."""
+    from k = 11), |Z| = 11, 12 from k = 11, |Z| = 13, 14 from k = 13."""
     assert autotune.shape_bands(16) == []
     assert autotune.shapes_for(16) == (0,)
     assert autotune.shapes_for(18) == (0, 1)
     assert autotune.shape_bands(22) == [[0, 1, 8], [0, 2, 4]]
     assert sorted(autotune.shapes_for(22)) == [0, 1, 2, 3, 4, 5, 8, 10, 12]
-    assert autotune.shape_bands(46) == [[0, 1, 8], [0, 2, 4]]
-    assert len(autotune.shapes_for(46)) == 9
+    assert autotune.shape_bands(24) == [[0, 1, 8], [0, 2, 4]]
+    assert autotune.shape_bands(26) == [[0, 1, 8], [0, 2, 4], [0, 16]]
+    assert autotune.shape_bands(46) == [[0, 1, 8], [0, 2, 4], [0, 16]]
+    assert len(autotune.shapes_for(46)) == 18 and 20 in autotune.shapes_for(46)
 
 
 def test_ties_go_to_the_smaller_chunk():
@@ -51,6 +53,12 @@ def test_ties_go_to_the_smaller_chunk():
     assert autotune.smallest_within({128: 10.5, 256: 10.0, 512: 9.98}) == 256
     assert autotune.smallest_within({64: 3.0}) == 64
     assert autotune.smallest_within({8: 2.0, 16: 1.0}, tol=0.0) == 16
+
+
+def test_engine_changes_only_when_clearly_faster():
+    assert autotune.faster_than(4, {4: 10.0, 20: 9.95, 0: 10.2}) == 4
+    assert autotune.faster_than(4, {4: 10.0, 20: 9.8, 0: 10.2}) == 20
+    assert autotune.faster_than(0, {0: 10.0, 2: 10.5}) == 0
 
 
 def test_load_cache_missing_or_corrupt(tmp_path, monkeypatch):

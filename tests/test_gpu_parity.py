@@ -2,7 +2,9 @@
 
 Tolerance: relative error 1e-9 on hafnians and probabilities (complex128 throughout).
 """
+import json
 import math
+import pathlib
 
 import bounds
 import numpy as np
@@ -227,22 +229,43 @@ def test_invalid_inputs_raise(ctx, torch_dev):
 
 @pytest.mark.parametrize("k", [17, 18, 19, 20, 21, 22, 23])
 def test_bipartite_permanent_large(ctx, torch_dev, k):
-    """n = 34..46 (the 3x3-tile engine): Haf of the bipartite block matrix against Ryser's formula."""
-    rng = np.random.default_rng(300 + k)
-    W = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2)
-    A = np.block([[np.zeros((k, k)), W], [W.T, np.zeros((k, k))]])
+    """n = 34..46: Haf of the bipartite block matrix [[0, W], [W^t, 0]] against the permanent of W by
+    Ryser's formula (an independent closed form) and against the oracle's power trace stored by
+    tests/golden/make_general_golden.py --bipartite. Tolerances: the rounding bound of tests/bounds.py
+    from the stored kappa, kappa2 of the subset sum; against Ryser's double sum, plus its own bound
+    2 k u kappa_R (k - 1 additions per row sum and k - 1 products per term, each within u), with
+    kappa_R of Ryser's alternating sum (worst case sum |term|, root-sum-square counterpart as in
+    tests/bounds.py; the tighter)."""
+    recs = {}
+    path = pathlib.Path(__file__).parent / "golden" / "bipartite_haf.json"
+    if path.exists():
+        recs = {r["k"]: r for r in json.loads(path.read_text())["records"]}
+    if k not in recs:
+        pytest.skip(f"no stored oracle value for k = {k}")
+    g = recs[k]
+    n = 2 * k
+    W, A = inputs.bipartite(k, np.random.default_rng(300 + k))
     h = ctx.haf_batch(to_dev(A[None], torch_dev)).cpu().numpy()[0]
     per = 0j
+    s1 = 0.0
+    s2 = 0.0
     step = 1 << 16
     cols = np.arange(k)
     for s0 in range(1, 1 << k, step):
         masks = np.arange(s0, min(1 << k, s0 + step))
         sel = ((masks[:, None] >> cols[None, :]) & 1).astype(np.float64)
-        rows = sel @ W.T
-        per += np.sum((-1.0) ** sel.sum(axis=1) * np.prod(rows, axis=1))
+        terms = (-1.0) ** sel.sum(axis=1) * np.prod(sel @ W.T, axis=1)
+        per += np.sum(terms)
+        s1 += float(np.sum(np.abs(terms)))
+        s2 += float(np.sum(np.abs(terms) ** 2))
     per *= (-1) ** k
-    print(f"k={k} n={2*k} rel err {relerr(h, per):.3e}")
-    assert relerr(h, per) < 1e-8
+    ryser = 2 * k * bounds.U53 * min(s1, np.sqrt(s2)) / abs(per)
+    b = bounds.bound(n, g["kappa"], g["kappa2"], g["oracle"])
+    ref = complex(*g["haf"])
+    print(f"k={k} n={n} vs Ryser {relerr(h, per):.3e} (bound {b + ryser:.2e}), vs oracle {relerr(h, ref):.3e} "
+          f"(bound {b:.2e})")
+    assert relerr(h, ref) <= b
+    assert relerr(h, per) <= bounds.bound(n, g["kappa"], g["kappa2"]) + ryser
 
 
 def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
@@ -250,8 +273,6 @@ def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
     oracle's power trace stored by tests/golden/make_config5_golden.py (long double where present,
     else double) with each matrix's cancellation kappa = sum_Z |term(Z)| / |Haf| (and kappa2, its
     root-sum-square counterpart). Bound: the rounding bound of tests/bounds.py."""
-    import json
-    import pathlib
     gold = json.loads((pathlib.Path(__file__).parent / "golden" / "config5_haf.json").read_text())["records"]
     gold = [g for g in gold if "kappa" in g]
     if not gold:
@@ -297,8 +318,6 @@ def test_largest_size_block_diagonal(ctx, torch_dev):
     the blocks' matching sums. Block-diagonal input is the worst case for the subset sum's
     cancellation (every term mixing the blocks cancels exactly); its kappa (and kappa2), from the
     oracle's double power trace, are stored with it, and the bound is that of tests/bounds.py."""
-    import json
-    import pathlib
     path = pathlib.Path(__file__).parent / "golden" / "blockdiag46_haf.json"
     if not path.exists():
         pytest.skip("blockdiag46_haf.json not written yet")

@@ -172,10 +172,11 @@ def test_prob_batch_mixed_sizes(ctx, torch_dev):
 
 
 @pytest.mark.parametrize("n,shape", [(24, 1), (24, 2), (24, 3), (30, 3), (38, 1), (38, 2), (22, 4), (24, 8), (24, 12),
-                                     (26, 12), (30, 4), (34, 8), (38, 4), (38, 12), (46, 12)])
+                                     (26, 12), (30, 4), (34, 8), (38, 4), (38, 12), (46, 12), (26, 16), (28, 20),
+                                     (32, 16), (36, 20), (40, 16), (42, 20), (44, 20), (46, 20)])
 def test_engine_shapes(ctx, torch_dev, n, shape):
     """The engine shapes the autotuner can pick (|Z| = 9, 10 and / or 11, 12 on the 16x16-tile engine or
-    the symmetric quad-tile engine) give the oracle's values (n <= 24 against the matching sum; larger n
+    the symmetric quad-tile engine; |Z| = 13, 14 on the 7x7 symmetric quad-tile engine) give the oracle's values (n <= 24 against the matching sum; larger n
     against the stored ones) and agree with the built-in shape up to the order of the partial sums."""
     from paper_1908_10070_amd import gbs
     if n <= 24:
@@ -205,7 +206,7 @@ def test_engine_shapes(ctx, torch_dev, n, shape):
     c.set_shape(n, -1)
     assert c.get_shape(n) == ctx.get_shape(n)  # back to the built-in table
     with pytest.raises(gbs.GBSError):
-        c.set_shape(n, 16)
+        c.set_shape(n, 32)
 
 
 @pytest.mark.parametrize("chunks", [(512, 256), (2048, 16), (128, 8), (4096, 128)])
