@@ -268,6 +268,21 @@ __device__ __forceinline__ void reduce_folded(const double (&w)[K], int lane, St
 }
 
 typedef const __attribute__((address_space(3))) double lds_d;  // LDS-qualified, for direct ds_read
+typedef __attribute__((address_space(3))) double lds_dw;       // the same, writable
+
+// Element e of an LDS array of double2 / double through LDS-qualified pointers: in a function that is
+// not inlined into the kernel the compiler cannot see that a pointer is into LDS and would use flat
+// accesses with 64-bit address arithmetic; these give ds_read / ds_write with 32-bit addresses. The
+// pointer must point into LDS.
+typedef double d2v __attribute__((ext_vector_type(2)));  // 16-byte aligned: ds_read_b128 / ds_write_b128
+__device__ __forceinline__ double2 lds_ld2(const double2* p, int e) {
+  const d2v v = ((const __attribute__((address_space(3))) d2v*)p)[e];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void lds_st2(double2* p, int e, double2 v) {
+  ((__attribute__((address_space(3))) d2v*)p)[e] = d2v{v.x, v.y};
+}
+__device__ __forceinline__ void lds_st(double* p, int e, double v) { ((lds_dw*)p)[e] = v; }
 
 struct PatternView {
   const double2* lds;     // staged matrix in LDS, row-major with leading dimension ld, or nullptr
@@ -281,7 +296,19 @@ struct PatternView {
     if (modes) return A[(int64_t)modes[i] * m + modes[j]];
     return A[src + (int64_t)i * n + j];
   }
+  // at() with the address spaces spelled out (LDS copy and mode list, global matrix), for functions
+  // that are not inlined into the kernel and would otherwise use flat accesses
+  __device__ __forceinline__ double2 at_as(int i, int j) const;
 };
+
+typedef const __attribute__((address_space(1))) double gbl_d;
+__device__ __forceinline__ double2 PatternView::at_as(int i, int j) const {
+  if (lds) return lds_ld2(lds, i * ld + j);
+  typedef const __attribute__((address_space(3))) int32_t lds_mode;
+  const int64_t off = modes ? (int64_t)((lds_mode*)modes)[i] * m + ((lds_mode*)modes)[j] : src + (int64_t)i * n + j;
+  gbl_d* g = (gbl_d*)A;
+  return make_double2(g[2 * off], g[2 * off + 1]);
+}
 
 // Gather from the zero-padded staged copy that the item loop below writes (ld = n + 1, row n and
 // column n zero): offset of row a and index of column c of M_Z = X A_Z (d x d) for the pair list

@@ -105,8 +105,8 @@ __device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, 
   for (int q = 0; q < P.nq; ++q)
     if (P.J[q] < T4) {
       const int t = sqt_idx(G, P.I[q], P.J[q]);
-      xq[t * 64 + lane] = make_double2(X.r[q], X.i[q]);
-      if (!SAME) yq[t * 64 + lane] = make_double2(Y.r[q], Y.i[q]);
+      lds_st2(xq, t * 64 + lane, make_double2(X.r[q], X.i[q]));
+      if (!SAME) lds_st2(yq, t * 64 + lane, make_double2(Y.r[q], Y.i[q]));
     }
   __syncthreads();
   double t1[Q], t2[Q], t3[Q];
@@ -118,14 +118,14 @@ __device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, 
 #pragma unroll
       for (int c = 0; c < P.nc; ++c) {
         const int J = P.cols[c];
-        b[c] = K <= J ? yq[sqt_idx(G, K, J) * 64 + lane] : yq[sqt_idx(G, J, K) * 64 + ln.tf];
+        b[c] = K <= J ? lds_ld2(yq, sqt_idx(G, K, J) * 64 + lane) : lds_ld2(yq, sqt_idx(G, J, K) * 64 + ln.tf);
         bs[c] = b[c].x + b[c].y;
       }
       // one A operand (a row of the wave's tiles) at a time
 #pragma unroll
       for (int r = 0; r < P.nr; ++r) {
         const int I = P.rows[r];
-        const double2 a = K <= I ? xq[sqt_idx(G, K, I) * 64 + ln.l17] : xq[sqt_idx(G, I, K) * 64 + ln.tr];
+        const double2 a = K <= I ? lds_ld2(xq, sqt_idx(G, K, I) * 64 + ln.l17) : lds_ld2(xq, sqt_idx(G, I, K) * 64 + ln.tr);
         const double as = a.x + a.y;
 #pragma unroll
         for (int q = 0; q < P.nq; ++q) {
@@ -192,7 +192,7 @@ __device__ __forceinline__ void run_ops_sqt(SqtMat<G> (&S)[NS], double (&tb)[4],
       sqt_mul<G, W, op.a == op.b>(S[op.a], S[op.b], S[op.x], T4, lane, ln, xq);
     } else {
       const double2 p = op.type == OP_TDIAG ? sqt_diag<G, W>(S[op.a], lane) : sqt_pair<G, W>(S[op.a], S[op.b]);
-      push_trace<K, OI>(tb, fold32(p.x, p.y), lane, [&](int j, int part, double v) { tred_b[(j - 1) * 2 + part] = v; });
+      push_trace<K, OI>(tb, fold32(p.x, p.y), lane, [&](int j, int part, double v) { lds_st(tred_b, (j - 1) * 2 + part, v); });
     }
     run_ops_sqt<K, G, W, OI + 1, NS>(S, tb, tred_b, T4, lane, ln, xq);
   }
@@ -207,6 +207,7 @@ __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4,
                                          int lane, double2* xq, double* tred) {
   constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   constexpr int NS = kChainTable[K].nslots;
+  T4 = __builtin_amdgcn_readfirstlane(T4);  // uniform: the k-tile and output-tile tests become scalar branches
   const int b = (lane >> 2) & 3;
   const int x = lane & 3, y = lane >> 4;
   const int32_t* pl = pl4 + b * kMaxK;
@@ -218,7 +219,8 @@ __device__ __noinline__ void eval_sqt(const PatternView& Pv, const int32_t* pl4,
     double vr = 0.0, vi = 0.0;
     if (a < dv && c < dv) {
       const int bb = a ^ 1;  // M = X A_Z: row a of M is row a^1 of A_Z
-      const double2 e = Pv.at(2 * pl[bb >> 1] + (bb & 1), 2 * pl[c >> 1] + (c & 1));
+      const int i = 2 * ((lds_i32*)pl)[bb >> 1] + (bb & 1), j = 2 * ((lds_i32*)pl)[c >> 1] + (c & 1);
+      const double2 e = Pv.at_as(i, j);
       vr = e.x;
       vi = e.y;
     }
