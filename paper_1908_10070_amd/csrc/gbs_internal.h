@@ -114,7 +114,8 @@ struct MargArgs {
 //   63..69  quad-tile engine, |Z| = 11, 12, k = 17..23               (gbs_eng_tile.hip)
 //   70..84  tile engine, 2x2 16x16 tiles, |Z| = 13..16 (and 9..12 where the engine shape asks for
 //           it), k = 9..23                                             (gbs_eng_tile.hip)
-//   85..91  tile engine, 3x3 16x16 tiles, |Z| >= 17, k = 17..23      (gbs_eng_tile.hip)
+//   85..91  tile engine, 3x3 16x16 tiles (the six on and above the diagonal), |Z| >= 17, k = 17..23
+//                                                                      (gbs_eng_tile.hip)
 //   92..94  double-double engine (accuracy mode), 2|Z| <= 16, 32, 48; any k (gbs_eng_dd.hip)
 //   95..107 symmetric quad-tile engine, 6x6 grid, |Z| = 11, 12 (and 9, 10), k = 11..23 (gbs_eng_sqt.hip)
 //   108..118 symmetric quad-tile engine, 7x7 grid, |Z| = 13, 14, k = 13..23 (gbs_eng_sqt7.hip)
@@ -133,7 +134,10 @@ constexpr int kShapeSqt910 = 8;    // |Z| = 9, 10: symmetric quad-tile engine
 constexpr int kShapeSqt1314 = 16;  // |Z| = 13, 14: symmetric quad-tile engine on a 7x7 grid
 constexpr int kShapeMask = 31;
 
-enum EngineKind { kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3, kDdKind = 4, kSqtKind = 5 };
+enum EngineKind {
+  kQuadKind = 0, kStripKind = 1, kQtileKind = 2, kTileKind = 3, kDdKind = 4, kSqtKind = 5,
+  kTileSymKind = 6  // the 16x16 tile engine storing only the tiles on and above the diagonal
+};
 
 // Arithmetic of the subset engines: FP64 (MFMA) or double-double (VALU, error-free transformations).
 enum Precision { kPrecFp64 = 0, kPrecDd = 1 };

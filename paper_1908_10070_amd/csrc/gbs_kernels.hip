@@ -491,7 +491,8 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   const EngineVariant v = variant(cls);
   if (v.kind == kQtileKind) return qtile_lds_layout(nmax, kmax, stage_A).total;
   if (v.kind == kStripKind) return strip_lds_bytes(nmax, kmax, stage_A);
-  if (v.kind == kTileKind) return tile_lds_layout(v.tiles, nmax, kmax, stage_A).total;
+  if (v.kind == kTileKind) return tile_lds_layout(v.tiles, false, nmax, kmax, stage_A).total;
+  if (v.kind == kTileSymKind) return tile_lds_layout(v.tiles, true, nmax, kmax, stage_A).total;
   if (v.kind == kDdKind) return dd_lds_layout(v.tiles, nmax, kmax).total;
   if (v.kind == kSqtKind) return sqt_lds_layout(v.tiles, nmax, kmax, stage_A).total;
   return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));

@@ -1,30 +1,81 @@
 // Tile-per-wave subset engine for subsets with 16 < d = 2|Z| <= 16 T (T = 2 or 3), gfx950.
 //
-// A workgroup of T*T waves evaluates one subset at a time. Wave (I, J) keeps tile (I, J) of M_Z and
-// of every power in registers, in the v_mfma_f64_16x16x4f64 accumulator layout (see the register
-// engine). A product Z = X Y publishes each wave's tiles of X and Y to LDS once; wave (I, J) then
-// accumulates Z(I, J) = sum_K X(I, K) Y(K, J) with the A operand X(I, K) read from tile (K, I) at lane
-// l ^ 17 (the pair symmetry Q^t = X Q X of every power) and the B operand from tile (K, J). Trace
-// inner products pair a tile with the same tile of the other factor, so they stay local; each wave
-// reduces its k partial traces with the shared VALU lane exchanges, and the T*T wave
-// results are added in wave order.
+// A workgroup evaluates one subset at a time, one 16x16 tile of M_Z and of every power per wave, in
+// registers in the v_mfma_f64_16x16x4f64 accumulator layout (lane x + 16y, register r holds element
+// (y + 4r, x)). Without SYM there are T*T waves, wave (I, J) holding tile (I, J); with SYM only the
+// T(T+1)/2 tiles with I <= J exist, one per wave in row-major order (every power Q has
+// Q[a][c] = Q[c^1][a^1], so tile (J, I) is a permutation of tile (I, J)). A product Z = X Y publishes
+// each wave's tiles of X and Y to LDS once; wave (I, J) then accumulates Z(I, J) = sum_K X(I, K) Y(K, J)
+// with the A operand X(I, K) read from tile (K, I) at lane l ^ 17 and the B operand from tile (K, J);
+// under SYM a tile below the diagonal is read out of its stored mirror with the permuted addresses
+// of tile_a_addr / tile_b_addr. Trace inner products pair a tile with the same tile of the other
+// factor, so they stay local (under SYM an off-diagonal tile counts twice, for its mirror); each wave
+// reduces its k partial traces with the shared VALU lane exchanges, and the wave results are added in
+// wave order.
 // Coefficient recursion, compensated summation and partials are the shared ones (gbs_engine_common.h).
 #pragma once
 #include "gbs_engine_common.h"
 
 namespace gbs {
+
+// waves (= stored tiles) per subset
+__host__ __device__ constexpr int tile_waves(int T, bool sym) { return sym ? T * (T + 1) / 2 : T * T; }
+
 namespace {
 
-template <int T, bool G>
+// stored index of tile (I, J) (I <= J under SYM)
+template <int T, bool SYM>
+__device__ __forceinline__ int tile_slot(int I, int J) {
+  return SYM ? I * T - I * (I - 1) / 2 + (J - I) : I * T + J;
+}
+// the tile wave w holds
+template <int T, bool SYM>
+__device__ __forceinline__ void tile_of_wave(int w, int& I, int& J) {
+  if constexpr (!SYM) {
+    I = w / T;
+    J = w % T;
+  } else {
+    I = 0;
+    while (w >= T - I) {
+      w -= T - I;
+      ++I;
+    }
+    J = I + w;
+  }
+}
+// LDS element index (in double2 units, inside the stored tile) of the A operand of step r for tile
+// (I, K), K > I, read from the stored tile (I, K): the operand wants element (x, y + 4r) of X(I, K)
+// at lane x + 16y, i.e. register x >> 2 at lane (y + 4r) + 16 (x & 3).
+__device__ __forceinline__ int tile_a_addr(int lane, int r) {
+  const int x = lane & 15, y = lane >> 4;
+  return (x >> 2) * 64 + (y + 4 * r) + 16 * (x & 3);
+}
+// The B operand of step r for tile (K, J), K > J, from the stored tile (J, K): element (y + 4r, x) of
+// Y(K, J) is element (x^1, (y + 4r)^1) of Y(J, K): register (x^1) >> 2 at lane ((y^1) + 4r) + 16 ((x^1) & 3).
+__device__ __forceinline__ int tile_b_addr(int lane, int r) {
+  const int x = lane & 15, y = lane >> 4;
+  return ((x ^ 1) >> 2) * 64 + ((y ^ 1) + 4 * r) + 16 * ((x ^ 1) & 3);
+}
+
+template <int T, bool SYM, bool G>
 __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMat<1>& Z, int d, int lane, int w,
                                          int I, int J, double2* xbuf) {
-  constexpr int NT = T * T;
+  constexpr int NT = tile_waves(T, SYM);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     xbuf[((0 * NT + w) * 4 + r) * 64 + lane] = make_double2(X.r[0][0][r], X.i[0][0][r]);
     xbuf[((1 * NT + w) * 4 + r) * 64 + lane] = make_double2(Y.r[0][0][r], Y.i[0][0][r]);
   }
   __syncthreads();
+  // operand r of k-tile K: A from X(I, K), B from Y(K, J)
+  auto opA = [&](int K, int r) -> double2 {
+    if (!SYM || K <= I) return xbuf[((0 * NT + tile_slot<T, SYM>(K, I)) * 4 + r) * 64 + (lane ^ 17)];
+    return xbuf[(0 * NT + tile_slot<T, SYM>(I, K)) * 4 * 64 + tile_a_addr(lane, r)];
+  };
+  auto opB = [&](int K, int r) -> double2 {
+    if (!SYM || K <= J) return xbuf[((1 * NT + tile_slot<T, SYM>(K, J)) * 4 + r) * 64 + lane];
+    return xbuf[(1 * NT + tile_slot<T, SYM>(J, K)) * 4 * 64 + tile_b_addr(lane, r)];
+  };
   // The first step (K = 0, r = 0) always runs for a tile inside d and starts the accumulators.
   const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
   d4 accr, acci;
@@ -38,8 +89,8 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
         for (int r = 0; r < 4; ++r) {
           const bool first = K == 0 && r == 0;
           if (first || 16 * K + 4 * r < d) {
-            const double2 a = xbuf[((0 * NT + K * T + I) * 4 + r) * 64 + (lane ^ 17)];
-            const double2 b = xbuf[((1 * NT + K * T + J) * 4 + r) * 64 + lane];
+            const double2 a = opA(K, r);
+            const double2 b = opB(K, r);
             accr = mfma(a.x, b.x, first ? zero : accr);
             acci = mfma(a.y, b.y, first ? zero : acci);
             t3 = mfma(a.x + a.y, b.x + b.y, first ? zero : t3);
@@ -62,8 +113,8 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
       for (int r = 0; r < 4; ++r) {
         const bool first = K == 0 && r == 0;
         if (first || 16 * K + 4 * r < d) {
-          const double2 a = xbuf[((0 * NT + K * T + I) * 4 + r) * 64 + (lane ^ 17)];
-          const double2 b = xbuf[((1 * NT + K * T + J) * 4 + r) * 64 + lane];
+          const double2 a = opA(K, r);
+          const double2 b = opB(K, r);
           accr = mfma(a.x, b.x, first ? zero : accr);
           acci = mfma(a.x, b.y, first ? zero : acci);
           accr = mfma(-a.y, b.y, accr);
@@ -79,30 +130,32 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
   Z.i[0][0] = acci;
 }
 
-template <int K, int T, int OI, int NS>
+template <int K, int T, bool SYM, int OI, int NS>
 __device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double (&tw)[K], int d, int lane, int w, int I, int J,
                                              double2* xbuf) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      tile_mul<T, (K <= GBS_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
+      tile_mul<T, SYM, (K <= GBS_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
     } else if constexpr (op.type == OP_TDIAG) {
       const double2 p = I == J ? tdiag<1>(S[op.a], lane) : make_double2(0.0, 0.0);
       tw[op.x - 1] = fold32(p.x, p.y);
     } else {
-      const double2 p = tpair<1>(S[op.a], S[op.b]);
+      double2 p = tpair<1>(S[op.a], S[op.b]);
+      if (SYM && I != J) p = make_double2(2.0 * p.x, 2.0 * p.y);  // and its mirror tile
       tw[op.x - 1] = fold32(p.x, p.y);
     }
-    run_ops_tile<K, T, OI + 1, NS>(S, tw, d, lane, w, I, J, xbuf);
+    run_ops_tile<K, T, SYM, OI + 1, NS>(S, tw, d, lane, w, I, J, xbuf);
   }
 }
 
 // One subset on the whole workgroup; the wave sums of the traces land in tred[w][component].
-template <int K, int T>
+template <int K, int T, bool SYM>
 __device__ __forceinline__ void eval_subset_tile(const PatternView& P, const int32_t* pl, int d, int lane, int w,
                                                  double2* xbuf, double* tred) {
   constexpr int NS = kChainTable[K].nslots;
-  const int I = w / T, J = w % T;
+  int I, J;
+  tile_of_wave<T, SYM>(w, I, J);
   CMat<1> S[NS];
   const int x = lane & 15, y = lane >> 4;
 #pragma unroll
@@ -121,16 +174,16 @@ __device__ __forceinline__ void eval_subset_tile(const PatternView& P, const int
   }
   // each wave's share of every trace, summed over the wave; added across waves in wave order later
   double tw[K];
-  run_ops_tile<K, T, 0, NS>(S, tw, d, lane, w, I, J, xbuf);
+  run_ops_tile<K, T, SYM, 0, NS>(S, tw, d, lane, w, I, J, xbuf);
   reduce_folded<K>(tw, lane, [&](int j, int part, double v) { tred[w * 2 * K + 2 * (j - 1) + part] = v; });
 }
 
-template <int K, int T>
+template <int K, int T, bool SYM>
 __device__ void tile_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl, double2* xbuf, double* tred,
                            double* trw, int32_t* sz, double2* terms, int tid, double& sr, double& si, double& cr,
                            double& ci) {
-  constexpr int NT = T * T;
-  const int w = tid >> 6, lane = tid & 63;
+  constexpr int NT = tile_waves(T, SYM);
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   int s = 1;
   uint32_t mask = lo < hi ? unrank(K, lo, &s) : 0u;
   for (int64_t g0 = lo; g0 < hi; g0 += kWaveG) {
@@ -141,7 +194,7 @@ __device__ void tile_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       if (tid < K && ((mask >> tid) & 1u)) pl[__popc(mask & ((1u << tid) - 1u))] = tid;
       if (tid == 0) sz[u] = s;
       __syncthreads();
-      eval_subset_tile<K, T>(P, pl, 2 * s, lane, w, xbuf, tred);
+      eval_subset_tile<K, T, SYM>(P, pl, 2 * s, lane, w, xbuf, tred);
       __syncthreads();
       if (tid < 2 * K) {
         double v = tred[tid];
@@ -162,7 +215,8 @@ struct TileLds {
   size_t A, modes, pl, xbuf, tred, trw, sz, terms, item, total;
 };
 
-__host__ __device__ inline TileLds tile_lds_layout(int T, int nmax, int kmax, int stage_A) {
+__host__ __device__ inline TileLds tile_lds_layout(int T, bool sym, int nmax, int kmax, int stage_A) {
+  const int NT = tile_waves(T, sym);
   TileLds L;
   size_t off = 0;
   L.A = off;
@@ -172,9 +226,9 @@ __host__ __device__ inline TileLds tile_lds_layout(int T, int nmax, int kmax, in
   L.pl = off;
   off += wal16(sizeof(int32_t) * kMaxK);
   L.xbuf = off;
-  off += wal16(sizeof(double) * 2 * 2 * T * T * 4 * 64);
+  off += wal16(sizeof(double) * 2 * 2 * NT * 4 * 64);
   L.tred = off;
-  off += wal16(sizeof(double) * T * T * 2 * kmax);
+  off += wal16(sizeof(double) * NT * 2 * kmax);
   L.trw = off;
   off += wal16(sizeof(double) * (kmax + 1) * 2 * kWaveG);
   L.sz = off;
@@ -187,11 +241,11 @@ __host__ __device__ inline TileLds tile_lds_layout(int T, int nmax, int kmax, in
   return L;
 }
 
-template <int T, int K>
-__global__ __launch_bounds__(T * T * 64) void tile_engine_kernel(EngineArgs args) {
+template <int T, int K, bool SYM = false>
+__global__ __launch_bounds__(tile_waves(T, SYM) * 64) void tile_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NTH = T * T * 64;
-  const TileLds L = tile_lds_layout(T, args.nmax, args.kmax, args.stage_A);
+  constexpr int NTH = tile_waves(T, SYM) * 64;
+  const TileLds L = tile_lds_layout(T, SYM, args.nmax, args.kmax, args.stage_A);
   double2* Alds = reinterpret_cast<double2*>(smem + L.A);
   int32_t* mlds = reinterpret_cast<int32_t*>(smem + L.modes);
   int32_t* pl = reinterpret_cast<int32_t*>(smem + L.pl);
@@ -235,7 +289,7 @@ __global__ __launch_bounds__(T * T * 64) void tile_engine_kernel(EngineArgs args
     P.m = args.m;
     P.ld = n;
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-    if (k == K) tile_range<K, T>(P, item.lo, item.hi, pl, xbuf, tred, trw, sz, terms, tid, sr, si, cr, ci);
+    if (k == K) tile_range<K, T, SYM>(P, item.lo, item.hi, pl, xbuf, tred, trw, sz, terms, tid, sr, si, cr, ci);
     if (tid == 0) {
       gbs_partial p;
       p.s_re = sr;
