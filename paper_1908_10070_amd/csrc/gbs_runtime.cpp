@@ -231,10 +231,6 @@ struct Plan {
   int nmax = 0, kmax = 0;
 };
 
-struct ItemLists {
-  std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
-};
-
 // The runs of subset sizes of a size-n pattern that share an engine variant (engine_class), in
 // increasing |Z|, each with its range [a, b) of the canonical order clipped to [lo, hi) and its chunk:
 // chunk_small subsets per item for |Z| <= 8, chunk_large above.
@@ -244,6 +240,12 @@ struct ClassRun {
 };
 
 constexpr int64_t kDdChunk = 32;
+
+struct ItemLists {
+  std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
+  std::vector<ClassRun> full_runs[GBS_N_MAX + 1];  // class runs of a whole size-n pattern
+  bool have_full[GBS_N_MAX + 1] = {};
+};
 
 std::vector<ClassRun> class_runs(const gbs_ctx* ctx, int n, int64_t lo, int64_t hi) {
   std::vector<ClassRun> out;
@@ -267,10 +269,22 @@ std::vector<ClassRun> class_runs(const gbs_ctx* ctx, int n, int64_t lo, int64_t 
 }
 
 // Split [lo, hi) of pattern p into items: the class runs cut into chunks; partial indices follow
-// the runs in increasing |Z|.
+// the runs in increasing |Z|. The runs of a whole pattern depend only on n and are kept per call in
+// L.full_runs.
 void plan_range(const gbs_ctx* ctx, Plan& pl, ItemLists& L, int p, int n, int64_t lo, int64_t hi) {
   if (hi <= lo) return;
-  for (const ClassRun& r : class_runs(ctx, n, lo, hi)) {
+  std::vector<ClassRun> part;
+  const std::vector<ClassRun>* runs = &part;
+  if (lo == 0 && hi == subset_count(n)) {
+    if (!L.have_full[n]) {
+      L.full_runs[n] = class_runs(ctx, n, lo, hi);
+      L.have_full[n] = true;
+    }
+    runs = &L.full_runs[n];
+  } else {
+    part = class_runs(ctx, n, lo, hi);
+  }
+  for (const ClassRun& r : *runs) {
     std::vector<WorkItem>& out = L.cls[r.cls];
     for (int64_t x = r.a; x < r.b; x += r.chunk) {
       WorkItem w;
@@ -291,17 +305,20 @@ void order_items(Plan& pl, ItemLists& L) {
   pl.items.clear();
   pl.groups.clear();
   for (int cls = kEngineClasses - 1; cls >= 0; --cls) {
-    std::vector<WorkItem>& v = L.cls[cls];
+    const std::vector<WorkItem>& v = L.cls[cls];
     if (v.empty()) continue;
-    std::stable_sort(v.begin(), v.end(), [&](const WorkItem& a, const WorkItem& b) {
-      return pl.pats[a.pattern].n > pl.pats[b.pattern].n;
-    });
+    // stable order by decreasing n: a counting pass over the (at most GBS_N_MAX + 1) sizes
+    int64_t count[GBS_N_MAX + 2] = {};
+    for (const WorkItem& w : v) ++count[GBS_N_MAX - pl.pats[w.pattern].n + 1];
+    for (int q = 1; q <= GBS_N_MAX + 1; ++q) count[q] += count[q - 1];
     Plan::Group g;
     g.cls = cls;
-    g.n = pl.pats[v.front().pattern].n;
     g.first = (int64_t)pl.items.size();
     g.count = (int64_t)v.size();
-    pl.items.insert(pl.items.end(), v.begin(), v.end());
+    pl.items.resize(pl.items.size() + v.size());
+    WorkItem* dst = pl.items.data() + g.first;
+    for (const WorkItem& w : v) dst[count[GBS_N_MAX - pl.pats[w.pattern].n]++] = w;
+    g.n = pl.pats[dst[0].pattern].n;
     pl.groups.push_back(g);
   }
 }
@@ -558,11 +575,13 @@ bool check_gfx950(int device) {
 // Validate one mode list and compute prod_j s_j! (collision multiplicities, Eq. ProOri).
 int pattern_sfact(gbs_ctx* ctx, const int32_t* modes, int64_t len, int32_t m, double* sfact) {
   int32_t tmp[GBS_N_MAX];
+  bool sorted = true;
   for (int64_t i = 0; i < len; ++i) {
     if (modes[i] < 0 || modes[i] >= m) return fail(ctx, GBS_ERANGE, "mode %d outside [0, %d)", modes[i], m);
     tmp[i] = modes[i];
+    sorted = sorted && (i == 0 || tmp[i - 1] <= tmp[i]);
   }
-  std::sort(tmp, tmp + len);
+  if (!sorted) std::sort(tmp, tmp + len);  // mode lists usually come sorted
   double f = 1.0;
   int64_t run = 1;
   for (int64_t i = 1; i <= len; ++i) {
