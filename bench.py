@@ -330,6 +330,8 @@ def run_config3(args):
     from paper_1908_10070_amd import gbs, inputs
     dev = torch.device("cuda", 0)
     ctx = gbs.Context(0)
+    if args.streams:
+        ctx.set_streams(args.streams)
     c5 = args.workload == "config5"
     st_in, pats = inputs.config5() if c5 else inputs.config3()
     st = ctx.state(torch.from_numpy(st_in.U).to(dev), st_in.r)
@@ -381,6 +383,8 @@ def main():
                     help="arrival rates as fractions of the measured batched capacity")
     ap.add_argument("--step-flops", type=float, default=1.6e12, help="modelled work per server step")
     ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO per-pattern server")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="streams of the headline context (gbs_ctx_set_streams; 0 = the library's default)")
     ap.add_argument("--serve-streams", type=int, default=4,
                     help="streams a mixed batch's kernels are spread over (gbs_ctx_set_streams), for the batched "
                          "capacity and each server step")
@@ -426,6 +430,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = gbs.Context(0, use_graph=True, persistent=True)
+    if args.streams:
+        ctx.set_streams(args.streams)
     stream = torch.cuda.current_stream()
     # launch shape: the built-in table (the autotuner's output for every n), or tuned here with --tune
     from paper_1908_10070_amd import autotune
@@ -484,6 +490,7 @@ def main():
         "config": {"workload": "config2: 4096 random complex-symmetric 24x24 matrices (seed 1002), haf_batch, "
                                "persistent launch replayed from a HIP graph", "n": n, "batch": batch,
                    "chunk_small": int(chunks[0]), "chunk_large": int(chunks[1]), "engine_shape": int(shape),
+                   "streams": ctx.streams,
                    "launch_shape_from": "chunks given" if args.chunks else ("autotuned here" if args.tune else
                                                                              "built-in table (autotuner output)")},
         "max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),

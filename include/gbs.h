@@ -103,9 +103,12 @@ int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
  * internal streams, forked from the call's stream after its staging copy and joined back before the
  * final combine, so that the kernels of a mixed batch (a serving step: many sizes, each a few
  * patterns) run side by side instead of one after another. With use_graph the fork and join are
- * captured as graph edges. 1 (default) = every kernel on the call's stream. Results are the same bit
- * for bit. GBS_EINVAL outside [1, 8]; GBS_EHIP if a stream or event cannot be created. */
+ * captured as graph edges. 1 = every kernel on the call's stream; the default is 2 (a one-size batch's
+ * few kernels then overlap their tails; a serving step's many small kernels want about 4). Results are
+ * the same bit for bit. GBS_EINVAL outside [1, 8]; GBS_EHIP if a stream or event cannot be created. */
 int gbs_ctx_set_streams(gbs_ctx* ctx, int32_t nstreams);
+/* The context's stream count (*nstreams). GBS_EINVAL for a null argument. */
+int gbs_ctx_get_streams(const gbs_ctx* ctx, int32_t* nstreams);
 
 /* Debugging hooks (process-wide, any thread).
  * gbs_debug_fault_inject(N): the N-th library call from now on that would enqueue compute work

@@ -28,7 +28,7 @@ GBS_SHAPE_SQT_13_14 = 16
 EXPORTS = [
     "gbs_ctx_create", "gbs_ctx_destroy", "gbs_ctx_set_workspace", "gbs_ctx_workspace_needed", "gbs_status_str",
     "gbs_last_error", "gbs_ctx_set_exec", "gbs_ctx_set_precision", "gbs_ctx_get_precision", "gbs_debug_fault_inject",
-    "gbs_debug_check_symmetry", "gbs_ctx_set_streams", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_ctx_set_shape", "gbs_ctx_get_shape", "gbs_haf_flops",
+    "gbs_debug_check_symmetry", "gbs_ctx_set_streams", "gbs_ctx_get_streams", "gbs_ctx_set_tuning", "gbs_ctx_get_tuning", "gbs_ctx_set_shape", "gbs_ctx_get_shape", "gbs_haf_flops",
     "haf_batch", "haf_batch_varlen", "haf_batch_noalloc", "gbs_state_bytes", "gbs_state_create", "gbs_state_destroy",
     "gbs_state_info", "gbs_state_copy_B", "gbs_prob_batch", "gbs_subset_count", "gbs_prob_slices",
     "gbs_finalize", "gbs_marginal_batch", "gbs_photon_number_pmf", "gbs_sample_step", "gbs_sweep_count",
@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         "gbs_debug_check_symmetry": (ctypes.c_int, [i32]),
         "gbs_ctx_get_precision": (i32, [vp]),
         "gbs_ctx_set_streams": (ctypes.c_int, [vp, i32]),
+        "gbs_ctx_get_streams": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
         "gbs_ctx_set_tuning": (ctypes.c_int, [vp, i32, i64, i64]),
         "gbs_ctx_get_tuning": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "gbs_ctx_set_shape": (ctypes.c_int, [vp, i32, i32]),
@@ -286,8 +287,15 @@ class Context:
         return "dd" if lib().gbs_ctx_get_precision(self.handle) == GBS_PREC_DD else "fp64"
 
     def set_streams(self, nstreams: int):
-        """Eager launches: spread a call's engine kernels over nstreams internal streams (1 = serial)."""
+        """Spread a call's engine kernels over nstreams internal streams (1 = all on the call's stream;
+        a new context uses 2)."""
         self._check(lib().gbs_ctx_set_streams(self.handle, int(nstreams)))
+
+    @property
+    def streams(self) -> int:
+        v = ctypes.c_int32()
+        self._check(lib().gbs_ctx_get_streams(self.handle, ctypes.byref(v)))
+        return v.value
 
     def set_tuning(self, n: int, chunk_small: int, chunk_large: int):
         self._check(lib().gbs_ctx_set_tuning(self.handle, int(n), int(chunk_small), int(chunk_large)))

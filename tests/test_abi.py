@@ -66,6 +66,7 @@ def test_null_context_rejected(lib):
     assert lib.gbs_state_destroy(None) == gbs.GBS_EINVAL
     assert lib.gbs_ctx_set_exec(None, 1, 1) == gbs.GBS_EINVAL
     assert lib.gbs_ctx_set_streams(None, 2) == gbs.GBS_EINVAL
+    assert lib.gbs_ctx_get_streams(None, None) == gbs.GBS_EINVAL
     out = vp()
     assert lib.gbs_ctx_create(0, None, 0, None) == gbs.GBS_EINVAL
     assert lib.gbs_ctx_create(0, None, 123, ctypes.byref(out)) == gbs.GBS_EINVAL

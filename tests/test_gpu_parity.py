@@ -162,10 +162,12 @@ def test_multi_stream_launches_are_bitwise_equal(ctx, torch_dev):
     st = ctx.state(to_dev(U, torch_dev), r)
     pats = [sorted(rng.choice(m, int(n), replace=False).tolist()) for n in rng.choice(range(4, 31, 2), 60)]
     ref = ctx.prob_batch(st, pats).cpu().numpy()
+    assert gbs.Context(0).streams == 2  # a new context's default
     for ns, graph, persistent in [(4, False, True), (8, False, False), (3, False, True), (4, True, True),
                                   (8, True, False)]:
         c2 = gbs.Context(0, use_graph=graph, persistent=persistent)
         c2.set_streams(ns)
+        assert c2.streams == ns
         for _ in range(3):  # a graph is captured on the first call and replayed after
             assert np.array_equal(c2.prob_batch(st, pats).cpu().numpy(), ref), (ns, graph)
     with pytest.raises(gbs.GBSError):
