@@ -495,6 +495,8 @@ size_t engine_lds_bytes(int cls, int nmax, int kmax, int stage_A) {
   if (v.kind == kTileSymKind) return tile_lds_layout(v.tiles, true, nmax, kmax, stage_A).total;
   if (v.kind == kDdKind) return dd_lds_layout(v.tiles, nmax, kmax).total;
   if (v.kind == kSqtKind) return sqt_lds_layout(v.tiles, nmax, kmax, stage_A).total;
+  // the |Z| <= 6 kernel (tiles 3) parks no traces up to k = kQuad3WavesKMax
+  if (v.tiles == 3 && kmax <= kQuad3WavesKMax) return quad_lds_bytes(nmax, kmax, stage_A, 0);
   return quad_lds_bytes(nmax, kmax, stage_A, quad_park_k(v.tiles, kmax));
 }
 

@@ -22,9 +22,13 @@ namespace {
 #ifndef GBS_QUAD_GAUSS_KMAX
 #define GBS_QUAD_GAUSS_KMAX kMaxK
 #endif
-// occupancy: the |Z| <= 6 kernels run two waves per SIMD up to k = 20 (one above, where two would
-// spill; three, with spills, measured 1% slower at n = 24); up to GBS_QUAD_WAVES2_KMAX the 4x4-grid
-// kernels run two as well (one above)
+// occupancy: up to k = kQuad3WavesKMax the |Z| <= 6 kernels run three waves per SIMD (168 registers,
+// about 100 bytes of spills per lane) with their traces reduced four at a time instead of parked in
+// LDS, which is what lets three workgroups fit a CU (n = 24: 18.5 -> 18.0 ms; config 3: 73.4 -> 67.9
+// ms; at k = 14, 16 it measured within 1%); above, two waves up to k = 20 and one beyond (where two
+// would spill). Up to GBS_QUAD_WAVES2_KMAX the 4x4-grid kernels run two waves per SIMD (one above;
+// three spilled 132 registers and ran 35% slower).
+constexpr int kQuad3WavesKMax = 12;
 #ifndef GBS_QUAD_WAVES2_KMAX
 #define GBS_QUAD_WAVES2_KMAX 12
 #endif
@@ -156,6 +160,7 @@ __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
 
 // Traces of 3x3 and larger tile grids are parked in LDS (park[(j - 1) * 64 + lane]) until the chain
 // ends instead of holding k registers through every product; smaller grids keep them in registers.
+// (The |Z| <= 6 kernel up to k = kQuad3WavesKMax reduces them four at a time instead: push_trace.)
 constexpr int kQuadParkT4 = 3;
 // parking rows per wave: a kernel whose grids have at most T4 tiles per side forms min(k, 4 T4) traces
 __host__ __device__ constexpr int quad_park_k(int t4max, int k) { return k < 4 * t4max ? k : 4 * t4max; }
@@ -206,12 +211,12 @@ __device__ __forceinline__ void reduce_folded_quad(const double (&w)[K], int lan
   }
 }
 
-// Batched trace reduction for engines whose LDS budget cannot hold a parking area: the q-th trace
+// Batched trace reduction for engines whose occupancy a parking area would limit: the q-th trace
 // operation of a chain program goes to slot q % 4 of a four-value buffer, and each full buffer (and
 // the last, partial one) is reduced over the 16 lanes of every block at once (reduce_folded_quad) and
 // handed to store(j, part, value) with its trace index j. The exchanges per trace are those of one
 // reduction at the end; the buffer's registers stay live across the products in between, which is why
-// the one-wave engines above park their traces instead (their occupancy is bound by registers, not LDS).
+// the quad grids, whose occupancy registers bound, park their traces instead (the 4x4 grid spilled).
 __host__ __device__ constexpr int chain_trace_ord(const ChainProgram& p, int oi) {
   int c = 0;
   for (int i = 0; i < oi; ++i) c += p.ops[i].type != OP_MUL;
@@ -247,7 +252,22 @@ __device__ __forceinline__ void push_trace(double (&tb)[4], double v, int lane, 
 
 // Four subsets (one per block) with matrices of at most 4*T4 rows; forms the first KK of the K
 // traces (KK >= 2|Z| for all four, so the combine step extends the rest exactly).
-template <int K, int T4, int KK>
+template <int K, int T4, int OI, int NS, typename Store>
+__device__ __forceinline__ void run_ops_quad_b(QMat<T4> (&S)[NS], double (&tb)[4], int lane, const QPerm& pm,
+                                               Store store) {
+  if constexpr (OI < kChainTable[K].nops) {
+    constexpr Op op = kChainTable[K].ops[OI];
+    if constexpr (op.type == OP_MUL) {
+      qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], pm);
+    } else {
+      const double2 p = op.type == OP_TDIAG ? qdiag<T4>(S[op.a], lane) : qpair<T4>(S[op.a], S[op.b]);
+      push_trace<K, OI>(tb, fold32(p.x, p.y), lane, store);
+    }
+    run_ops_quad_b<K, T4, OI + 1, NS>(S, tb, lane, pm, store);
+  }
+}
+
+template <int K, int T4, int KK, bool PARK = true>
 __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* pl4, int d_b, bool valid_b, double* trw,
                                           double* park, int u_b, int lane) {
   static_assert(KK <= K, "trace count");
@@ -289,6 +309,13 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
         S[0].i[I][J] = vi;
       }
   }
+  if constexpr (!PARK) {
+    double tb[4];
+    run_ops_quad_b<KK, T4, 0, NS>(S, tb, lane, qperm(lane), [&](int j, int part, double v) {
+      if (valid_b) trw[j * (2 * kWaveG) + 2 * u_b + part] = 0.5 * v;
+    });
+    return;
+  }
   double w[KK];
   run_ops_quad<KK, T4, 0, NS>(S, w, park, lane, qperm(lane));
   if constexpr (T4 >= kQuadParkT4) {
@@ -303,7 +330,7 @@ __device__ __forceinline__ void eval_quad(const PatternView& P, const int32_t* p
 
 // Subsets [lo, hi) of one pattern on one wave, four at a time: all with |Z| <= 6 (grids of up to
 // 3x3 tiles), or, with T4F > 0, all with |Z| = 2 T4F - 1 or 2 T4F (a T4F x T4F grid).
-template <int K, int T4F = 0>
+template <int K, int T4F = 0, bool PARK = true>
 __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t* pl4, double* trw, double* park,
                            int32_t* sz,
                            double2* terms, int lane, double& sr, double& si, double& cr, double& ci) {
@@ -344,19 +371,19 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
       // traces formed: min(K, 2 smax), the rest follow from them (extend_traces)
       if constexpr (T4F > 0) {  // a kernel for one grid size: |Z| = 2 T4F - 1 or 2 T4F
         if (smax <= 2 * T4F - 1)
-          eval_quad<K, T4F, cmin(K, 4 * T4F - 2)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+          eval_quad<K, T4F, cmin(K, 4 * T4F - 2), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
         else
-          eval_quad<K, T4F, cmin(K, 4 * T4F)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+          eval_quad<K, T4F, cmin(K, 4 * T4F), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       } else if (smax <= 2)
-        eval_quad<K, 1, cmin(K, 4)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        eval_quad<K, 1, cmin(K, 4), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 3)
-        eval_quad<K, 2, cmin(K, 6)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        eval_quad<K, 2, cmin(K, 6), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 4)
-        eval_quad<K, 2, cmin(K, 8)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        eval_quad<K, 2, cmin(K, 8), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else if (smax <= 5)
-        eval_quad<K, 3, cmin(K, 10)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        eval_quad<K, 3, cmin(K, 10), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
       else
-        eval_quad<K, 3, cmin(K, 12)>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
+        eval_quad<K, 3, cmin(K, 12), PARK>(P, pl4, d_b, valid_b, trw, park, u_b, lane);
     }
     wave_sync();
     combine_batch<K, (K > 4)>(trw, sz, cnt, lane, sr, si, cr, ci);
@@ -366,7 +393,8 @@ __device__ void quad_range(const PatternView& P, int64_t lo, int64_t hi, int32_t
 
 }  // namespace
 
-// LDS: the shared item-loop layout (wave_lds_layout), then one trace-parking area per wave.
+// LDS: the shared item-loop layout (wave_lds_layout), then one trace-parking area per wave (park_k
+// rows; none for the |Z| <= 6 kernel up to k = kQuad3WavesKMax).
 __host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A, int park_k) {
   return wave_lds_layout(nmax, kmax, stage_A).total + sizeof(double) * 4 * park_k * 64;
 }
@@ -391,7 +419,8 @@ quad_grid_kernel(EngineArgs args) {
 }
 
 template <int K>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(K <= 20 ? 2 : 1, 8))) void
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    K <= kQuad3WavesKMax ? 3 : (K <= 20 ? 2 : 1), 8))) void
 quad_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);
@@ -401,8 +430,9 @@ quad_engine_kernel(EngineArgs args) {
     double* trw = reinterpret_cast<double*>(smem + L.trw) + (size_t)wave * (args.kmax + 1) * 2 * kWaveG;
     int32_t* sz = reinterpret_cast<int32_t*>(smem + L.sz) + wave * kWaveG;
     double2* terms = reinterpret_cast<double2*>(smem + L.terms) + wave * kWaveG;
-    double* park = reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(3, K) * 64;
-    quad_range<K>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
+    double* park = K > kQuad3WavesKMax ? reinterpret_cast<double*>(smem + L.total) + wave * quad_park_k(3, K) * 64
+                                       : nullptr;  // no park area (traces reduced four at a time)
+    quad_range<K, 0, (K > kQuad3WavesKMax)>(P, lo, hi, pl4, trw, park, sz, terms, lane, sr, si, cr, ci);
   });
 }
 
