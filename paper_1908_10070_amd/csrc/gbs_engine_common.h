@@ -267,6 +267,24 @@ __device__ __forceinline__ void reduce_folded(const double (&w)[K], int lane, St
   }
 }
 
+// Trace operations of a chain program in program order (for engines that reduce traces in batches):
+// the ordinal of operation oi among them, and the trace index j of the ord-th one.
+__host__ __device__ constexpr int chain_trace_ord(const ChainProgram& p, int oi) {
+  int c = 0;
+  for (int i = 0; i < oi; ++i) c += p.ops[i].type != OP_MUL;
+  return c;
+}
+// trace index j of the ord-th trace operation (0 past the last)
+__host__ __device__ constexpr int chain_trace_at(const ChainProgram& p, int ord) {
+  int c = 0;
+  for (int i = 0; i < p.nops; ++i)
+    if (p.ops[i].type != OP_MUL) {
+      if (c == ord) return p.ops[i].x;
+      ++c;
+    }
+  return 0;
+}
+
 typedef const __attribute__((address_space(3))) double lds_d;  // LDS-qualified, for direct ds_read
 typedef __attribute__((address_space(3))) double lds_dw;       // the same, writable
 

@@ -217,22 +217,6 @@ __device__ __forceinline__ void reduce_folded_quad(const double (&w)[K], int lan
 // handed to store(j, part, value) with its trace index j. The exchanges per trace are those of one
 // reduction at the end; the buffer's registers stay live across the products in between, which is why
 // the quad grids, whose occupancy registers bound, park their traces instead (the 4x4 grid spilled).
-__host__ __device__ constexpr int chain_trace_ord(const ChainProgram& p, int oi) {
-  int c = 0;
-  for (int i = 0; i < oi; ++i) c += p.ops[i].type != OP_MUL;
-  return c;
-}
-// trace index j of the ord-th trace operation (0 past the last)
-__host__ __device__ constexpr int chain_trace_at(const ChainProgram& p, int ord) {
-  int c = 0;
-  for (int i = 0; i < p.nops; ++i)
-    if (p.ops[i].type != OP_MUL) {
-      if (c == ord) return p.ops[i].x;
-      ++c;
-    }
-  return 0;
-}
-
 template <int KK, int OI, typename Store>
 __device__ __forceinline__ void push_trace(double (&tb)[4], double v, int lane, Store store) {
   static_assert(chain_trace_ord(kChainTable[KK], kChainTable[KK].nops) == KK, "one operation per trace");

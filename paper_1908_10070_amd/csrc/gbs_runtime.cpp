@@ -187,10 +187,10 @@ struct ShapeRow {
   int32_t cs, cl, shape;
 };
 constexpr ShapeRow kDefaultShape[GBS_N_MAX / 2 + 1] = {
-    {1024, 8, 0}, {1024, 8, 0}, {1024, 8, 0}, {1024, 8, 0}, {1024, 8, 0}, {1024, 8, 0}, {1024, 8, 0},
-    {1024, 8, 0}, {1024, 8, 0}, {256, 8, 1}, {256, 16, 0}, {512, 128, 2}, {256, 256, 4}, {512, 256, 4},
-    {512, 512, 4}, {256, 128, 4}, {256, 128, 20}, {256, 128, 20}, {256, 128, 20}, {256, 64, 20}, {256, 128, 20},
-    {128, 128, 20}, {256, 64, 20}, {128, 128, 20},
+    {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0},
+    {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {256, 16, 1}, {256, 64, 0}, {512, 128, 2}, {256, 256, 4},
+    {512, 32, 4}, {512, 128, 4}, {256, 256, 4}, {256, 128, 20}, {256, 128, 20}, {256, 128, 20}, {256, 128, 20},
+    {256, 128, 20}, {128, 128, 20}, {1024, 128, 20}, {128, 128, 20},
 };
 
 void default_chunks(int n, int64_t* cs, int64_t* cl) {

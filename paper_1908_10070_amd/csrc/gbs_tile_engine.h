@@ -10,8 +10,8 @@
 // under SYM a tile below the diagonal is read out of its stored mirror with the permuted addresses
 // of tile_a_addr / tile_b_addr. Trace inner products pair a tile with the same tile of the other
 // factor, so they stay local (under SYM an off-diagonal tile counts twice, for its mirror); each wave
-// reduces its k partial traces with the shared VALU lane exchanges, and the wave results are added in
-// wave order.
+// reduces its partial traces with the shared VALU lane exchanges, four traces at a time, and the wave
+// results are added in wave order.
 // Coefficient recursion, compensated summation and partials are the shared ones (gbs_engine_common.h).
 #pragma once
 #include "gbs_engine_common.h"
@@ -130,22 +130,40 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
   Z.i[0][0] = acci;
 }
 
-template <int K, int T, bool SYM, int OI, int NS>
-__device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double (&tw)[K], int d, int lane, int w, int I, int J,
-                                             double2* xbuf) {
+// Traces are reduced over the wave four at a time as the chain forms them (the q-th trace operation
+// goes to slot q % 4; full buffers, and the last, go through reduce_folded), so no k registers are held
+// across the products: that lets the kernel run three waves per SIMD (168 registers; at k = 22 about
+// 300 bytes of spills per lane) instead of two (n = 46, 2 hafnians: 212 -> 205 ms; n <= 36 unchanged).
+template <int KK, int OI, typename Store>
+__device__ __forceinline__ void push_trace_tile(double (&tb)[4], double v, int lane, Store store) {
+  constexpr int ord = chain_trace_ord(kChainTable[KK], OI), slot = ord % 4, first = ord - slot;
+  tb[slot] = v;
+  if constexpr (slot == 3 || ord == KK - 1) {
+#pragma unroll
+    for (int q = slot + 1; q < 4; ++q) tb[q] = 0.0;
+    constexpr int j0 = chain_trace_at(kChainTable[KK], first), j1 = chain_trace_at(kChainTable[KK], first + 1),
+                  j2 = chain_trace_at(kChainTable[KK], first + 2), j3 = chain_trace_at(kChainTable[KK], first + 3);
+    reduce_folded<4>(tb, lane, [&](int q, int part, double x) {
+      const int j = q == 1 ? j0 : (q == 2 ? j1 : (q == 3 ? j2 : j3));
+      if (q - 1 <= slot) store(j, part, x);
+    });
+  }
+}
+
+template <int K, int T, bool SYM, int OI, int NS, typename Store>
+__device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double (&tb)[4], int d, int lane, int w, int I, int J,
+                                             double2* xbuf, Store store) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       tile_mul<T, SYM, (K <= GBS_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
-    } else if constexpr (op.type == OP_TDIAG) {
-      const double2 p = I == J ? tdiag<1>(S[op.a], lane) : make_double2(0.0, 0.0);
-      tw[op.x - 1] = fold32(p.x, p.y);
     } else {
-      double2 p = tpair<1>(S[op.a], S[op.b]);
-      if (SYM && I != J) p = make_double2(2.0 * p.x, 2.0 * p.y);  // and its mirror tile
-      tw[op.x - 1] = fold32(p.x, p.y);
+      double2 p = op.type == OP_TDIAG ? (I == J ? tdiag<1>(S[op.a], lane) : make_double2(0.0, 0.0))
+                                      : tpair<1>(S[op.a], S[op.b]);
+      if (op.type != OP_TDIAG && SYM && I != J) p = make_double2(2.0 * p.x, 2.0 * p.y);
+      push_trace_tile<K, OI>(tb, fold32(p.x, p.y), lane, store);
     }
-    run_ops_tile<K, T, SYM, OI + 1, NS>(S, tw, d, lane, w, I, J, xbuf);
+    run_ops_tile<K, T, SYM, OI + 1, NS>(S, tb, d, lane, w, I, J, xbuf, store);
   }
 }
 
@@ -173,9 +191,9 @@ __device__ __forceinline__ void eval_subset_tile(const PatternView& P, const int
     S[0].i[0][0][r] = vi;
   }
   // each wave's share of every trace, summed over the wave; added across waves in wave order later
-  double tw[K];
-  run_ops_tile<K, T, SYM, 0, NS>(S, tw, d, lane, w, I, J, xbuf);
-  reduce_folded<K>(tw, lane, [&](int j, int part, double v) { tred[w * 2 * K + 2 * (j - 1) + part] = v; });
+  double tb[4];
+  run_ops_tile<K, T, SYM, 0, NS>(S, tb, d, lane, w, I, J, xbuf,
+                                 [&](int j, int part, double v) { tred[w * 2 * K + 2 * (j - 1) + part] = v; });
 }
 
 template <int K, int T, bool SYM>
@@ -242,7 +260,8 @@ __host__ __device__ inline TileLds tile_lds_layout(int T, bool sym, int nmax, in
 }
 
 template <int T, int K, bool SYM = false>
-__global__ __launch_bounds__(tile_waves(T, SYM) * 64) void tile_engine_kernel(EngineArgs args) {
+__global__ __launch_bounds__(tile_waves(T, SYM) * 64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
+tile_engine_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NTH = tile_waves(T, SYM) * 64;
   const TileLds L = tile_lds_layout(T, SYM, args.nmax, args.kmax, args.stage_A);
