@@ -68,77 +68,11 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Up to this k, complex products use three real products per step (Gauss): with T1 = Xr Yr,
-// T2 = Xi Yi, T3 = (Xr + Xi)(Yr + Yi), Re = T1 - T2 and Im = T3 - T1 - T2. That is 3/4 of the MFMA
-// work for two extra additions per step. The imaginary part's rounding bound is about twice the
-// four-product one; measured hafnian errors at n = 36..44 against the long-double oracle were no
-// larger, so every k uses it by default.
-#ifndef GBS_GAUSS_KMAX
-#define GBS_GAUSS_KMAX kMaxK
-#endif
-
-// Z = X Y (Z may alias X or Y). Every k-step runs: entries beyond d are zero, so the padded steps
-// add nothing, and starting each accumulator from the first product lets that MFMA take a zero
-// accumulator operand instead of registers cleared beforehand.
-template <int T, bool G>
-__device__ __forceinline__ void cmul_mat(const CMat<T>& X, const CMat<T>& Y, CMat<T>& Z, int d) {
-  (void)d;
-  const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
-  if constexpr (G) {
-    d4 t1[T][T], t2[T][T], t3[T][T];
-#pragma unroll
-    for (int K = 0; K < T; ++K)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double bs[T];
-#pragma unroll
-        for (int J = 0; J < T; ++J) bs[J] = Y.r[K][J][r] + Y.i[K][J][r];
-#pragma unroll
-        for (int I = 0; I < T; ++I) {
-          const double ar = swap17(X.r[K][I][r]);
-          const double ai = swap17(X.i[K][I][r]);
-          const double as = ar + ai;
-          const bool first = K == 0 && r == 0;
-#pragma unroll
-          for (int J = 0; J < T; ++J) {
-            t1[I][J] = mfma(ar, Y.r[K][J][r], first ? zero : t1[I][J]);
-            t2[I][J] = mfma(ai, Y.i[K][J][r], first ? zero : t2[I][J]);
-            t3[I][J] = mfma(as, bs[J], first ? zero : t3[I][J]);
-          }
-        }
-      }
-#pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-      for (int J = 0; J < T; ++J) {
-        Z.r[I][J] = t1[I][J] - t2[I][J];
-        Z.i[I][J] = t3[I][J] - t1[I][J] - t2[I][J];
-      }
-    return;
-  }
-  CMat<T> acc;
-#pragma unroll
-  for (int K = 0; K < T; ++K)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {  // register r of tile row K holds rows 16K + 4r .. 16K + 4r + 3
-#pragma unroll
-      for (int I = 0; I < T; ++I) {
-        const double ar = swap17(X.r[K][I][r]);
-        const double ai = swap17(X.i[K][I][r]);
-        const bool first = K == 0 && r == 0;
-#pragma unroll
-        for (int J = 0; J < T; ++J) {
-          const double br = Y.r[K][J][r];
-          const double bi = Y.i[K][J][r];
-          acc.r[I][J] = mfma(ar, br, first ? zero : acc.r[I][J]);
-          acc.i[I][J] = mfma(ar, bi, first ? zero : acc.i[I][J]);
-          acc.r[I][J] = mfma(-ai, bi, acc.r[I][J]);
-          acc.i[I][J] = mfma(ai, br, acc.i[I][J]);
-        }
-      }
-    }
-  Z = acc;
-}
+// Complex products use three real products per step (Gauss): with T1 = Xr Yr, T2 = Xi Yi,
+// T3 = (Xr + Xi)(Yr + Yi), Re = T1 - T2 and Im = T3 - T1 - T2. That is 3/4 of the MFMA work for two
+// extra additions per step. The imaginary part's rounding bound is about twice the four-product one;
+// measured hafnian errors at n = 36..44 against the long-double oracle were no larger, so every engine
+// uses it at every k.
 
 // per-lane partial of tr(X): the diagonal element this lane holds, if any
 template <int T>

@@ -18,20 +18,14 @@
 namespace gbs {
 namespace {
 
-// up to this k the quad engine multiplies with three real products per step (see cmul_mat)
-#ifndef GBS_QUAD_GAUSS_KMAX
-#define GBS_QUAD_GAUSS_KMAX kMaxK
-#endif
 // occupancy: up to k = kQuad3WavesKMax the |Z| <= 6 kernels run three waves per SIMD (168 registers,
 // about 100 bytes of spills per lane) with their traces reduced four at a time instead of parked in
 // LDS, which is what lets three workgroups fit a CU (n = 24: 18.5 -> 18.0 ms; config 3: 73.4 -> 67.9
 // ms; at k = 14, 16 it measured within 1%); above, two waves up to k = 20 and one beyond (where two
-// would spill). Up to GBS_QUAD_WAVES2_KMAX the 4x4-grid kernels run two waves per SIMD (one above;
+// would spill). Up to kQuadWaves2KMax the 4x4-grid kernels run two waves per SIMD (one above;
 // three spilled 132 registers and ran 35% slower).
 constexpr int kQuad3WavesKMax = 12;
-#ifndef GBS_QUAD_WAVES2_KMAX
-#define GBS_QUAD_WAVES2_KMAX 12
-#endif
+constexpr int kQuadWaves2KMax = 12;
 
 template <int T4>
 struct QMat {
@@ -60,11 +54,11 @@ __device__ __forceinline__ QPerm qperm(int lane) {
   return q;
 }
 
-// Z = X Y on the stored tiles (I <= J); three real products per step (see cmul_mat) when G.
+// Z = X Y on the stored tiles (I <= J); three real products per step (Gauss, gbs_engine_common.h).
 // The A operand of (I, K) is tile (K, I) read at lane l ^ 17 when K <= I (the symmetry above), else
 // stored tile (I, K) transposed; the B operand of (K, J) is stored when K <= J, else tile (J, K)
 // through tf. Z may alias X or Y: it is written after the last product.
-template <int T4, bool G>
+template <int T4>
 __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<T4>& Z, const QPerm& pm) {
   double t1[T4][T4], t2[T4][T4], t3[T4][T4];
 #pragma unroll
@@ -79,7 +73,7 @@ __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<
         br[J] = bperm(pm.tf, Y.r[J][K]);
         bi[J] = bperm(pm.tf, Y.i[J][K]);
       }
-      if constexpr (G) bs[J] = br[J] + bi[J];
+      bs[J] = br[J] + bi[J];
     }
 #pragma unroll
     for (int I = 0; I < T4; ++I) {
@@ -91,22 +85,12 @@ __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<
         ar = bperm(pm.tr, X.r[I][K]);
         ai = bperm(pm.tr, X.i[I][K]);
       }
-      if constexpr (G) {
-        const double as = ar + ai;
+      const double as = ar + ai;
 #pragma unroll
-        for (int J = I; J < T4; ++J) {
-          t1[I][J] = mfma4(ar, br[J], K == 0 ? 0.0 : t1[I][J]);
-          t2[I][J] = mfma4(ai, bi[J], K == 0 ? 0.0 : t2[I][J]);
-          t3[I][J] = mfma4(as, bs[J], K == 0 ? 0.0 : t3[I][J]);
-        }
-      } else {
-#pragma unroll
-        for (int J = I; J < T4; ++J) {
-          t1[I][J] = mfma4(ar, br[J], K == 0 ? 0.0 : t1[I][J]);
-          t3[I][J] = mfma4(ar, bi[J], K == 0 ? 0.0 : t3[I][J]);
-          t1[I][J] = mfma4(-ai, bi[J], t1[I][J]);
-          t3[I][J] = mfma4(ai, br[J], t3[I][J]);
-        }
+      for (int J = I; J < T4; ++J) {
+        t1[I][J] = mfma4(ar, br[J], K == 0 ? 0.0 : t1[I][J]);
+        t2[I][J] = mfma4(ai, bi[J], K == 0 ? 0.0 : t2[I][J]);
+        t3[I][J] = mfma4(as, bs[J], K == 0 ? 0.0 : t3[I][J]);
       }
     }
   }
@@ -114,13 +98,8 @@ __device__ __forceinline__ void qmul(const QMat<T4>& X, const QMat<T4>& Y, QMat<
   for (int I = 0; I < T4; ++I)
 #pragma unroll
     for (int J = I; J < T4; ++J) {
-      if constexpr (G) {
-        Z.r[I][J] = t1[I][J] - t2[I][J];
-        Z.i[I][J] = t3[I][J] - t1[I][J] - t2[I][J];
-      } else {
-        Z.r[I][J] = t1[I][J];
-        Z.i[I][J] = t3[I][J];
-      }
+      Z.r[I][J] = t1[I][J] - t2[I][J];
+      Z.i[I][J] = t3[I][J] - t1[I][J] - t2[I][J];
     }
 }
 
@@ -171,7 +150,7 @@ __device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], 
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], pm);
+      qmul<T4>(S[op.a], S[op.b], S[op.x], pm);
     } else {
       const double2 p = op.type == OP_TDIAG ? qdiag<T4>(S[op.a], lane) : qpair<T4>(S[op.a], S[op.b]);
       if constexpr (T4 >= kQuadParkT4)
@@ -242,7 +221,7 @@ __device__ __forceinline__ void run_ops_quad_b(QMat<T4> (&S)[NS], double (&tb)[4
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      qmul<T4, (K <= GBS_QUAD_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], pm);
+      qmul<T4>(S[op.a], S[op.b], S[op.x], pm);
     } else {
       const double2 p = op.type == OP_TDIAG ? qdiag<T4>(S[op.a], lane) : qpair<T4>(S[op.a], S[op.b]);
       push_trace<K, OI>(tb, fold32(p.x, p.y), lane, store);
@@ -387,7 +366,7 @@ __host__ __device__ inline size_t quad_lds_bytes(int nmax, int kmax, int stage_A
 // occupancy its registers allow: T4 = 4 (10 stored tiles, two waves per SIMD), T4 = 5 (15 stored
 // tiles, 380-512 VGPRs and AGPRs, one wave per SIMD)
 template <int K, int T4>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(T4 >= 5 || K > GBS_QUAD_WAVES2_KMAX ? 1 : 2, 8))) void
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(T4 >= 5 || K > kQuadWaves2KMax ? 1 : 2, 8))) void
 quad_grid_kernel(EngineArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WaveLds L = wave_lds_layout(args.nmax, args.kmax, args.stage_A);

@@ -57,7 +57,7 @@ __device__ __forceinline__ int tile_b_addr(int lane, int r) {
   return ((x ^ 1) >> 2) * 64 + ((y ^ 1) + 4 * r) + 16 * ((x ^ 1) & 3);
 }
 
-template <int T, bool SYM, bool G>
+template <int T, bool SYM>
 __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMat<1>& Z, int d, int lane, int w,
                                          int I, int J, double2* xbuf) {
   constexpr int NT = tile_waves(T, SYM);
@@ -76,36 +76,10 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
     if (!SYM || K <= J) return xbuf[((1 * NT + tile_slot<T, SYM>(K, J)) * 4 + r) * 64 + lane];
     return xbuf[(1 * NT + tile_slot<T, SYM>(J, K)) * 4 * 64 + tile_b_addr(lane, r)];
   };
-  // The first step (K = 0, r = 0) always runs for a tile inside d and starts the accumulators.
+  // The first step (K = 0, r = 0) always runs for a tile inside d and starts the accumulators; three
+  // real products per step (Gauss, gbs_engine_common.h).
   const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
-  d4 accr, acci;
-  if constexpr (G) {
-    // three real products per step (see cmul_mat)
-    d4 t3;
-    if (16 * I < d && 16 * J < d) {
-#pragma unroll
-      for (int K = 0; K < T; ++K)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const bool first = K == 0 && r == 0;
-          if (first || 16 * K + 4 * r < d) {
-            const double2 a = opA(K, r);
-            const double2 b = opB(K, r);
-            accr = mfma(a.x, b.x, first ? zero : accr);
-            acci = mfma(a.y, b.y, first ? zero : acci);
-            t3 = mfma(a.x + a.y, b.x + b.y, first ? zero : t3);
-          }
-        }
-    } else {
-      accr = zero;
-      acci = zero;
-      t3 = zero;
-    }
-    __syncthreads();
-    Z.r[0][0] = accr - acci;
-    Z.i[0][0] = t3 - accr - acci;
-    return;
-  }
+  d4 accr, acci, t3;
   if (16 * I < d && 16 * J < d) {
 #pragma unroll
     for (int K = 0; K < T; ++K)
@@ -116,18 +90,18 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
           const double2 a = opA(K, r);
           const double2 b = opB(K, r);
           accr = mfma(a.x, b.x, first ? zero : accr);
-          acci = mfma(a.x, b.y, first ? zero : acci);
-          accr = mfma(-a.y, b.y, accr);
-          acci = mfma(a.y, b.x, acci);
+          acci = mfma(a.y, b.y, first ? zero : acci);
+          t3 = mfma(a.x + a.y, b.x + b.y, first ? zero : t3);
         }
       }
   } else {
     accr = zero;
     acci = zero;
+    t3 = zero;
   }
   __syncthreads();
-  Z.r[0][0] = accr;
-  Z.i[0][0] = acci;
+  Z.r[0][0] = accr - acci;
+  Z.i[0][0] = t3 - accr - acci;
 }
 
 // Traces are reduced over the wave four at a time as the chain forms them (the q-th trace operation
@@ -156,7 +130,7 @@ __device__ __forceinline__ void run_ops_tile(CMat<1> (&S)[NS], double (&tb)[4], 
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
-      tile_mul<T, SYM, (K <= GBS_GAUSS_KMAX)>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
+      tile_mul<T, SYM>(S[op.a], S[op.b], S[op.x], d, lane, w, I, J, xbuf);
     } else {
       double2 p = op.type == OP_TDIAG ? (I == J ? tdiag<1>(S[op.a], lane) : make_double2(0.0, 0.0))
                                       : tpair<1>(S[op.a], S[op.b]);
