@@ -296,6 +296,43 @@ def test_config5_large_hafnians_vs_oracle_goldens(ctx, torch_dev):
         assert err <= b, (g["index"], err, b)
 
 
+def test_config5_slices_vs_oracle_goldens(ctx, torch_dev):
+    """Config-5 patterns of n = 36, 40 and 44 cut into uneven subset slices (slice edges inside every
+    engine band: the 6x6 and 7x7 symmetric quad-tile kernels, the 16x16-tile kernels, the quad grids),
+    evaluated by gbs_prob_slices and combined by gbs_finalize, against the stored oracle values with
+    the same rounding bound as the batched call."""
+    from paper_1908_10070_amd import gbs
+    gold = json.loads((pathlib.Path(__file__).parent / "golden" / "config5_haf.json").read_text())["records"]
+    picked = {}
+    for g in gold:
+        if "kappa" in g and g["n"] not in picked:
+            picked[g["n"]] = g
+    gold = [picked[n] for n in sorted(picked)]
+    if not gold:
+        pytest.skip("no config-5 record with kappa yet")
+    st_in, pats = inputs.config5()
+    st = ctx.state(to_dev(st_in.U, torch_dev), st_in.r)
+    rng = np.random.default_rng(55)
+    sl_pats, lo, hi, part_off = [], [], [], [0]
+    for g in gold:
+        p = pats[g["index"]]
+        cnt = gbs.subset_count(len(p))
+        cuts = sorted(set([0, cnt] + rng.integers(1, cnt, 7).tolist()))
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            sl_pats.append(p)
+            lo.append(a)
+            hi.append(b)
+        part_off.append(part_off[-1] + len(cuts) - 1)
+    parts = ctx.prob_slices(st, sl_pats, lo, hi)
+    _, haf = ctx.finalize(st, parts, part_off[:-1], part_off[1:], [pats[g["index"]] for g in gold])
+    haf = haf.cpu().numpy()
+    for g, h in zip(gold, haf):
+        ld = "haf_pt_ld" in g
+        ref = complex(*(g["haf_pt_ld"] if ld else g["haf_pt"]))
+        b = bounds.bound(g["n"], g["kappa"], g.get("kappa2"), "long double" if ld else "double")
+        assert relerr(h, ref) <= b, (g["index"], g["n"], relerr(h, ref), b)
+
+
 def test_config3_full_size_sampled(ctx, torch_dev):
     """Config 3 as the benchmark runs it (100,000 twenty-photon patterns, m = 50, one batched call):
     40 outputs spread over the batch against the oracle, and properties of all of them."""
