@@ -219,6 +219,30 @@ __host__ __device__ constexpr int chain_trace_at(const ChainProgram& p, int ord)
   return 0;
 }
 
+// Inner products tr(P Q) are sums of P[l] Q[l ^ 17]-style lane pairs, symmetric in the two factors,
+// so a run of consecutive OP_TPAIR operations that all name one slot s exchanges that slot's lanes
+// once for the whole run. pair_run gives the run starting at operation oi (len 0 if it is not an
+// inner product; at most 4; the slot that makes it longest), pair_other the other factor of one.
+struct PairRun {
+  int len, s;
+};
+__host__ __device__ constexpr PairRun pair_run(const ChainProgram& p, int oi) {
+  if (oi >= p.nops || p.ops[oi].type != OP_TPAIR) return {0, 0};
+  PairRun best{1, p.ops[oi].b};
+  for (int c = 0; c < 2; ++c) {
+    const int s = c == 0 ? p.ops[oi].b : p.ops[oi].a;
+    int len = 1;
+    while (len < 4 && oi + len < p.nops && p.ops[oi + len].type == OP_TPAIR &&
+           (p.ops[oi + len].a == s || p.ops[oi + len].b == s))
+      ++len;
+    if (len > best.len) best = {len, s};
+  }
+  return best;
+}
+__host__ __device__ constexpr int pair_other(const ChainProgram& p, int oi, int s) {
+  return oi >= p.nops ? 0 : (p.ops[oi].a == s ? p.ops[oi].b : p.ops[oi].a);
+}
+
 typedef const __attribute__((address_space(3))) double lds_d;  // LDS-qualified, for direct ds_read
 typedef __attribute__((address_space(3))) double lds_dw;       // the same, writable
 

@@ -137,6 +137,40 @@ __device__ __forceinline__ double2 qpair(const QMat<T4>& X, const QMat<T4>& Y) {
   return make_double2(fma(2.0, o.x, d.x), fma(2.0, o.y, d.y));
 }
 
+// One tile's contribution to the partial of tr(X S[s]) with S[s]'s lane-exchanged tile (yr, yi).
+template <int T4, int NS, int X>
+__device__ __forceinline__ void qpair_acc(const QMat<T4> (&S)[NS], int I, int C, double yr, double yi, double2& t) {
+  t.x = fma(S[X].r[I][C], yr, t.x);
+  t.x = fma(-S[X].i[I][C], yi, t.x);
+  t.y = fma(S[X].r[I][C], yi, t.y);
+  t.y = fma(S[X].i[I][C], yr, t.y);
+}
+
+// The per-lane partials of the run of inner products starting at operation OI of program KK
+// (pair_run): the shared slot is exchanged (lane l ^ 17) once per tile for all of them.
+template <int KK, int T4, int OI, int NS>
+__device__ __forceinline__ void qpair_run(const QMat<T4> (&S)[NS], double2 (&out)[4]) {
+  constexpr PairRun run = pair_run(kChainTable[KK], OI);
+  constexpr int s = run.s, x0 = pair_other(kChainTable[KK], OI, s), x1 = pair_other(kChainTable[KK], OI + 1, s),
+                x2 = pair_other(kChainTable[KK], OI + 2, s), x3 = pair_other(kChainTable[KK], OI + 3, s);
+  double2 d[4], o[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) d[r] = o[r] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int I = 0; I < T4; ++I)
+#pragma unroll
+    for (int C = I; C < T4; ++C) {
+      const double yr = swap17(S[s].r[I][C]);
+      const double yi = swap17(S[s].i[I][C]);
+      qpair_acc<T4, NS, x0>(S, I, C, yr, yi, C == I ? d[0] : o[0]);
+      if constexpr (run.len > 1) qpair_acc<T4, NS, x1>(S, I, C, yr, yi, C == I ? d[1] : o[1]);
+      if constexpr (run.len > 2) qpair_acc<T4, NS, x2>(S, I, C, yr, yi, C == I ? d[2] : o[2]);
+      if constexpr (run.len > 3) qpair_acc<T4, NS, x3>(S, I, C, yr, yi, C == I ? d[3] : o[3]);
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = make_double2(fma(2.0, o[r].x, d[r].x), fma(2.0, o[r].y, d[r].y));
+}
+
 // Traces of 3x3 and larger tile grids are parked in LDS (park[(j - 1) * 64 + lane]) until the chain
 // ends instead of holding k registers through every product; smaller grids keep them in registers.
 // (The |Z| <= 6 kernel up to k = kQuad3WavesKMax reduces them four at a time instead: push_trace.)
@@ -149,16 +183,28 @@ __device__ __forceinline__ void run_ops_quad(QMat<T4> (&S)[NS], double (&w)[K], 
                                              const QPerm& pm) {
   if constexpr (OI < kChainTable[K].nops) {
     constexpr Op op = kChainTable[K].ops[OI];
+    auto put = [&](int j, const double2& p) {
+      if constexpr (T4 >= kQuadParkT4)
+        park[(j - 1) * 64 + lane] = fold32(p.x, p.y);
+      else
+        w[j - 1] = fold32(p.x, p.y);
+    };
     if constexpr (op.type == OP_MUL) {
       qmul<T4>(S[op.a], S[op.b], S[op.x], pm);
+      run_ops_quad<K, T4, OI + 1, NS>(S, w, park, lane, pm);
+    } else if constexpr (op.type == OP_TDIAG) {
+      put(op.x, qdiag<T4>(S[op.a], lane));
+      run_ops_quad<K, T4, OI + 1, NS>(S, w, park, lane, pm);
     } else {
-      const double2 p = op.type == OP_TDIAG ? qdiag<T4>(S[op.a], lane) : qpair<T4>(S[op.a], S[op.b]);
-      if constexpr (T4 >= kQuadParkT4)
-        park[(op.x - 1) * 64 + lane] = fold32(p.x, p.y);
-      else
-        w[op.x - 1] = fold32(p.x, p.y);
+      constexpr int len = pair_run(kChainTable[K], OI).len;
+      double2 p[4];
+      qpair_run<K, T4, OI, NS>(S, p);
+      put(op.x, p[0]);
+      if constexpr (len > 1) put(kChainTable[K].ops[OI + 1].x, p[1]);
+      if constexpr (len > 2) put(kChainTable[K].ops[OI + 2].x, p[2]);
+      if constexpr (len > 3) put(kChainTable[K].ops[OI + 3].x, p[3]);
+      run_ops_quad<K, T4, OI + len, NS>(S, w, park, lane, pm);
     }
-    run_ops_quad<K, T4, OI + 1, NS>(S, w, park, lane, pm);
   }
 }
 
@@ -222,11 +268,21 @@ __device__ __forceinline__ void run_ops_quad_b(QMat<T4> (&S)[NS], double (&tb)[4
     constexpr Op op = kChainTable[K].ops[OI];
     if constexpr (op.type == OP_MUL) {
       qmul<T4>(S[op.a], S[op.b], S[op.x], pm);
-    } else {
-      const double2 p = op.type == OP_TDIAG ? qdiag<T4>(S[op.a], lane) : qpair<T4>(S[op.a], S[op.b]);
+      run_ops_quad_b<K, T4, OI + 1, NS>(S, tb, lane, pm, store);
+    } else if constexpr (op.type == OP_TDIAG) {
+      const double2 p = qdiag<T4>(S[op.a], lane);
       push_trace<K, OI>(tb, fold32(p.x, p.y), lane, store);
+      run_ops_quad_b<K, T4, OI + 1, NS>(S, tb, lane, pm, store);
+    } else {
+      constexpr int len = pair_run(kChainTable[K], OI).len;
+      double2 p[4];
+      qpair_run<K, T4, OI, NS>(S, p);
+      push_trace<K, OI>(tb, fold32(p[0].x, p[0].y), lane, store);
+      if constexpr (len > 1) push_trace<K, OI + 1>(tb, fold32(p[1].x, p[1].y), lane, store);
+      if constexpr (len > 2) push_trace<K, OI + 2>(tb, fold32(p[2].x, p[2].y), lane, store);
+      if constexpr (len > 3) push_trace<K, OI + 3>(tb, fold32(p[3].x, p[3].y), lane, store);
+      run_ops_quad_b<K, T4, OI + len, NS>(S, tb, lane, pm, store);
     }
-    run_ops_quad_b<K, T4, OI + 1, NS>(S, tb, lane, pm, store);
   }
 }
 
