@@ -80,17 +80,25 @@ struct SqtMat {
   double i[sqt_q(G)];
 };
 
-// Lane byte addresses of the three permutations (inside each block): lane ^ 17, transpose, flipped transpose.
+// A published tile keeps lane l's element at position sqt_pos(l) of its 64 (16-byte) slots: the lane
+// number with bits 4..5 folded into bits 0..1. The transposed reads (lane (x, y) <- (y, x) and
+// (y^1, x^1)) then hit eight different 16-byte bank groups in every run of eight lanes, as the direct
+// and lane ^ 17 reads do, instead of four lanes sharing one (measured as LDS bank conflicts).
+__host__ __device__ constexpr int sqt_pos(int l) { return l ^ ((l >> 4) & 3); }
+
+// Per-lane slot positions of the own element and of the three permutations read (inside each block):
+// lane ^ 17, transpose, flipped transpose.
 struct SqtLanes {
-  int l17, tr, tf;
+  int self, l17, tr, tf;
 };
 
 __device__ __forceinline__ SqtLanes sqt_lanes(int lane) {
   const int x = lane & 3, b = (lane >> 2) & 3, y = lane >> 4;
   SqtLanes s;
-  s.l17 = lane ^ 17;
-  s.tr = y + 4 * b + 16 * x;
-  s.tf = (y ^ 1) + 4 * b + 16 * (x ^ 1);
+  s.self = sqt_pos(lane);
+  s.l17 = sqt_pos(lane ^ 17);
+  s.tr = sqt_pos(y + 4 * b + 16 * x);
+  s.tf = sqt_pos((y ^ 1) + 4 * b + 16 * (x ^ 1));
   return s;
 }
 
@@ -105,8 +113,8 @@ __device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, 
   for (int q = 0; q < P.nq; ++q)
     if (P.J[q] < T4) {
       const int t = sqt_idx(G, P.I[q], P.J[q]);
-      lds_st2(xq, t * 64 + lane, make_double2(X.r[q], X.i[q]));
-      if (!SAME) lds_st2(yq, t * 64 + lane, make_double2(Y.r[q], Y.i[q]));
+      lds_st2(xq, t * 64 + ln.self, make_double2(X.r[q], X.i[q]));
+      if (!SAME) lds_st2(yq, t * 64 + ln.self, make_double2(Y.r[q], Y.i[q]));
     }
   __syncthreads();
   double t1[Q], t2[Q], t3[Q];
@@ -118,7 +126,7 @@ __device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, 
 #pragma unroll
       for (int c = 0; c < P.nc; ++c) {
         const int J = P.cols[c];
-        b[c] = K <= J ? lds_ld2(yq, sqt_idx(G, K, J) * 64 + lane) : lds_ld2(yq, sqt_idx(G, J, K) * 64 + ln.tf);
+        b[c] = K <= J ? lds_ld2(yq, sqt_idx(G, K, J) * 64 + ln.self) : lds_ld2(yq, sqt_idx(G, J, K) * 64 + ln.tf);
         bs[c] = b[c].x + b[c].y;
       }
       // one A operand (a row of the wave's tiles) at a time

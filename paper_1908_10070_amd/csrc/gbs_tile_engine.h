@@ -43,18 +43,28 @@ __device__ __forceinline__ void tile_of_wave(int w, int& I, int& J) {
     J = I + w;
   }
 }
-// LDS element index (in double2 units, inside the stored tile) of the A operand of step r for tile
-// (I, K), K > I, read from the stored tile (I, K): the operand wants element (x, y + 4r) of X(I, K)
-// at lane x + 16y, i.e. register x >> 2 at lane (y + 4r) + 16 (x & 3).
+// A published tile is four register planes of kTilePlane 16-byte slots; lane l's register r sits at
+// r * kTilePlane + tile_pos(l), tile_pos folding lane bits 4..5 into bits 0..1. Both choices serve the
+// transposed operand reads below, whose 16 lanes of a row would otherwise all hit one 16-byte bank
+// group (lane bits 0..1 select the source row of 16, bits 2..3 the plane): the fold spreads the rows,
+// the 4-slot pad per plane spreads the planes. Every offset stays a sum of a per-lane base and a
+// constant, so the reads keep immediate offsets.
+constexpr int kTilePlane = 68, kTileSlots = 4 * kTilePlane;
+__device__ __forceinline__ int tile_pos(int l) { return l ^ ((l >> 4) & 3); }
+
+// LDS slot (in double2 units, inside the stored tile) of the A operand of step r for tile (I, K),
+// K > I, read from the stored tile (I, K): the operand wants element (x, y + 4r) of X(I, K) at lane
+// x + 16y, i.e. register x >> 2 at lane (y + 4r) + 16 (x & 3). The fold there leaves bits 2..3 (4r)
+// alone, so the slot is that of step 0 plus 4r (written so, for the immediate offset).
 __device__ __forceinline__ int tile_a_addr(int lane, int r) {
   const int x = lane & 15, y = lane >> 4;
-  return (x >> 2) * 64 + (y + 4 * r) + 16 * (x & 3);
+  return (x >> 2) * kTilePlane + tile_pos(y + 16 * (x & 3)) + 4 * r;
 }
 // The B operand of step r for tile (K, J), K > J, from the stored tile (J, K): element (y + 4r, x) of
 // Y(K, J) is element (x^1, (y + 4r)^1) of Y(J, K): register (x^1) >> 2 at lane ((y^1) + 4r) + 16 ((x^1) & 3).
 __device__ __forceinline__ int tile_b_addr(int lane, int r) {
   const int x = lane & 15, y = lane >> 4;
-  return ((x ^ 1) >> 2) * 64 + ((y ^ 1) + 4 * r) + 16 * ((x ^ 1) & 3);
+  return ((x ^ 1) >> 2) * kTilePlane + tile_pos((y ^ 1) + 16 * ((x ^ 1) & 3)) + 4 * r;
 }
 
 template <int T, bool SYM>
@@ -63,18 +73,19 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
   constexpr int NT = tile_waves(T, SYM);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    xbuf[((0 * NT + w) * 4 + r) * 64 + lane] = make_double2(X.r[0][0][r], X.i[0][0][r]);
-    xbuf[((1 * NT + w) * 4 + r) * 64 + lane] = make_double2(Y.r[0][0][r], Y.i[0][0][r]);
+    xbuf[(0 * NT + w) * kTileSlots + r * kTilePlane + tile_pos(lane)] = make_double2(X.r[0][0][r], X.i[0][0][r]);
+    xbuf[(1 * NT + w) * kTileSlots + r * kTilePlane + tile_pos(lane)] = make_double2(Y.r[0][0][r], Y.i[0][0][r]);
   }
   __syncthreads();
   // operand r of k-tile K: A from X(I, K), B from Y(K, J)
   auto opA = [&](int K, int r) -> double2 {
-    if (!SYM || K <= I) return xbuf[((0 * NT + tile_slot<T, SYM>(K, I)) * 4 + r) * 64 + (lane ^ 17)];
-    return xbuf[(0 * NT + tile_slot<T, SYM>(I, K)) * 4 * 64 + tile_a_addr(lane, r)];
+    if (!SYM || K <= I)
+      return xbuf[(0 * NT + tile_slot<T, SYM>(K, I)) * kTileSlots + r * kTilePlane + tile_pos(lane ^ 17)];
+    return xbuf[(0 * NT + tile_slot<T, SYM>(I, K)) * kTileSlots + tile_a_addr(lane, r)];
   };
   auto opB = [&](int K, int r) -> double2 {
-    if (!SYM || K <= J) return xbuf[((1 * NT + tile_slot<T, SYM>(K, J)) * 4 + r) * 64 + lane];
-    return xbuf[(1 * NT + tile_slot<T, SYM>(J, K)) * 4 * 64 + tile_b_addr(lane, r)];
+    if (!SYM || K <= J) return xbuf[(1 * NT + tile_slot<T, SYM>(K, J)) * kTileSlots + r * kTilePlane + tile_pos(lane)];
+    return xbuf[(1 * NT + tile_slot<T, SYM>(J, K)) * kTileSlots + tile_b_addr(lane, r)];
   };
   // The first step (K = 0, r = 0) always runs for a tile inside d and starts the accumulators; three
   // real products per step (Gauss, gbs_engine_common.h).
@@ -218,7 +229,7 @@ __host__ __device__ inline TileLds tile_lds_layout(int T, bool sym, int nmax, in
   L.pl = off;
   off += wal16(sizeof(int32_t) * kMaxK);
   L.xbuf = off;
-  off += wal16(sizeof(double) * 2 * 2 * NT * 4 * 64);
+  off += wal16(sizeof(double) * 2 * 2 * NT * kTileSlots);
   L.tred = off;
   off += wal16(sizeof(double) * NT * 2 * kmax);
   L.trw = off;
