@@ -27,6 +27,9 @@
  *   - Device inputs must stay alive and unmodified until the stream reaches the work.
  *   - A context is not thread-safe: use one per host thread (and per stream if work on
  *     several streams must overlap). Calls on one context serialise on its internal staging.
+ *     A context keeps the host storage of its largest work plan (about 50 bytes per work item
+ *     and 40 per pattern: 32 MB for 100,000 twenty-photon patterns) so that later calls plan
+ *     without reallocating; gbs_ctx_destroy releases it.
  *   - n (photon number, matrix size) must satisfy 0 <= n <= GBS_N_MAX. n = 0 gives Haf = 1;
  *     odd n gives Haf = 0 and p = 0 (P_n = 0 for odd n, Eq. Eqdistribution).
  *   - Input matrices are assumed complex symmetric; diagonal entries are never used
@@ -103,11 +106,15 @@ int gbs_ctx_set_exec(gbs_ctx* ctx, int use_graph, int persistent);
  * internal streams, forked from the call's stream after its staging copy and joined back before the
  * final combine, so that the kernels of a mixed batch (a serving step: many sizes, each a few
  * patterns) run side by side instead of one after another. With use_graph the fork and join are
- * captured as graph edges. 1 = every kernel on the call's stream; the default is 2 (a one-size batch's
- * few kernels then overlap their tails; a serving step's many small kernels want about 4). Results are
- * the same bit for bit. GBS_EINVAL outside [1, 8]; GBS_EHIP if a stream or event cannot be created. */
+ * captured as graph edges. 1 = every kernel on the call's stream. Until this is called the context
+ * holds 2 and a call whose patterns all have one size n takes the built-in count for that n (two,
+ * so that a one-size batch's few kernels overlap their tails; one at n = 18 and 20, where two measured
+ * slower); a call that mixes sizes takes 2. Once called, every call takes nstreams (a serving step's
+ * many small kernels want about 4). Results are the same bit for bit. GBS_EINVAL outside [1, 8];
+ * GBS_EHIP if a stream or event cannot be created. */
 int gbs_ctx_set_streams(gbs_ctx* ctx, int32_t nstreams);
-/* The context's stream count (*nstreams). GBS_EINVAL for a null argument. */
+/* The context's stream count (*nstreams; 2 until gbs_ctx_set_streams). GBS_EINVAL for a null
+ * argument. */
 int gbs_ctx_get_streams(const gbs_ctx* ctx, int32_t* nstreams);
 
 /* Debugging hooks (process-wide, any thread).

@@ -192,8 +192,8 @@ TABLE_BATCH = {16: 16384, 18: 16384, 20: 16384, 22: 8192, 24: 4096, 26: 2048, 28
 
 def tune_table(ns=None, seed: int = 7700, log=None) -> Dict[int, dict]:
     """Tune every n of ``ns`` (default n = 16..46) on random complex-symmetric matrices (seed + n)
-    in a fresh context each; returns {n: {chunk_small, chunk_large, shape, best_ms}} -- the library's
-    built-in table (kDefaultShape in the runtime) is this output."""
+    in a fresh context each; returns {n: {chunk_small, chunk_large, shape, streams, best_ms}} -- the
+    library's built-in table (kDefaultShape in the runtime) is this output."""
     import numpy as np
     import torch
     from paper_1908_10070_amd import gbs, inputs
@@ -203,11 +203,18 @@ def tune_table(ns=None, seed: int = 7700, log=None) -> Dict[int, dict]:
         A = torch.from_numpy(inputs.random_symmetric(n, TABLE_BATCH[n], np.random.default_rng(seed + n))).cuda()
         lg = []
         cs, cl = tune(ctx, n, A, reps=3 if n <= 40 else 1, cache=None, log=lg)
+        # then the stream count: two (the context default) unless one is faster by more than TIE
+        res = torch.empty(A.shape[0], dtype=torch.complex128, device=A.device)
+        ts = {}
+        for s in (2, 1):
+            ctx.set_streams(s)
+            ts[s] = _time_call(lambda: ctx.haf_batch(A, out=res), 3 if n <= 40 else 1)
         out[n] = {"batch": TABLE_BATCH[n], "chunk_small": cs, "chunk_large": cl, "shape": ctx.get_shape(n),
-                  "best_ms": min(r["ms"] for r in lg)}
+                  "streams": faster_than(2, ts), "best_ms": min(r["ms"] for r in lg)}
         if log is not None:
             log.extend(lg)
-        print(f"n={n}: chunks {cs}/{cl} shape {out[n]['shape']} ({out[n]['best_ms']:.3f} ms)", flush=True)
+        print(f"n={n}: chunks {cs}/{cl} shape {out[n]['shape']} streams {out[n]['streams']} "
+              f"({out[n]['best_ms']:.3f} ms)", flush=True)
         ctx.close()
     return out
 

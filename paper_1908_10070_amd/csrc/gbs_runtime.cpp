@@ -48,6 +48,57 @@ double flops_subset(const ChainProgram& p, int k, int s) {
   return p.nmul * 8.0 * d * d * d + p.npair * 8.0 * d * d + 8.0 * k * (k + 1) / 2.0;
 }
 
+struct Plan {
+  std::vector<PatternDesc> pats;
+  std::vector<WorkItem> items;  // grouped by engine kernel
+  struct Group {
+    int cls;                     // engine kernel variant (one k per variant)
+    int n;                       // photon number of every pattern in the group
+    int64_t first, count;
+  };
+  std::vector<Group> groups;
+  std::vector<int64_t> part_off;  // batch + 1 (finalize groups)
+  std::vector<int32_t> nvec;
+  std::vector<double> sfact;
+  std::vector<int64_t> out_idx;  // optional destination index per finalize group
+  int64_t n_partials = 0;
+  int nmax = 0, kmax = 0;
+  int nmin = GBS_N_MAX + 1;  // smallest n that has items
+};
+
+// The runs of subset sizes of a size-n pattern that share an engine variant (engine_class), in
+// increasing |Z|, each with its range [a, b) of the canonical order clipped to [lo, hi) and its chunk:
+// chunk_small subsets per item for |Z| <= 8, chunk_large above.
+struct ClassRun {
+  int cls;
+  int64_t a, b, chunk;
+};
+
+constexpr int64_t kDdChunk = 32;
+
+struct ItemLists {
+  std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
+  std::vector<ClassRun> full_runs[GBS_N_MAX + 1];  // class runs of a whole size-n pattern
+  bool have_full[GBS_N_MAX + 1] = {};
+};
+
+// Empty a plan and its item lists for the next call, keeping their storage: a batch of the same
+// shape then plans without reallocating or touching fresh pages (config 3: 600,000 items).
+void plan_reset(Plan& pl, ItemLists& L) {
+  pl.pats.clear();
+  pl.items.clear();
+  pl.groups.clear();
+  pl.part_off.clear();
+  pl.nvec.clear();
+  pl.sfact.clear();
+  pl.out_idx.clear();
+  pl.n_partials = 0;
+  pl.nmax = pl.kmax = 0;
+  pl.nmin = GBS_N_MAX + 1;
+  for (std::vector<WorkItem>& v : L.cls) v.clear();
+  for (bool& h : L.have_full) h = false;  // the launch shape may have changed since
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ objects
@@ -78,13 +129,14 @@ struct gbs_ctx {
   hipStream_t cap_stream = nullptr;
   int use_graph = 1;
   int persistent = 1;
-  // eager launches only: spread a call's engine kernels over this many streams (forked from and
-  // joined back into the caller's stream), so small per-variant kernels overlap
+  // spread a call's engine kernels over this many streams (forked from and joined back into the
+  // caller's stream; in a captured graph the fork and join are edges), so per-variant kernels overlap
   static constexpr int kMaxStreams = 8;
   // default: two (measured no slower than one on every one-size workload and 1.1% faster on the
   // n = 24 batch, whose four kernels then overlap their tails; three were 11% slower there)
   static constexpr int kDefaultStreams = 2;
   int nstreams = 1;
+  bool streams_auto = true;  // no gbs_ctx_set_streams yet: one-size calls take the table's count
   hipStream_t aux[kMaxStreams] = {};
   hipEvent_t aux_ev[kMaxStreams] = {};
   hipEvent_t fork_ev = nullptr;
@@ -93,6 +145,9 @@ struct gbs_ctx {
   std::map<int, int> shape;  // engine shape bits per n (kShape*)
   std::string last_error;
   std::list<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
+  // the work plan of the call in progress, kept between calls for its storage (plan_reset)
+  Plan plan;
+  ItemLists lists;
 };
 
 // Views into caller-owned state memory (layout: state_layout).
@@ -180,17 +235,20 @@ struct DeviceGuard {
 };
 
 // Built-in launch shape per even n: the autotuner's picks (autotune.tune over chunk sizes and engine
-// shapes, haf_batch on random complex-symmetric matrices, one MI355X; python -m
-// paper_1908_10070_amd.autotune --table reproduces it). Rows below n = 16 repeat n = 16's (a
-// pattern's subsets fit one item either way). {chunk_small, chunk_large, shape}
+// shapes, then one or two streams, haf_batch on random complex-symmetric matrices, one MI355X;
+// python -m paper_1908_10070_amd.autotune --table reproduces it). Rows below n = 16 repeat n = 16's
+// (a pattern's subsets fit one item either way). {chunk_small, chunk_large, shape, streams}; the
+// streams column applies to calls whose patterns all have that n while the caller has not chosen a
+// stream count (one stream at n = 18, 20, where two measured 5% and 1-3% slower).
 struct ShapeRow {
-  int32_t cs, cl, shape;
+  int32_t cs, cl, shape, streams;
 };
 constexpr ShapeRow kDefaultShape[GBS_N_MAX / 2 + 1] = {
-    {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0},
-    {2048, 128, 0}, {2048, 128, 0}, {2048, 128, 0}, {256, 16, 1}, {256, 64, 0}, {512, 128, 2}, {256, 256, 4},
-    {512, 32, 4}, {512, 128, 4}, {256, 256, 4}, {256, 128, 20}, {256, 128, 20}, {256, 128, 20}, {256, 128, 20},
-    {256, 128, 20}, {128, 128, 20}, {1024, 128, 20}, {128, 128, 20},
+    {2048, 128, 0, 2}, {2048, 128, 0, 2},  {2048, 128, 0, 2},  {2048, 128, 0, 2},  {2048, 128, 0, 2},
+    {2048, 128, 0, 2}, {2048, 128, 0, 2},  {2048, 128, 0, 2},  {2048, 128, 0, 2},  {256, 16, 1, 1},
+    {256, 64, 0, 1},   {512, 128, 2, 2},   {256, 256, 4, 2},   {512, 32, 4, 2},    {512, 128, 4, 2},
+    {256, 256, 4, 2},  {256, 128, 20, 2},  {256, 128, 20, 2},  {256, 128, 20, 2},  {256, 128, 20, 2},
+    {256, 128, 20, 2}, {128, 128, 20, 2},  {1024, 128, 20, 2}, {128, 128, 20, 2},
 };
 
 void default_chunks(int n, int64_t* cs, int64_t* cl) {
@@ -210,6 +268,7 @@ void chunks_for(const gbs_ctx* ctx, int n, int64_t* cs, int64_t* cl) {
 
 // Engine shape bits for size-n patterns: the caller's (autotuner's) choice, else the built-in table.
 int default_shape(int n) { return kDefaultShape[(n < 0 ? 0 : (n > GBS_N_MAX ? GBS_N_MAX : n)) / 2].shape; }
+int default_streams(int n) { return kDefaultShape[(n < 0 ? 0 : (n > GBS_N_MAX ? GBS_N_MAX : n)) / 2].streams; }
 
 int shape_for(const gbs_ctx* ctx, int n) {
   auto it = ctx->shape.find(n);
@@ -217,38 +276,6 @@ int shape_for(const gbs_ctx* ctx, int n) {
 }
 
 // Host-side plan of one call, laid out exactly as it is copied into the device workspace.
-struct Plan {
-  std::vector<PatternDesc> pats;
-  std::vector<WorkItem> items;  // grouped by engine kernel
-  struct Group {
-    int cls;                     // engine kernel variant (one k per variant)
-    int n;                       // photon number of every pattern in the group
-    int64_t first, count;
-  };
-  std::vector<Group> groups;
-  std::vector<int64_t> part_off;  // batch + 1 (finalize groups)
-  std::vector<int32_t> nvec;
-  std::vector<double> sfact;
-  std::vector<int64_t> out_idx;  // optional destination index per finalize group
-  int64_t n_partials = 0;
-  int nmax = 0, kmax = 0;
-};
-
-// The runs of subset sizes of a size-n pattern that share an engine variant (engine_class), in
-// increasing |Z|, each with its range [a, b) of the canonical order clipped to [lo, hi) and its chunk:
-// chunk_small subsets per item for |Z| <= 8, chunk_large above.
-struct ClassRun {
-  int cls;
-  int64_t a, b, chunk;
-};
-
-constexpr int64_t kDdChunk = 32;
-
-struct ItemLists {
-  std::vector<WorkItem> cls[kEngineClasses];  // by engine kernel variant
-  std::vector<ClassRun> full_runs[GBS_N_MAX + 1];  // class runs of a whole size-n pattern
-  bool have_full[GBS_N_MAX + 1] = {};
-};
 
 std::vector<ClassRun> class_runs(const gbs_ctx* ctx, int n, int64_t lo, int64_t hi) {
   std::vector<ClassRun> out;
@@ -299,6 +326,7 @@ void plan_range(const gbs_ctx* ctx, Plan& pl, ItemLists& L, int p, int n, int64_
     }
   }
   pl.nmax = std::max(pl.nmax, n);
+  pl.nmin = std::min(pl.nmin, n);
   pl.kmax = std::max(pl.kmax, n / 2);
 }
 
@@ -310,17 +338,25 @@ void order_items(Plan& pl, ItemLists& L) {
   for (int cls = kEngineClasses - 1; cls >= 0; --cls) {
     const std::vector<WorkItem>& v = L.cls[cls];
     if (v.empty()) continue;
-    // stable order by decreasing n: a counting pass over the (at most GBS_N_MAX + 1) sizes
+    // stable order by decreasing n: a counting pass over the (at most GBS_N_MAX + 1) sizes; a list of
+    // one size is already in that order and is copied as it is
     int64_t count[GBS_N_MAX + 2] = {};
-    for (const WorkItem& w : v) ++count[GBS_N_MAX - pl.pats[w.pattern].n + 1];
-    for (int q = 1; q <= GBS_N_MAX + 1; ++q) count[q] += count[q - 1];
+    bool one_size = pl.nmin == pl.nmax;
+    if (!one_size) {
+      for (const WorkItem& w : v) ++count[GBS_N_MAX - pl.pats[w.pattern].n + 1];
+      one_size = count[GBS_N_MAX - pl.pats[v[0].pattern].n + 1] == (int64_t)v.size();
+      for (int q = 1; q <= GBS_N_MAX + 1; ++q) count[q] += count[q - 1];
+    }
     Plan::Group g;
     g.cls = cls;
     g.first = (int64_t)pl.items.size();
     g.count = (int64_t)v.size();
     pl.items.resize(pl.items.size() + v.size());
     WorkItem* dst = pl.items.data() + g.first;
-    for (const WorkItem& w : v) dst[count[GBS_N_MAX - pl.pats[w.pattern].n]++] = w;
+    if (one_size)
+      std::copy(v.begin(), v.end(), dst);
+    else
+      for (const WorkItem& w : v) dst[count[GBS_N_MAX - pl.pats[w.pattern].n]++] = w;
     g.n = pl.pats[dst[0].pattern].n;
     pl.groups.push_back(g);
   }
@@ -498,7 +534,11 @@ int run_plan(gbs_ctx* ctx, const Plan& pl, const int32_t* modes_host, size_t n_m
   // With several streams the engine kernels go round-robin to the auxiliary streams, forked from s
   // after the staging copy and the counter reset and joined back before the finalize kernel. Under
   // graph capture the fork and join become graph edges, so a replay runs the kernels side by side.
-  const int ns = ctx->nstreams > 1 ? (int)std::min<size_t>((size_t)ctx->nstreams, launches.size()) : 1;
+  // (a call on patterns of one size n, on a context whose stream count the caller has not set, takes
+  // the built-in count for n; default_streams never exceeds the kDefaultStreams created with it)
+  const int want = ctx->streams_auto && pl.nmin == pl.nmax ? std::min(default_streams(pl.nmin), ctx->nstreams)
+                                                           : ctx->nstreams;
+  const int ns = want > 1 ? (int)std::min<size_t>((size_t)want, launches.size()) : 1;
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     if (ctx->persistent && !launches.empty()) launch_reset(counters, (int)launches.size(), s);
     if (ns > 1) {
@@ -680,6 +720,7 @@ int gbs_ctx_create(int device, void* workspace_dev, size_t workspace_bytes, gbs_
     gbs_ctx_destroy(c);
     return GBS_EHIP;
   }
+  c->streams_auto = true;  // the default, not a caller's choice
   c->ws = workspace_dev;
   c->ws_bytes = workspace_dev ? workspace_bytes : 0;
   *out = c;
@@ -764,6 +805,7 @@ int gbs_ctx_set_streams(gbs_ctx* ctx, int32_t nstreams) {
     if (!ctx->aux_ev[i]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming));
   }
   ctx->nstreams = nstreams;
+  ctx->streams_auto = false;
   return GBS_OK;
 }
 
@@ -829,12 +871,13 @@ int haf_batch_varlen(gbs_ctx* ctx, const gbs_c128* A_dev, const int64_t* elem_of
   for (int64_t b = 0; b < batch && !any_data; ++b) any_data = n_host[b] > 0;
   if (any_data && !A_dev) return fail(ctx, GBS_EINVAL, "null matrix pointer");
   if (batch > (int64_t)1 << 30) return fail(ctx, GBS_ERANGE, "batch too large");
-  Plan pl;
+  Plan& pl = ctx->plan;
+  ItemLists& lists = ctx->lists;
+  plan_reset(pl, lists);
   pl.pats.resize(batch);
   pl.part_off.resize(batch + 1);
   pl.nvec.resize(batch);
   pl.sfact.assign(batch, 1.0);
-  ItemLists lists;
   pl.part_off[0] = 0;
   for (int64_t b = 0; b < batch; ++b) {
     const int n = n_host[b];
@@ -1096,13 +1139,14 @@ int prob_common(gbs_ctx* ctx, const gbs_state* st, const int32_t* modes_host, co
   if (offsets_host[0] != 0) return fail(ctx, GBS_EINVAL, "offsets[0] must be 0");
   const int64_t total = offsets_host[batch];
   if (total > 0 && !modes_host) return fail(ctx, GBS_EINVAL, "null modes");
-  Plan pl;
+  Plan& pl = ctx->plan;
+  ItemLists& lists = ctx->lists;
+  plan_reset(pl, lists);
   pl.pats.resize(batch);
   pl.part_off.resize(batch + 1);
   pl.nvec.resize(batch);
   pl.sfact.resize(batch);
   pl.part_off[0] = 0;
-  ItemLists lists;
   for (int64_t b = 0; b < batch; ++b) {
     const int64_t len = offsets_host[b + 1] - offsets_host[b];
     if (len < 0) return fail(ctx, GBS_EINVAL, "offsets must be non-decreasing");

@@ -172,6 +172,15 @@ def test_multi_stream_launches_are_bitwise_equal(ctx, torch_dev):
             assert np.array_equal(c2.prob_batch(st, pats).cpu().numpy(), ref), (ns, graph)
     with pytest.raises(gbs.GBSError):
         c2.set_streams(9)
+    # a one-size batch on a context left at its default takes the built-in count for its n (one
+    # stream at n = 20, two at n = 24): the same bits as either explicit count
+    for n in (20, 24):
+        pn = [sorted(rng.choice(m, n, replace=False).tolist()) for _ in range(24)]
+        ref_n = gbs.Context(0).prob_batch(st, pn).cpu().numpy()
+        for ns in (1, 2):
+            c3 = gbs.Context(0)
+            c3.set_streams(ns)
+            assert np.array_equal(c3.prob_batch(st, pn).cpu().numpy(), ref_n), (n, ns)
 
 
 def test_graph_replays(ctx, torch_dev):
