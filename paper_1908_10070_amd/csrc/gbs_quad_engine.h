@@ -20,10 +20,11 @@ namespace {
 
 // occupancy: up to k = kQuad3WavesKMax the |Z| <= 6 kernels run three waves per SIMD (168 registers,
 // about 100 bytes of spills per lane) with their traces reduced four at a time instead of parked in
-// LDS, which is what lets three workgroups fit a CU (n = 24: 18.5 -> 18.0 ms; config 3: 73.4 -> 67.9
-// ms; at k = 14, 16 it measured within 1%); above, two waves up to k = 20 and one beyond (where two
-// would spill). Up to kQuadWaves2KMax the 4x4-grid kernels run two waves per SIMD (one above;
-// three spilled 132 registers and ran 35% slower).
+// LDS, which is what lets three workgroups fit a CU (4096 hafnians of n = 24: 18.5 -> 18.0 ms;
+// probabilities of 100,000 twenty-photon patterns: 73.4 -> 67.9 ms; at k = 14, 16 it measured within
+// 1%; a fourth wave up to k = 10 spilled 244 bytes per lane and ran 24% slower); above, two waves up
+// to k = 20 and one beyond (where two would spill). Up to kQuadWaves2KMax the 4x4-grid kernels run two
+// waves per SIMD (one above; three spilled 132 registers and ran 35% slower).
 constexpr int kQuad3WavesKMax = 12;
 constexpr int kQuadWaves2KMax = 12;
 

@@ -83,7 +83,8 @@ struct ItemLists {
 };
 
 // Empty a plan and its item lists for the next call, keeping their storage: a batch of the same
-// shape then plans without reallocating or touching fresh pages (config 3: 600,000 items).
+// shape then plans without reallocating or touching fresh pages (100,000 twenty-photon patterns are
+// 600,000 items).
 void plan_reset(Plan& pl, ItemLists& L) {
   pl.pats.clear();
   pl.items.clear();
