@@ -197,6 +197,40 @@ def test_graph_replays(ctx, torch_dev):
         assert torch.equal(out, ref)
 
 
+def test_reused_plan_storage_across_call_shapes(torch_dev):
+    """A context keeps its plan storage between calls: a large one-size batch, then a small mixed one,
+    sliced subset ranges, a one-size batch of another n and the large batch again on one context give
+    the bits that each call gives on a fresh context."""
+    from paper_1908_10070_amd import gbs
+    rng = np.random.default_rng(31)
+    m = 40
+    U = inputs.haar_unitary(m, rng)
+    big = [sorted(rng.choice(m, 20, replace=False).tolist()) for _ in range(3000)]
+    mixed = [sorted(rng.choice(m, int(n), replace=False).tolist()) for n in rng.choice(range(0, 29, 2), 50)]
+    other = [sorted(rng.choice(m, 24, replace=False).tolist()) for _ in range(40)]
+    c = gbs.Context(0)
+    st = c.state(to_dev(U, torch_dev), np.full(m, 0.88))
+
+    def fresh(pats):
+        return gbs.Context(0).prob_batch(st, pats).cpu().numpy()
+
+    expect = {name: fresh(p) for name, p in (("big", big), ("mixed", mixed), ("other", other))}
+    assert np.array_equal(c.prob_batch(st, big).cpu().numpy(), expect["big"])
+    assert np.array_equal(c.prob_batch(st, mixed).cpu().numpy(), expect["mixed"])
+    # each n = 24 pattern's subset range in two uneven slices, combined by finalize (the same value to
+    # rounding: the slices' partials are summed in another order than one item list's)
+    total = gbs.subset_count(24)
+    sl_pats = [p for p in other for _ in range(2)]
+    lo = [v for _ in other for v in (0, total // 3)]
+    hi = [v for _ in other for v in (total // 3, total)]
+    parts = c.prob_slices(st, sl_pats, lo, hi)
+    offs = list(range(0, 2 * len(other) + 1, 2))
+    p_sl, _ = c.finalize(st, parts, offs[:-1], offs[1:], other)
+    assert np.max(relerr(p_sl.cpu().numpy(), expect["other"])) < TOL
+    assert np.array_equal(c.prob_batch(st, other).cpu().numpy(), expect["other"])
+    assert np.array_equal(c.prob_batch(st, big).cpu().numpy(), expect["big"])
+
+
 def test_slices_and_finalize(ctx, torch_dev):
     from paper_1908_10070_amd import gbs
     rng = np.random.default_rng(23)
