@@ -109,6 +109,10 @@ __device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, 
   constexpr SqtPlan<G> P = SqtPlanOf<G, W>::p;
   constexpr int Q = sqt_q(G);
   double2* yq = SAME ? xq : xq + sqt_stored(G) * 64;
+  // every wave done reading the previous product's factors before they are overwritten; waiting here
+  // rather than at the end of that product lets a wave that finished its tiles early form its traces
+  // while the others still multiply
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < P.nq; ++q)
     if (P.J[q] < T4) {
@@ -147,7 +151,6 @@ __device__ __forceinline__ void sqt_mul(const SqtMat<G>& X, const SqtMat<G>& Y, 
       }
     }
   }
-  __syncthreads();  // every wave done reading before the next publish
 #pragma unroll
   for (int q = 0; q < P.nq; ++q) {
     const bool act = P.J[q] < T4;

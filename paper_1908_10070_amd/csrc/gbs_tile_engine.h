@@ -71,6 +71,10 @@ template <int T, bool SYM>
 __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMat<1>& Z, int d, int lane, int w,
                                          int I, int J, double2* xbuf) {
   constexpr int NT = tile_waves(T, SYM);
+  // every wave done reading the previous product's factors before they are overwritten; waiting here
+  // rather than at the end of that product lets the waves whose tiles lie outside d, or finish early,
+  // form their traces while the others still multiply
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     xbuf[(0 * NT + w) * kTileSlots + r * kTilePlane + tile_pos(lane)] = make_double2(X.r[0][0][r], X.i[0][0][r]);
@@ -110,7 +114,6 @@ __device__ __forceinline__ void tile_mul(const CMat<1>& X, const CMat<1>& Y, CMa
     acci = zero;
     t3 = zero;
   }
-  __syncthreads();
   Z.r[0][0] = accr - acci;
   Z.i[0][0] = t3 - accr - acci;
 }
